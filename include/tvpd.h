@@ -1,0 +1,166 @@
+/*
+ * tvpd.h -- C ABI of the MI355X (gfx950) primal-dual image-sweep library.
+ *
+ * Problem.  The paper's regularised inverse problem (Section 6, eq. opt:
+ * data misfit plus lam times a regulariser) with the identity as forward
+ * operator and the isotropic total variation as regulariser:
+ *
+ *     minimise_f  E(f) = 1/2 ||f - g||^2 + lam * sum_i |(grad f)_i|_2
+ *
+ * over images f (2D) or volumes (3D).  grad is the forward difference with
+ * Neumann boundary (zero difference at the last index of every axis), and
+ * div = -grad^T, the adjoint relation the paper states for its operator pair
+ * (Section 1, eq. adjoint).  The solver is the first-order primal-dual
+ * iteration (Chambolle & Pock 2011, Algorithm 1) with extrapolation theta:
+ *
+ *     fbar    = f^k + theta (f^k - f^{k-1})
+ *     p^{k+1} = projection of p^k + sigma grad fbar onto {|p_i|_2 <= lam}
+ *     f^{k+1} = (f^k + tau div p^{k+1} + tau g) / (1 + tau)
+ *
+ * from f^0 = f^{-1} = g, p^0 = 0.  Convergence needs tau sigma ||grad||^2 < 1;
+ * ||grad||^2 < 8 in 2D and < 12 in 3D, so tau = sigma = 1/sqrt(8) (2D) and
+ * 1/sqrt(12) (3D) are always admissible.  The duality gap of a pair (f, p) is
+ *     gap = sum_i 1/2 (f_i - g_i - (div p)_i)^2 + lam |(grad f)_i| - <(grad f)_i, p_i>
+ * (= P(f) - D(p) with P = E and D(p) = -1/2 ||div p||^2 - <g, div p>).
+ *
+ * Conventions.
+ *   - Arrays are float32, dense and row-major: [ny][nx] (2D), [nz][ny][nx]
+ *     (3D), batches lead: [batch][...].  x is the fastest axis.
+ *   - A dual field is planar: [ndim][...], component 0 along x, 1 along y,
+ *     2 along z.
+ *   - "device" pointers point to memory of the current HIP device; "host"
+ *     pointers to ordinary host memory.  The caller owns every buffer,
+ *     including the workspace, whose size the *_workspace_size calls give;
+ *     the library never allocates device memory.  A workspace must be
+ *     256-byte aligned.  It holds the solver state between calls (f ring,
+ *     dual ring, a padded copy of g, reduction partials and a small header).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work on it and return at once, except where a function
+ *     says it synchronises the stream (those that return host results).
+ *   - Every function returns a status: TVPD_OK (0) or a negative error code;
+ *     tvpd_status_string() names it.  Arguments are validated before any
+ *     device work is enqueued, so an error leaves the workspace untouched.
+ *     Non-convergence is not an error: it is reported in tvpd_result.
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef TVPD_H
+#define TVPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TVPD_OK = 0,
+  TVPD_ERR_INVALID_ARG = -1, /* null pointer, bad count or parameter */
+  TVPD_ERR_SHAPE = -2,       /* ndim not 2 or 3, or a non-positive size */
+  TVPD_ERR_ALIGNMENT = -3,   /* workspace not 256-byte aligned */
+  TVPD_ERR_WORKSPACE = -4,   /* workspace smaller than required */
+  TVPD_ERR_HIP = -5,         /* a HIP runtime call failed */
+  TVPD_ERR_UNSUPPORTED = -6, /* valid request this build does not handle */
+  TVPD_ERR_STEP = -7,        /* tau * sigma * ||grad||^2 >= 1 (or <= 0) */
+  TVPD_ERR_DEVICE = -8       /* a device-side check failed (see string) */
+};
+
+/* Image or volume shape.  ndim = 2: nz must be 1.  Sizes >= 1. */
+typedef struct tvpd_shape {
+  int32_t ndim;
+  int32_t nz, ny, nx;
+} tvpd_shape;
+
+/* Coefficients of one iteration: weight lam >= 0 on the regulariser, primal
+ * step tau > 0, dual step sigma > 0, extrapolation theta in [0, 1]. */
+typedef struct tvpd_coeffs {
+  float lam, tau, sigma, theta;
+} tvpd_coeffs;
+
+/* Solve parameters.  The gap of (f^k, p^k) is evaluated during iteration k
+ * whenever check_every > 0 and k % check_every == 0; the solve stops at the
+ * first such k with gap <= gap_tol * P(f^k) and returns f^k.  gap_tol < 0
+ * never stops (fixed max_iter iterations).  use_graph: 1 replays the
+ * iterations as HIP graphs, 0 launches them one by one, -1 decides. */
+typedef struct tvpd_params {
+  tvpd_coeffs c;
+  int32_t max_iter;
+  int32_t check_every;
+  double gap_tol;
+  int32_t use_graph;
+  int32_t reserved;
+} tvpd_params;
+
+/* Result of a solve: iters = k of the returned iterate; converged = 1 if a
+ * check passed; primal = P(f), dual = D(p), gap = their difference, for the
+ * returned pair (evaluated at the passing check, or at the final pair when
+ * no check passed). */
+typedef struct tvpd_result {
+  int32_t iters;
+  int32_t converged;
+  double primal, dual, gap;
+} tvpd_result;
+
+/* Name of a status code (static string, never NULL). */
+const char* tvpd_status_string(int status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int tvpd_version(void);
+
+/* ---------------------------------------------------------------------
+ * Plain solver (one image or volume).
+ * ------------------------------------------------------------------- */
+
+/* Bytes of workspace the plain solver needs for `shape` (host out). */
+int tvpd_workspace_size(const tvpd_shape* shape, size_t* bytes);
+
+/* Start a solve: f^0 = f^{-1} = g, p^0 = 0, k = 0.  g: device, dense. */
+int tvpd_init(const tvpd_shape* shape, const float* g, void* ws,
+              size_t ws_bytes, void* stream);
+
+/* Run n_iter iterations with coefficients c from the current state, without
+ * gap checks.  Resumable: the state stays in the workspace. */
+int tvpd_step(const tvpd_shape* shape, const tvpd_coeffs* c, int32_t n_iter,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the current iterate f^k (device, dense, [ny][nx] / [nz][ny][nx]) and,
+ * if p_out is not NULL, the dual p^k (device, dense, [ndim][...]). */
+int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
+                    float* f_out, float* p_out, void* stream);
+
+/* Current iteration index k (host out).  Synchronises the stream. */
+int tvpd_iteration(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
+                   int32_t* k, void* stream);
+
+/* Primal energy, dual energy and duality gap of the current pair
+ * (f^k, p^k) for weight lam, accumulated in float64: out[0] = P,
+ * out[1] = D, out[2] = gap (host out).  Synchronises the stream. */
+int tvpd_energy_gap(const tvpd_shape* shape, float lam, void* ws,
+                    size_t ws_bytes, double out[3], void* stream);
+
+/* Full solve: init from g (device), iterate with the stopping rule of
+ * tvpd_params, write the returned iterate to f_out (device, dense).  res is
+ * host memory.  Synchronises the stream. */
+int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
+               const tvpd_params* prm, void* ws, size_t ws_bytes,
+               tvpd_result* res, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Tiling of the fused 2D sweep.  A wave walks a band of `th` rows of a
+ * 256-column strip; a block holds `wpb` waves.  The iterates do not depend
+ * on the tile (halo values are recomputed with the owner's arithmetic), only
+ * the speed and the summation order of the gap do.
+ * ------------------------------------------------------------------- */
+
+/* Use this tile for `shape` from now on in this process (overrides the
+ * default and any autotuned choice).  th in [1, 65536], wpb in {1, 2, 4}. */
+int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb);
+
+/* Tile the library will use for `shape` (host out). */
+int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TVPD_H */

@@ -1,0 +1,19 @@
+"""MI355X-native primal-dual image sweep (total-variation regularised
+denoising), after the regularised inverse problem of arXiv 1608.03589,
+Section 6.
+
+The compute path is ``libtvpd.so`` (HIP, gfx950) behind the C ABI in
+``include/tvpd.h``; this package only marshals arguments and supplies device
+memory and streams through PyTorch.
+"""
+from ._lib import TVPDError, lib  # noqa: F401
+from .solver import (  # noqa: F401
+    PlainSolver, SolveResult, alloc_workspace, default_step, get_tile,
+    make_shape, set_tile, solve, workspace_size,
+)
+
+__all__ = [
+    "PlainSolver", "SolveResult", "TVPDError", "alloc_workspace",
+    "default_step", "get_tile", "lib", "make_shape", "set_tile", "solve",
+    "workspace_size",
+]

@@ -1,0 +1,417 @@
+// C ABI of the primal-dual sweep library: argument checks, workspace
+// layout, and the host side of the iteration loop.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+
+namespace tvpd {
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+
+bool shape_ok(const tvpd_shape* s) {
+  if (!s) return false;
+  if (s->ndim == 2) {
+    if (s->nz != 1) return false;
+  } else if (s->ndim == 3) {
+    if (s->nz < 1) return false;
+  } else {
+    return false;
+  }
+  if (s->ny < 1 || s->nx < 1) return false;
+  // every index fits in int32 along an axis; planes are addressed in int64
+  return s->nx <= (INT_MAX - 1024) && s->ny <= (INT_MAX - 1024);
+}
+
+// ||grad||^2 on the grid: the largest eigenvalue of the Neumann Laplacian,
+// a sum over axes of 4 sin^2(pi (n-1) / (2n)).
+double grad_norm2(const tvpd_shape& s) {
+  auto term = [](int n) {
+    const double a = std::sin(M_PI * (n - 1) / (2.0 * n));
+    return 4.0 * a * a;
+  };
+  double v = term(s.nx) + term(s.ny);
+  if (s.ndim == 3) v += term(s.nz);
+  return v;
+}
+
+int coeffs_ok(const tvpd_shape& s, const tvpd_coeffs* c) {
+  if (!c) return TVPD_ERR_INVALID_ARG;
+  if (!(c->lam >= 0.0f) || !std::isfinite(c->lam)) return TVPD_ERR_INVALID_ARG;
+  if (!(c->theta >= 0.0f && c->theta <= 1.0f)) return TVPD_ERR_INVALID_ARG;
+  if (!(c->tau > 0.0f) || !(c->sigma > 0.0f) || !std::isfinite(c->tau) ||
+      !std::isfinite(c->sigma))
+    return TVPD_ERR_STEP;
+  if ((double)c->tau * (double)c->sigma * grad_norm2(s) >= 1.0)
+    return TVPD_ERR_STEP;
+  return TVPD_OK;
+}
+
+Layout make_layout(const tvpd_shape& s) {
+  Layout L;
+  L.ndim = s.ndim;
+  L.nz = s.nz;
+  L.ny = s.ny;
+  L.nx = s.nx;
+  L.pitch = (int)round_up(s.nx, kColsPerLane);
+  L.plane = round_up((int64_t)s.nz * s.ny * L.pitch, 64);
+  L.nplanes = 3 + 2 * s.ndim + 1;
+  // enough reduction slots for one block per (strip, row) and for the
+  // one-pixel-per-thread energy kernel
+  const int64_t ntx = (s.nx + kStripCols - 1) / kStripCols;
+  const int64_t a = ntx * (int64_t)s.ny * s.nz;
+  const int64_t b = ((int64_t)s.nz * s.ny * s.nx + kMaxBlock - 1) / kMaxBlock;
+  L.max_partials = (a > b ? a : b) + 1;
+  L.partial_off = kHeaderBytes;
+  L.plane_off = (size_t)round_up((int64_t)L.partial_off + L.max_partials * 16,
+                                 (int64_t)kAlign);
+  L.bytes = L.plane_off + (size_t)L.nplanes * (size_t)L.plane * sizeof(float);
+  return L;
+}
+
+int ws_ok(const Layout& L, const void* ws, size_t bytes) {
+  if (!ws) return TVPD_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
+  if (bytes < L.bytes) return TVPD_ERR_WORKSPACE;
+  return TVPD_OK;
+}
+
+// Tile choice of the 2D sweep: a process-wide table filled by the autotuner
+// or by tvpd_set_tile; otherwise a default that gives every CU several
+// waves while keeping halo re-reads under a few percent.
+std::mutex g_tile_mu;
+struct TileEntry {
+  tvpd_shape s;
+  Tile2D t;
+};
+TileEntry g_tiles[64];
+int g_ntiles = 0;
+
+Tile2D default_tile2d(const Layout& L) {
+  Tile2D t;
+  t.wpb = 4;
+  const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
+  // aim for >= 4096 wave tiles (16 waves per CU) with th in [8, 64]
+  int th = 64;
+  while (th > 8 && ntx * ((L.ny + th - 1) / th) < 4096) th /= 2;
+  t.th = th;
+  return t;
+}
+
+Tile2D tile2d_for(const Layout& L) {
+  std::lock_guard<std::mutex> g(g_tile_mu);
+  for (int i = 0; i < g_ntiles; ++i) {
+    const tvpd_shape& s = g_tiles[i].s;
+    if (s.ndim == L.ndim && s.nz == L.nz && s.ny == L.ny && s.nx == L.nx)
+      return g_tiles[i].t;
+  }
+  return default_tile2d(L);
+}
+
+void remember_tile2d(const tvpd_shape& s, const Tile2D& t) {
+  std::lock_guard<std::mutex> g(g_tile_mu);
+  for (int i = 0; i < g_ntiles; ++i) {
+    tvpd_shape& e = g_tiles[i].s;
+    if (e.ndim == s.ndim && e.nz == s.nz && e.ny == s.ny && e.nx == s.nx) {
+      g_tiles[i].t = t;
+      return;
+    }
+  }
+  const int i = g_ntiles < 64 ? g_ntiles++ : 63;
+  g_tiles[i].s = s;
+  g_tiles[i].t = t;
+}
+
+// Per-thread host resources for polling the device convergence flag while
+// the next chunk of iterations is already queued.
+struct Poller {
+  int device = -1;
+  int32_t* host = nullptr;  // pinned, 2 slots of DevState-sized copies
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t capture = nullptr;
+  bool ok = false;
+};
+thread_local Poller t_poll;
+
+int poller_get(Poller** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TVPD_ERR_HIP;
+  Poller& p = t_poll;
+  if (p.ok && p.device == dev) {
+    *out = &p;
+    return TVPD_OK;
+  }
+  if (p.ok) {
+    // device changed: the old resources belong to another device
+    p.ok = false;
+  }
+  if (hipHostMalloc((void**)&p.host, 2 * sizeof(DevState),
+                    hipHostMallocDefault) != hipSuccess)
+    return TVPD_ERR_HIP;
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) != hipSuccess)
+      return TVPD_ERR_HIP;
+  if (hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking) != hipSuccess)
+    return TVPD_ERR_HIP;
+  p.device = dev;
+  p.ok = true;
+  *out = &p;
+  return TVPD_OK;
+}
+
+#define TVPD_HIP(call)                                    \
+  do {                                                    \
+    if ((call) != hipSuccess) return TVPD_ERR_HIP;        \
+  } while (0)
+
+int enqueue_sweeps2d(const Layout& L, const Tile2D& t, const tvpd_coeffs& c,
+                     int64_t k_first, int n, int check_every, void* ws,
+                     hipStream_t s) {
+  for (int i = 0; i < n; ++i) {
+    const int64_t kk = k_first + i;
+    const bool gap = check_every > 0 && (kk % check_every) == 0;
+    TVPD_HIP(launch_sweep2d(L, t, c, gap, ws, s));
+  }
+  return TVPD_OK;
+}
+
+int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
+            float* f_out, const tvpd_params& prm, void* ws, tvpd_result* res,
+            hipStream_t s) {
+  Poller* poll = nullptr;
+  int rc = poller_get(&poll);
+  if (rc) return rc;
+  const Tile2D t = tile2d_for(L);
+  TVPD_HIP(launch_init2d(L, g, ws, s));
+  TVPD_HIP(launch_set_params(ws, prm.max_iter, prm.gap_tol, s));
+
+  const int ce = prm.check_every;
+  const bool can_stop = ce > 0 && prm.gap_tol >= 0.0;
+  // chunk of iterations between host polls: a multiple of check_every
+  int chunk = 64;
+  if (ce > 0) chunk = ce * ((64 + ce - 1) / ce);
+  bool use_graph = prm.use_graph == 1;
+  if (prm.use_graph < 0) {
+    // graphs pay off when launches are short, i.e. on small images
+    use_graph = (int64_t)L.ny * L.nx <= (1 << 20) && prm.max_iter >= 2 * chunk;
+  }
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph && prm.max_iter >= chunk) {
+    TVPD_HIP(hipStreamBeginCapture(poll->capture, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_sweeps2d(L, t, prm.c, 0, chunk, ce, ws, poll->capture);
+    hipGraph_t gtmp = nullptr;
+    const hipError_t e = hipStreamEndCapture(poll->capture, &gtmp);
+    if (rc || e != hipSuccess) {
+      if (gtmp) (void)hipGraphDestroy(gtmp);
+      return rc ? rc : TVPD_ERR_HIP;
+    }
+    graph = gtmp;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return TVPD_ERR_HIP;
+    }
+  }
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  };
+
+  int64_t launched = 0;
+  int slot = 0, inflight = 0;
+  const DevState* dst = reinterpret_cast<const DevState*>(ws);
+  DevState* hst = reinterpret_cast<DevState*>(poll->host);
+  bool stop = false;
+  while (launched < prm.max_iter && !stop) {
+    const int n = (int)std::min<int64_t>(chunk, prm.max_iter - launched);
+    if (exec && n == chunk) {
+      if (hipGraphLaunch(exec, s) != hipSuccess) {
+        cleanup();
+        return TVPD_ERR_HIP;
+      }
+    } else {
+      rc = enqueue_sweeps2d(L, t, prm.c, launched, n, ce, ws, s);
+      if (rc) {
+        cleanup();
+        return rc;
+      }
+    }
+    launched += n;
+    if (can_stop) {
+      if (hipMemcpyAsync(&hst[slot], dst, sizeof(DevState),
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipEventRecord(poll->ev[slot], s) != hipSuccess) {
+        cleanup();
+        return TVPD_ERR_HIP;
+      }
+      ++inflight;
+      if (inflight == 2) {
+        // wait for the previous chunk only; the current one keeps the
+        // device busy meanwhile
+        const int prev = slot ^ 1;
+        if (hipEventSynchronize(poll->ev[prev]) != hipSuccess) {
+          cleanup();
+          return TVPD_ERR_HIP;
+        }
+        if (hst[prev].converged) stop = true;
+        inflight = 1;
+      }
+      slot ^= 1;
+    }
+  }
+  cleanup();
+  // final pair energies when no check passed
+  TVPD_HIP(launch_energy2d(L, prm.c.lam, ws, true, s));
+  TVPD_HIP(launch_read2d(L, ws, f_out, nullptr, s));
+  TVPD_HIP(hipMemcpyAsync(&hst[0], dst, sizeof(DevState),
+                          hipMemcpyDeviceToHost, s));
+  TVPD_HIP(hipStreamSynchronize(s));
+  if (res) {
+    res->converged = hst[0].converged;
+    res->iters = hst[0].converged ? hst[0].iters : hst[0].k;
+    res->primal = hst[0].P;
+    res->dual = hst[0].D;
+    res->gap = hst[0].gap;
+  }
+  return TVPD_OK;
+}
+
+}  // namespace
+}  // namespace tvpd
+
+using namespace tvpd;
+
+extern "C" {
+
+const char* tvpd_status_string(int status) {
+  switch (status) {
+    case TVPD_OK: return "ok";
+    case TVPD_ERR_INVALID_ARG: return "invalid argument";
+    case TVPD_ERR_SHAPE: return "invalid shape";
+    case TVPD_ERR_ALIGNMENT: return "workspace not 256-byte aligned";
+    case TVPD_ERR_WORKSPACE: return "workspace too small";
+    case TVPD_ERR_HIP: return "HIP runtime error";
+    case TVPD_ERR_UNSUPPORTED: return "unsupported request";
+    case TVPD_ERR_STEP: return "step sizes violate tau*sigma*||grad||^2 < 1";
+    case TVPD_ERR_DEVICE: return "device-side check failed";
+    default: return "unknown status";
+  }
+}
+
+int tvpd_version(void) { return kVersion; }
+
+int tvpd_workspace_size(const tvpd_shape* shape, size_t* bytes) {
+  if (!bytes) return TVPD_ERR_INVALID_ARG;
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  *bytes = make_layout(*shape).bytes;
+  return TVPD_OK;
+}
+
+int tvpd_init(const tvpd_shape* shape, const float* g, void* ws,
+              size_t ws_bytes, void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (!g) return TVPD_ERR_INVALID_ARG;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  return launch_init2d(L, g, ws, (hipStream_t)stream) == hipSuccess
+             ? TVPD_OK
+             : TVPD_ERR_HIP;
+}
+
+int tvpd_step(const tvpd_shape* shape, const tvpd_coeffs* c, int32_t n_iter,
+              void* ws, size_t ws_bytes, void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (n_iter < 0) return TVPD_ERR_INVALID_ARG;
+  if (int rc = coeffs_ok(*shape, c)) return rc;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  TVPD_HIP(launch_set_params(ws, INT_MAX, -1.0, s));
+  const Tile2D t = tile2d_for(L);
+  return enqueue_sweeps2d(L, t, *c, 0, n_iter, 0, ws, s);
+}
+
+int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
+                    float* f_out, float* p_out, void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (!f_out) return TVPD_ERR_INVALID_ARG;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  return launch_read2d(L, ws, f_out, p_out, (hipStream_t)stream) == hipSuccess
+             ? TVPD_OK
+             : TVPD_ERR_HIP;
+}
+
+int tvpd_iteration(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
+                   int32_t* k, void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (!k) return TVPD_ERR_INVALID_ARG;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  int32_t v = 0;
+  TVPD_HIP(hipMemcpyAsync(&v, ws, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  TVPD_HIP(hipStreamSynchronize(s));
+  *k = v;
+  return TVPD_OK;
+}
+
+int tvpd_energy_gap(const tvpd_shape* shape, float lam, void* ws,
+                    size_t ws_bytes, double out[3], void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (!out || !(lam >= 0.0f)) return TVPD_ERR_INVALID_ARG;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  TVPD_HIP(launch_energy2d(L, lam, ws, false, s));
+  DevState h;
+  TVPD_HIP(hipMemcpyAsync(&h, ws, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  TVPD_HIP(hipStreamSynchronize(s));
+  out[0] = h.P;
+  out[1] = h.D;
+  out[2] = h.gap;
+  return TVPD_OK;
+}
+
+int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
+               const tvpd_params* prm, void* ws, size_t ws_bytes,
+               tvpd_result* res, void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (!g || !f_out || !prm) return TVPD_ERR_INVALID_ARG;
+  if (prm->max_iter < 0 || prm->check_every < 0) return TVPD_ERR_INVALID_ARG;
+  if (std::isnan(prm->gap_tol)) return TVPD_ERR_INVALID_ARG;
+  if (int rc = coeffs_ok(*shape, &prm->c)) return rc;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  return solve2d(*shape, L, g, f_out, *prm, ws, res, (hipStream_t)stream);
+}
+
+int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (th < 1 || th > 65536) return TVPD_ERR_INVALID_ARG;
+  if (wpb != 1 && wpb != 2 && wpb != 4) return TVPD_ERR_INVALID_ARG;
+  Tile2D t;
+  t.th = th;
+  t.wpb = wpb;
+  remember_tile2d(*shape, t);
+  return TVPD_OK;
+}
+
+int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (!th || !wpb) return TVPD_ERR_INVALID_ARG;
+  const Tile2D t = tile2d_for(make_layout(*shape));
+  *th = t.th;
+  *wpb = t.wpb;
+  return TVPD_OK;
+}
+
+}  // extern "C"

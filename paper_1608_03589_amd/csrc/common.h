@@ -1,0 +1,84 @@
+// Internal definitions shared by the HIP kernels and the host entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tvpd.h"
+
+namespace tvpd {
+
+constexpr int kWave = 64;               // CDNA wavefront width
+constexpr int kColsPerLane = 4;         // one float4 per lane and row
+constexpr int kStripCols = kWave * kColsPerLane;  // columns per wave strip
+constexpr int kMaxBlock = 256;          // threads per block (4 waves)
+constexpr size_t kHeaderBytes = 4096;   // state header at the workspace start
+constexpr size_t kAlign = 256;
+
+// Solver state kept in device memory at the start of a workspace.  Kernels
+// read k to find the ring slots of f^k, f^{k-1}, f^{k+1}, p^k, p^{k+1}; the
+// last block of every sweep advances k (or freezes it on convergence).
+struct DevState {
+  int32_t k;             // index of the current iterate
+  int32_t k_end;         // sweeps do nothing once k >= k_end
+  int32_t converged;     // set by a passing gap check (k is then frozen)
+  int32_t iters;         // k at which the passing check happened
+  uint32_t blocks_done;  // completion counter of the running sweep
+  int32_t checks;        // number of gap checks performed
+  int32_t nblocks;       // block count of the last gap sweep
+  int32_t flags;         // device-side error bits
+  double P, D, gap;      // energies of the last evaluated pair
+  double tol;            // relative gap tolerance (< 0: never stop)
+  double pad[8];
+};
+static_assert(sizeof(DevState) <= 256, "state header");
+
+// Workspace layout of the plain solver (2D and 3D share it).
+struct Layout {
+  int ndim;
+  int nz, ny, nx;
+  int pitch;              // floats per stored row (multiple of 4, >= nx)
+  int64_t plane;          // floats per plane (multiple of 64)
+  int nplanes;            // 3 (f ring) + 2*ndim (dual ring) + 1 (g)
+  int64_t max_partials;   // reduction slots (2 doubles each)
+  size_t partial_off;     // byte offset of the partials
+  size_t plane_off;       // byte offset of plane 0
+  size_t bytes;           // total
+};
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Tile configuration of the 2D sweep: each wave owns a strip of 256 columns
+// and `th` rows; a block holds `wpb` waves stacked vertically.
+struct Tile2D {
+  int th;
+  int wpb;
+};
+
+// Arguments of the fused 2D sweep kernel (passed by value).
+struct Sweep2DArgs {
+  float* base;        // plane 0 of the workspace
+  int64_t plane;      // floats per plane
+  int32_t ny, nx, pitch;
+  int32_t th, wpb;
+  int32_t ntx, nty, ntiles;  // wave tiles: ntx strips by nty row bands
+  float lam, tau, sigma, theta;
+  DevState* st;
+  double* partials;   // 2 doubles per block (gap, P)
+};
+
+// Host launchers (kernels2d.hip).
+hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
+                         hipStream_t s);
+hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
+                          const tvpd_coeffs& c, bool with_gap, void* ws,
+                          hipStream_t s);
+hipError_t launch_read2d(const Layout& L, const void* ws, float* f_out,
+                         float* p_out, hipStream_t s);
+hipError_t launch_energy2d(const Layout& L, float lam, void* ws,
+                           bool skip_if_converged, hipStream_t s);
+hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
+                             hipStream_t s);
+int sweep2d_blocks(const Layout& L, const Tile2D& t);
+
+}  // namespace tvpd

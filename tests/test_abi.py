@@ -1,0 +1,122 @@
+"""The C ABI without a GPU: symbols, signatures and argument validation.
+
+Validation runs before any HIP call, so every error path here is reachable
+on a machine without a GPU.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1608_03589_amd import _lib
+from paper_1608_03589_amd._lib import Coeffs, Params, Result, Shape
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tvpd.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tvpd_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, f"{n} has no ctypes signature"
+
+
+def test_status_strings(L):
+    assert L.tvpd_status_string(0) == b"ok"
+    for code in range(-8, 0):
+        s = L.tvpd_status_string(code)
+        assert s and s != b"unknown status"
+    assert L.tvpd_status_string(12345) == b"unknown status"
+    assert L.tvpd_version() >= 10000
+
+
+def test_struct_layouts():
+    assert C.sizeof(Shape) == 16
+    assert C.sizeof(Coeffs) == 16
+    assert C.sizeof(Params) == 40
+    assert Params.gap_tol.offset == 24
+    assert C.sizeof(Result) == 32
+
+
+def _ws(shape):
+    n = C.c_size_t()
+    st = _lib.lib().tvpd_workspace_size(C.byref(shape), C.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_grows_and_validates():
+    st, a = _ws(Shape(2, 1, 256, 256))
+    assert st == 0 and a >= 8 * 256 * 256 * 4
+    st, b = _ws(Shape(2, 1, 4096, 4096))
+    assert st == 0 and b >= 8 * 4096 * 4096 * 4 and b < 8.2 * 4096 * 4096 * 4
+    st, c = _ws(Shape(2, 1, 7, 5))   # ragged: pitch rounds 5 up to 8
+    assert st == 0 and c >= 8 * 7 * 8 * 4
+    for bad in [Shape(2, 2, 4, 4), Shape(4, 1, 4, 4), Shape(2, 1, 0, 4),
+                Shape(2, 1, 4, -1), Shape(3, 0, 4, 4)]:
+        assert _ws(bad)[0] == -2
+    assert _lib.lib().tvpd_workspace_size(C.byref(Shape(2, 1, 4, 4)), None) == -1
+
+
+def _solve(shape, prm, ws, nbytes, g=0x1000, f=0x2000):
+    return _lib.lib().tvpd_solve(C.byref(shape), C.c_void_p(g), C.c_void_p(f),
+                                 C.byref(prm), C.c_void_p(ws), nbytes,
+                                 C.byref(Result()), None)
+
+
+def test_solve_argument_errors_before_any_device_call():
+    sh = Shape(2, 1, 64, 64)
+    _, need = _ws(sh)
+    s = 1 / 8 ** 0.5
+    good = Params(Coeffs(0.1, s, s, 1.0), 100, 10, 1e-4, -1, 0)
+    aligned = 1 << 20
+    assert _solve(Shape(2, 1, 0, 4), good, aligned, need) == -2
+    assert _solve(sh, good, 0, need) == -1                      # null ws
+    assert _solve(sh, good, aligned, need, g=0) == -1            # null g
+    assert _solve(sh, good, aligned + 16, need) == -3            # misaligned
+    assert _solve(sh, good, aligned, need - 1) == -4             # too small
+    bad_step = Params(Coeffs(0.1, 0.5, 0.5, 1.0), 100, 10, 1e-4, -1, 0)
+    assert _solve(sh, bad_step, aligned, need) == -7
+    neg_lam = Params(Coeffs(-0.1, s, s, 1.0), 100, 10, 1e-4, -1, 0)
+    assert _solve(sh, neg_lam, aligned, need) == -1
+    bad_theta = Params(Coeffs(0.1, s, s, 1.5), 100, 10, 1e-4, -1, 0)
+    assert _solve(sh, bad_theta, aligned, need) == -1
+    neg_iter = Params(Coeffs(0.1, s, s, 1.0), -1, 10, 1e-4, -1, 0)
+    assert _solve(sh, neg_iter, aligned, need) == -1
+    nan_tol = Params(Coeffs(0.1, s, s, 1.0), 10, 10, float("nan"), -1, 0)
+    assert _solve(sh, nan_tol, aligned, need) == -1
+
+
+def test_step_bound_is_the_grid_norm():
+    """tau sigma ||grad||^2 < 1 is checked with the exact grid norm: on a
+    2 x 2 image ||grad||^2 = 4, so tau = sigma = 0.49 passes and 0.51 fails."""
+    sh = Shape(2, 1, 2, 2)
+    _, need = _ws(sh)
+    L = _lib.lib()
+    ok = Coeffs(0.1, 0.49, 0.49, 1.0)
+    bad = Coeffs(0.1, 0.51, 0.51, 1.0)
+    # tvpd_step validates coefficients before touching the workspace
+    assert L.tvpd_step(C.byref(sh), C.byref(bad), 1, C.c_void_p(1 << 20), need,
+                       None) == -7
+    assert L.tvpd_step(C.byref(sh), C.byref(ok), -1, C.c_void_p(1 << 20), need,
+                       None) == -1
+
+
+def test_loud_failure_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.lib()

@@ -1,0 +1,236 @@
+"""GPU parity of the plain 2D solver against the FP64 oracle.
+
+Tolerances: the iterate after a fixed number of iterations must match the
+oracle to a relative L2 error of 1e-5 (float32 device arithmetic against
+float64); integer-valued results (iteration counts, bitwise tile invariance)
+are compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1608_03589_amd as tv
+from scenes import WORKLOADS, scene2d
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+S2 = 1.0 / math.sqrt(8.0)
+RTOL = 1e-5
+LAM32 = float(np.float32(0.1))   # the device holds lam in float32
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) /
+                 max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_fixed(g32, n, lam=0.1, tile=None, use_graph=-1):
+    if tile is not None:
+        tv.set_tile(g32.shape, *tile)
+    s = tv.PlainSolver(g32.shape, DEV)
+    s.solve(torch.from_numpy(g32).to(DEV), lam=lam, tau=S2, sigma=S2,
+            max_iter=n, check_every=0, gap_tol=-1.0, use_graph=use_graph)
+    f, p = s.state()
+    torch.cuda.synchronize()
+    return f.cpu().numpy(), p.cpu().numpy(), s
+
+
+def scene32(H, W, n_shapes, noise, seed):
+    _, g = scene2d(H, W, n_shapes, noise, seed)
+    return g.astype(np.float32)
+
+
+def test_parity_denoise_256_1000_iterations():
+    w = WORKLOADS["denoise_256"]
+    g32 = scene32(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    print(f"case: denoise_256 fixed {w['iters']} iterations", flush=True)
+    f, p, _ = gpu_fixed(g32, w["iters"], w["lam"])
+    f_ref, _, p_ref = oracle.run_fixed(g32.astype(np.float64), w["lam"], S2,
+                                       S2, w["iters"])
+    ef, ep = rel(f, f_ref), rel(p, p_ref)
+    print(f"rel L2 f = {ef:.3e}, p = {ep:.3e}")
+    assert ef <= RTOL
+    assert ep <= 10 * RTOL
+
+
+@pytest.mark.parametrize("shape,tile", [
+    ((1, 1), None), ((1, 7), None), ((7, 1), None), ((5, 3), (2, 1)),
+    ((37, 301), (3, 2)), ((130, 513), (7, 4)), ((300, 260), (64, 1)),
+    ((64, 1029), (5, 4)), ((2, 2), (1, 1)),
+])
+def test_parity_ragged_shapes(shape, tile):
+    print(f"case: ragged {shape} tile {tile}", flush=True)
+    g32 = scene32(shape[0], shape[1], 6, 0.1, 100 + shape[0] * 7 + shape[1])
+    n = 60
+    f, p, _ = gpu_fixed(g32, n, 0.1, tile)
+    f_ref, _, p_ref = oracle.run_fixed(g32.astype(np.float64), 0.1, S2, S2, n)
+    assert rel(f, f_ref) <= RTOL
+    if np.linalg.norm(p_ref) > 0:
+        assert rel(p, p_ref) <= 10 * RTOL
+    else:
+        assert np.all(p == 0)
+
+
+def test_tile_invariance_bitwise():
+    """Halo values are recomputed with the owner's arithmetic, so every tile
+    shape gives bit-identical iterates."""
+    shape = (300, 517)
+    g32 = scene32(*shape, 10, 0.1, 77)
+    outs = []
+    for tile in [(1, 1), (3, 2), (8, 4), (64, 4), (300, 1)]:
+        print(f"case: tile {tile}", flush=True)
+        f, p, _ = gpu_fixed(g32, 40, 0.1, tile)
+        outs.append((f, p))
+    for f, p in outs[1:]:
+        assert np.array_equal(f, outs[0][0])
+        assert np.array_equal(p, outs[0][1])
+
+
+def test_resume_and_graph_replay_bitwise():
+    shape = (200, 333)
+    g32 = scene32(*shape, 10, 0.1, 78)
+    gt = torch.from_numpy(g32).to(DEV)
+    a = tv.PlainSolver(shape, DEV)
+    a.init(gt)
+    a.step(25, 0.1, S2, S2)
+    a.step(25, 0.1, S2, S2)
+    assert a.iteration() == 50
+    fa, pa = a.state()
+    b = tv.PlainSolver(shape, DEV)
+    b.init(gt)
+    b.step(50, 0.1, S2, S2)
+    fb, pb = b.state()
+    assert torch.equal(fa, fb) and torch.equal(pa, pb)
+    f1, r1 = tv.PlainSolver(shape, DEV).solve(gt, 0.1, max_iter=300,
+                                              check_every=10, gap_tol=-1.0,
+                                              use_graph=1)
+    f0, r0 = tv.PlainSolver(shape, DEV).solve(gt, 0.1, max_iter=300,
+                                              check_every=10, gap_tol=-1.0,
+                                              use_graph=0)
+    assert torch.equal(f1, f0)
+    assert r1.iters == r0.iters == 300 and r1.gap == r0.gap
+
+
+def test_solve_stops_like_oracle():
+    w = WORKLOADS["denoise_256"]
+    g32 = scene32(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    g64 = g32.astype(np.float64)
+    ref = oracle.solve(g64, w["lam"], S2, S2, max_iter=w["iters"], check_every=10,
+                       gap_tol=1e-4, return_history=True)
+    for use_graph in (0, 1):
+        print(f"case: stopping solve use_graph={use_graph}", flush=True)
+        f, res = tv.PlainSolver(g32.shape, DEV).solve(
+            torch.from_numpy(g32).to(DEV), w["lam"], max_iter=w["iters"],
+            check_every=10, gap_tol=1e-4, use_graph=use_graph)
+        assert res.converged and ref["converged"]
+        assert abs(res.iters - ref["iters"]) <= 10
+        hist = {h[0]: h for h in ref["history"]}
+        _, P_ref, _, gap_ref = hist[res.iters]
+        assert abs(res.primal - P_ref) <= 1e-5 * P_ref
+        assert abs(res.gap - gap_ref) <= 1e-2 * gap_ref
+        f_ref, _, _ = oracle.run_fixed(g64, w["lam"], S2, S2, res.iters)
+        assert rel(f.cpu().numpy(), f_ref) <= RTOL
+
+
+def test_energy_gap_of_device_state_matches_oracle():
+    shape = (173, 289)
+    g32 = scene32(*shape, 12, 0.1, 79)
+    s = tv.PlainSolver(shape, DEV)
+    s.init(torch.from_numpy(g32).to(DEV))
+    s.step(70, 0.1, S2, S2)
+    f, p = s.state()
+    P, D, gap = s.energy_gap(0.1)
+    Pr, Dr, gr = oracle.energy_gap(f.cpu().numpy().astype(np.float64),
+                                   p.cpu().numpy().astype(np.float64),
+                                   g32.astype(np.float64), LAM32)
+    assert abs(P - Pr) <= 1e-10 * abs(Pr)
+    assert abs(gap - gr) <= 1e-10 * abs(Pr)
+    assert abs(D - Dr) <= 1e-10 * abs(Pr)
+
+
+def test_fused_gap_equals_standalone_gap():
+    """A solve that stops at a check reports the gap reduced inside the sweep;
+    re-evaluating the frozen pair with the standalone kernel gives the same
+    value up to summation order."""
+    shape = (257, 300)
+    g32 = scene32(*shape, 12, 0.1, 80)
+    s = tv.PlainSolver(shape, DEV)
+    f, res = s.solve(torch.from_numpy(g32).to(DEV), 0.1, max_iter=2000,
+                     check_every=10, gap_tol=1e-2)
+    assert res.converged and res.iters > 0
+    assert s.iteration() == res.iters
+    P, D, gap = s.energy_gap(0.1)
+    assert abs(P - res.primal) <= 1e-12 * P
+    assert abs(gap - res.gap) <= 1e-9 * P
+    assert torch.equal(f, s.state(with_dual=False))
+
+
+def _crop_bounds(c, r, n):
+    return max(c - r, 0), min(c + r + 1, n)
+
+
+def test_full_size_4096_sampled_windows():
+    """At 4096 x 4096 in the default launch configuration: after N
+    iterations a pixel depends only on data within N + 1 pixels, so the
+    oracle on a crop with a margin of N + 2 (or the true image edge)
+    reproduces sampled windows of the full-size run exactly."""
+    w = WORKLOADS["denoise_4096"]
+    g32 = scene32(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    N = 12
+    print(f"case: 4096 sampled windows, tile {tv.get_tile(g32.shape)}", flush=True)
+    f, p, _ = gpu_fixed(g32, N, w["lam"])
+    th, _ = tv.get_tile(g32.shape)
+    H, W = g32.shape
+    rng = np.random.default_rng(7)
+    centres = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, 255),
+               (H // 2, 256), (th - 1, 1000), (th, 1000), (5 * th, 511),
+               (H - 1, 2047), (17, W - 1)]
+    centres += [tuple(rng.integers(0, [H, W])) for _ in range(6)]
+    m = N + 2
+    for (cy, cx) in centres:
+        y0, y1 = _crop_bounds(cy, m + 3, H)
+        x0, x1 = _crop_bounds(cx, m + 3, W)
+        crop = g32[y0:y1, x0:x1].astype(np.float64)
+        fr, _, pr = oracle.run_fixed(crop, w["lam"], S2, S2, N)
+        # compare the part of the window that is at least m away from any
+        # crop edge that is not a true image edge
+        iy0 = 0 if y0 == 0 else m
+        iy1 = (y1 - y0) if y1 == H else (y1 - y0) - m
+        ix0 = 0 if x0 == 0 else m
+        ix1 = (x1 - x0) if x1 == W else (x1 - x0) - m
+        got = f[y0 + iy0:y0 + iy1, x0 + ix0:x0 + ix1]
+        exp = fr[iy0:iy1, ix0:ix1]
+        assert got.size > 0
+        assert rel(got, exp) <= RTOL, (cy, cx)
+        gotp = p[:, y0 + iy0:y0 + iy1, x0 + ix0:x0 + ix1]
+        expp = pr[:, iy0:iy1, ix0:ix1]
+        assert np.max(np.abs(gotp - expp)) <= 1e-5 * max(w["lam"], 1e-12), (cy, cx)
+
+
+def test_full_size_4096_properties():
+    """The benchmarked run itself (2000 iterations, gap every 10): mass is
+    conserved, the dual stays feasible, the gap is non-negative, and the
+    gap of the final pair agrees with the oracle's evaluation of it."""
+    w = WORKLOADS["denoise_4096"]
+    g32 = scene32(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    s = tv.PlainSolver(g32.shape, DEV)
+    gt = torch.from_numpy(g32).to(DEV)
+    print("case: 4096 full run properties", flush=True)
+    f, res = s.solve(gt, w["lam"], max_iter=w["iters"], check_every=10,
+                     gap_tol=-1.0)
+    assert res.iters == w["iters"] and not res.converged
+    fd, pd = s.state()
+    fn = fd.double().cpu().numpy()
+    pn = pd.double().cpu().numpy()
+    assert abs(fn.sum() - g32.astype(np.float64).sum()) <= 1e-6 * np.abs(g32).sum()
+    nrm = np.sqrt((pn ** 2).sum(axis=0))
+    assert nrm.max() <= w["lam"] * (1 + 1e-6)
+    assert res.gap >= 0 and res.gap < 1e-2 * res.primal
+    Pr, Dr, gr = oracle.energy_gap(fn, pn, g32.astype(np.float64),
+                                   float(np.float32(w["lam"])))
+    assert abs(res.primal - Pr) <= 1e-9 * Pr
+    assert abs(res.gap - gr) <= 1e-9 * Pr
