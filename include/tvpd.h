@@ -147,17 +147,39 @@ int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
 
 /* ---------------------------------------------------------------------
  * Tiling of the fused 2D sweep.  A wave walks a band of `th` rows of a
- * 256-column strip; a block holds `wpb` waves.  The iterates do not depend
- * on the tile (halo values are recomputed with the owner's arithmetic), only
- * the speed and the summation order of the gap do.
+ * 256-column strip; a block holds `wpb` consecutive wave tiles, numbered
+ * band by band (order 0: a block's waves sit side by side) or strip by
+ * strip (order 1: stacked).  The iterates do not depend on the tile (halo
+ * values are recomputed with the owner's arithmetic), only the speed and the
+ * summation order of the gap do.
  * ------------------------------------------------------------------- */
 
 /* Use this tile for `shape` from now on in this process (overrides the
- * default and any autotuned choice).  th in [1, 65536], wpb in {1, 2, 4}. */
-int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb);
+ * default and any autotuned choice).  th in [1, 65536], wpb in {1, 2, 4},
+ * order in {0, 1}. */
+int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
+                  int32_t order);
 
 /* Tile the library will use for `shape` (host out). */
-int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb);
+int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb,
+                  int32_t* order);
+
+/* Autotuner.  Times every candidate tile (th from 4 to 256, wpb 1/2/4, both
+ * orders) of the sweep on `ws`, an initialised workspace of this shape, and
+ * keeps the fastest for `shape` in this process.  The workspace state is
+ * advanced by the timing runs: call tvpd_init before solving with it.  If
+ * cache_path is not NULL the choice is appended to that text file (one line
+ * per shape: arch ndim nz ny nx th wpb order microseconds).  Outputs (host,
+ * each may be NULL): the chosen tile and its time per sweep in microseconds.
+ * Synchronises the stream. */
+int tvpd_autotune(const tvpd_shape* shape, void* ws, size_t ws_bytes,
+                  const char* cache_path, int32_t* th, int32_t* wpb,
+                  int32_t* order, float* us, void* stream);
+
+/* Read tiles recorded by tvpd_autotune for the current device's
+ * architecture from cache_path; later lines override earlier ones.
+ * *count (host) receives the number of entries taken. */
+int tvpd_tune_load(const char* cache_path, int32_t* count);
 
 #ifdef __cplusplus
 }

@@ -8,12 +8,13 @@ memory and streams through PyTorch.
 """
 from ._lib import TVPDError, lib  # noqa: F401
 from .solver import (  # noqa: F401
-    PlainSolver, SolveResult, alloc_workspace, default_step, get_tile,
-    make_shape, set_tile, solve, workspace_size,
+    PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
+    get_tile, make_shape, set_tile, solve, tune_load, workspace_size,
 )
 
 __all__ = [
-    "PlainSolver", "SolveResult", "TVPDError", "alloc_workspace",
+    "PlainSolver", "SolveResult", "TVPDError", "alloc_workspace", "autotune",
+    "tune_load",
     "default_step", "get_tile", "lib", "make_shape", "set_tile", "solve",
     "workspace_size",
 ]

@@ -65,8 +65,13 @@ SIGNATURES = {
                                   C.POINTER(C.c_double), _P]),
     "tvpd_solve": (C.c_int, [C.POINTER(Shape), _P, _P, C.POINTER(Params), _P, _SZ,
                              C.POINTER(Result), _P]),
-    "tvpd_set_tile": (C.c_int, [C.POINTER(Shape), _I32, _I32]),
-    "tvpd_get_tile": (C.c_int, [C.POINTER(Shape), C.POINTER(_I32), C.POINTER(_I32)]),
+    "tvpd_set_tile": (C.c_int, [C.POINTER(Shape), _I32, _I32, _I32]),
+    "tvpd_get_tile": (C.c_int, [C.POINTER(Shape), C.POINTER(_I32), C.POINTER(_I32),
+                                C.POINTER(_I32)]),
+    "tvpd_autotune": (C.c_int, [C.POINTER(Shape), _P, _SZ, C.c_char_p,
+                                C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
+                                C.POINTER(C.c_float), _P]),
+    "tvpd_tune_load": (C.c_int, [C.c_char_p, C.POINTER(_I32)]),
 }
 
 _lib = None

@@ -12,6 +12,12 @@ namespace {
 
 constexpr int kVersion = 10000;  // 1.0.0
 
+// Floats added to every plane so that consecutive planes do not start at
+// the same offset modulo large powers of two (a multiple of 64).
+#ifndef TVPD_PLANE_PAD
+#define TVPD_PLANE_PAD 0
+#endif
+
 bool shape_ok(const tvpd_shape* s) {
   if (!s) return false;
   if (s->ndim == 2) {
@@ -57,7 +63,7 @@ Layout make_layout(const tvpd_shape& s) {
   L.ny = s.ny;
   L.nx = s.nx;
   L.pitch = (int)round_up(s.nx, kColsPerLane);
-  L.plane = round_up((int64_t)s.nz * s.ny * L.pitch, 64);
+  L.plane = round_up((int64_t)s.nz * s.ny * L.pitch, 64) + TVPD_PLANE_PAD;
   L.nplanes = 3 + 2 * s.ndim + 1;
   // enough reduction slots for one block per (strip, row) and for the
   // one-pixel-per-thread energy kernel
@@ -77,52 +83,6 @@ int ws_ok(const Layout& L, const void* ws, size_t bytes) {
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
   if (bytes < L.bytes) return TVPD_ERR_WORKSPACE;
   return TVPD_OK;
-}
-
-// Tile choice of the 2D sweep: a process-wide table filled by the autotuner
-// or by tvpd_set_tile; otherwise a default that gives every CU several
-// waves while keeping halo re-reads under a few percent.
-std::mutex g_tile_mu;
-struct TileEntry {
-  tvpd_shape s;
-  Tile2D t;
-};
-TileEntry g_tiles[64];
-int g_ntiles = 0;
-
-Tile2D default_tile2d(const Layout& L) {
-  Tile2D t;
-  t.wpb = 4;
-  const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
-  // aim for >= 4096 wave tiles (16 waves per CU) with th in [8, 64]
-  int th = 64;
-  while (th > 8 && ntx * ((L.ny + th - 1) / th) < 4096) th /= 2;
-  t.th = th;
-  return t;
-}
-
-Tile2D tile2d_for(const Layout& L) {
-  std::lock_guard<std::mutex> g(g_tile_mu);
-  for (int i = 0; i < g_ntiles; ++i) {
-    const tvpd_shape& s = g_tiles[i].s;
-    if (s.ndim == L.ndim && s.nz == L.nz && s.ny == L.ny && s.nx == L.nx)
-      return g_tiles[i].t;
-  }
-  return default_tile2d(L);
-}
-
-void remember_tile2d(const tvpd_shape& s, const Tile2D& t) {
-  std::lock_guard<std::mutex> g(g_tile_mu);
-  for (int i = 0; i < g_ntiles; ++i) {
-    tvpd_shape& e = g_tiles[i].s;
-    if (e.ndim == s.ndim && e.nz == s.nz && e.ny == s.ny && e.nx == s.nx) {
-      g_tiles[i].t = t;
-      return;
-    }
-  }
-  const int i = g_ntiles < 64 ? g_ntiles++ : 63;
-  g_tiles[i].s = s;
-  g_tiles[i].t = t;
 }
 
 // Per-thread host resources for polling the device convergence flag while
@@ -394,23 +354,57 @@ int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
   return solve2d(*shape, L, g, f_out, *prm, ws, res, (hipStream_t)stream);
 }
 
-int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb) {
+int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
+                  int32_t order) {
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
   if (th < 1 || th > 65536) return TVPD_ERR_INVALID_ARG;
   if (wpb != 1 && wpb != 2 && wpb != 4) return TVPD_ERR_INVALID_ARG;
+  if (order != 0 && order != 1) return TVPD_ERR_INVALID_ARG;
   Tile2D t;
   t.th = th;
   t.wpb = wpb;
+  t.order = order;
   remember_tile2d(*shape, t);
   return TVPD_OK;
 }
 
-int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb) {
+int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb,
+                  int32_t* order) {
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
-  if (!th || !wpb) return TVPD_ERR_INVALID_ARG;
+  if (!th || !wpb || !order) return TVPD_ERR_INVALID_ARG;
   const Tile2D t = tile2d_for(make_layout(*shape));
   *th = t.th;
   *wpb = t.wpb;
+  *order = t.order;
+  return TVPD_OK;
+}
+
+int tvpd_autotune(const tvpd_shape* shape, void* ws, size_t ws_bytes,
+                  const char* cache_path, int32_t* th, int32_t* wpb,
+                  int32_t* order, float* us, void* stream) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  const Layout L = make_layout(*shape);
+  if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  Tile2D best;
+  float best_us = 0.0f;
+  if (int rc = autotune2d(*shape, L, ws, (hipStream_t)stream, &best, &best_us))
+    return rc;
+  if (cache_path) {
+    if (int rc = tune_save(cache_path, *shape, best, best_us)) return rc;
+  }
+  if (th) *th = best.th;
+  if (wpb) *wpb = best.wpb;
+  if (order) *order = best.order;
+  if (us) *us = best_us;
+  return TVPD_OK;
+}
+
+int tvpd_tune_load(const char* cache_path, int32_t* count) {
+  if (!cache_path || !count) return TVPD_ERR_INVALID_ARG;
+  int n = 0;
+  if (int rc = tune_load(cache_path, &n)) return rc;
+  *count = n;
   return TVPD_OK;
 }
 

@@ -1,0 +1,201 @@
+// Tile selection for the fused 2D sweep: a process-wide table of chosen
+// tiles, a default rule, a measuring autotuner and a small text cache.
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace tvpd {
+namespace {
+
+struct TileEntry {
+  tvpd_shape s;
+  Tile2D t;
+};
+
+std::mutex g_mu;
+std::vector<TileEntry> g_table;
+
+bool same(const tvpd_shape& a, const Layout& L) {
+  return a.ndim == L.ndim && a.nz == L.nz && a.ny == L.ny && a.nx == L.nx;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipGetDeviceProperties(&p, dev) == hipSuccess && p.multiProcessorCount > 0)
+      cus = p.multiProcessorCount;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipGetDeviceProperties(&p, dev) == hipSuccess) {
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+  }
+  return "unknown";
+}
+
+}  // namespace
+
+// Default: blocks of 4 side-by-side waves, bands tall enough that the grid
+// is about one block per compute unit.  Few concurrent row streams keep HBM
+// pages open; one block per CU keeps the CUs evenly loaded.
+Tile2D default_tile2d(const Layout& L) {
+  Tile2D t;
+  t.wpb = 4;
+  t.order = 0;
+  const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
+  const int64_t target_waves = 4LL * device_cus();
+  int64_t th = (ntx * L.ny + target_waves - 1) / target_waves;
+  if (th < 8) th = 8;
+  if (th > 256) th = 256;
+  t.th = (int)th;
+  return t;
+}
+
+Tile2D tile2d_for(const Layout& L) {
+  std::lock_guard<std::mutex> g(g_mu);
+  for (const TileEntry& e : g_table)
+    if (same(e.s, L)) return e.t;
+  return default_tile2d(L);
+}
+
+void remember_tile2d(const tvpd_shape& s, const Tile2D& t) {
+  std::lock_guard<std::mutex> g(g_mu);
+  for (TileEntry& e : g_table) {
+    if (e.s.ndim == s.ndim && e.s.nz == s.nz && e.s.ny == s.ny &&
+        e.s.nx == s.nx) {
+      e.t = t;
+      return;
+    }
+  }
+  g_table.push_back({s, t});
+}
+
+// Time one tile: warm up, then enough sweeps for about 2 ms of work.
+static int time_tile(const Layout& L, const Tile2D& t, void* ws,
+                     hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* us) {
+  tvpd_coeffs c;
+  c.lam = 0.1f;
+  c.tau = c.sigma = 0.35355339f;
+  c.theta = 1.0f;
+  if (sweep2d_blocks(L, t) > L.max_partials) return TVPD_ERR_INVALID_ARG;
+  for (int i = 0; i < 2; ++i)
+    if (launch_sweep2d(L, t, c, false, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+  int n = 2;
+  float ms = 0.0f;
+  for (int round = 0; round < 2; ++round) {
+    if (hipEventRecord(e0, s) != hipSuccess) return TVPD_ERR_HIP;
+    for (int i = 0; i < n; ++i)
+      if (launch_sweep2d(L, t, c, false, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+    if (hipEventRecord(e1, s) != hipSuccess) return TVPD_ERR_HIP;
+    if (hipEventSynchronize(e1) != hipSuccess) return TVPD_ERR_HIP;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TVPD_ERR_HIP;
+    if (round == 0) {
+      const float per = ms / n;
+      n = per > 0.0f ? (int)(2.0f / per) : 50;
+      if (n < 3) n = 3;
+      if (n > 200) n = 200;
+    }
+  }
+  *us = ms * 1000.0f / n;
+  return TVPD_OK;
+}
+
+int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
+               Tile2D* best, float* best_us) {
+  if (launch_set_params(ws, 0x7fffffff, -1.0, s) != hipSuccess) return TVPD_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return TVPD_ERR_HIP;
+  static const int ths[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+  static const int wpbs[] = {1, 2, 4};
+  float bu = 1e30f;
+  Tile2D bt = default_tile2d(L);
+  int rc = TVPD_OK;
+  for (int th : ths) {
+    if (th > L.ny && th != ths[0]) break;
+    for (int w : wpbs) {
+      for (int order = 0; order < 2; ++order) {
+        Tile2D t;
+        t.th = th;
+        t.wpb = w;
+        t.order = order;
+        float us = 0.0f;
+        rc = time_tile(L, t, ws, s, e0, e1, &us);
+        if (rc == TVPD_ERR_INVALID_ARG) {
+          rc = TVPD_OK;
+          continue;
+        }
+        if (rc) break;
+        if (us < bu) {
+          bu = us;
+          bt = t;
+        }
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  remember_tile2d(sh, bt);
+  *best = bt;
+  *best_us = bu;
+  return TVPD_OK;
+}
+
+// Cache file: one line per entry,
+//   <arch> <ndim> <nz> <ny> <nx> <th> <wpb> <order> <us>
+int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t,
+              float us) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return TVPD_ERR_INVALID_ARG;
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", device_arch().c_str(),
+               s.ndim, s.nz, s.ny, s.nx, t.th, t.wpb, t.order, us);
+  std::fclose(f);
+  return TVPD_OK;
+}
+
+int tune_load(const char* path, int* count) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return TVPD_ERR_INVALID_ARG;
+  const std::string arch = device_arch();
+  char line[512];
+  int n = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    char a[128];
+    tvpd_shape s;
+    Tile2D t;
+    float us;
+    if (std::sscanf(line, "%127s %d %d %d %d %d %d %d %f", a, &s.ndim, &s.nz,
+                    &s.ny, &s.nx, &t.th, &t.wpb, &t.order, &us) != 9)
+      continue;
+    if (arch != a) continue;
+    if (t.th < 1 || (t.wpb != 1 && t.wpb != 2 && t.wpb != 4) ||
+        (t.order != 0 && t.order != 1))
+      continue;
+    remember_tile2d(s, t);  // later lines override earlier ones
+    ++n;
+  }
+  std::fclose(f);
+  *count = n;
+  return TVPD_OK;
+}
+
+}  // namespace tvpd

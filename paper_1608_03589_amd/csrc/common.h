@@ -49,10 +49,15 @@ struct Layout {
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Tile configuration of the 2D sweep: each wave owns a strip of 256 columns
-// and `th` rows; a block holds `wpb` waves stacked vertically.
+// and a band of `th` rows; a block holds `wpb` consecutive wave tiles.
+// order 0 numbers tiles band by band (consecutive tiles are horizontally
+// adjacent strips: concurrent waves read long contiguous row segments);
+// order 1 numbers them strip by strip (consecutive tiles are vertically
+// adjacent bands).
 struct Tile2D {
   int th;
   int wpb;
+  int order;
 };
 
 // Arguments of the fused 2D sweep kernel (passed by value).
@@ -60,7 +65,7 @@ struct Sweep2DArgs {
   float* base;        // plane 0 of the workspace
   int64_t plane;      // floats per plane
   int32_t ny, nx, pitch;
-  int32_t th, wpb;
+  int32_t th, wpb, order;
   int32_t ntx, nty, ntiles;  // wave tiles: ntx strips by nty row bands
   float lam, tau, sigma, theta;
   DevState* st;
@@ -80,5 +85,14 @@ hipError_t launch_energy2d(const Layout& L, float lam, void* ws,
 hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
                              hipStream_t s);
 int sweep2d_blocks(const Layout& L, const Tile2D& t);
+
+// Tile table and autotuner (autotune.hip).
+Tile2D default_tile2d(const Layout& L);
+Tile2D tile2d_for(const Layout& L);
+void remember_tile2d(const tvpd_shape& s, const Tile2D& t);
+int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
+               Tile2D* best, float* best_us);
+int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t, float us);
+int tune_load(const char* path, int* count);
 
 }  // namespace tvpd

@@ -52,6 +52,34 @@ __device__ __forceinline__ F4 zero4() {
   return r;
 }
 
+// f^k and f^{k-1} of one row of a strip, with the strip's outer columns.
+struct RowF {
+  F4 f, m;
+  float lf, lm, rf, rm;
+};
+// p^k and g of one row of a strip, with p^k of the left outer column.
+struct RowP {
+  F4 px, py, g;
+  float lpx, lpy;
+};
+
+__device__ __forceinline__ RowF zeroF() {
+  RowF r;
+  r.f = zero4();
+  r.m = zero4();
+  r.lf = r.lm = r.rf = r.rm = 0.0f;
+  return r;
+}
+
+__device__ __forceinline__ RowP zeroP() {
+  RowP r;
+  r.px = zero4();
+  r.py = zero4();
+  r.g = zero4();
+  r.lpx = r.lpy = 0.0f;
+  return r;
+}
+
 // Projection of q onto the disc of radius lam; |q| <= lam keeps q.
 __device__ __forceinline__ void project2(float qx, float qy, float lam,
                                          float& px, float& py) {
@@ -194,7 +222,14 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
     float* pyn = pxn + PL;
     const float* g = a.base + 7 * PL;
 
-    const int tx = wt / a.nty, ty = wt - tx * a.nty;
+    int tx, ty;
+    if (a.order == 0) {
+      ty = wt / a.ntx;
+      tx = wt - ty * a.ntx;
+    } else {
+      tx = wt / a.nty;
+      ty = wt - tx * a.nty;
+    }
     const int x0 = tx * kStripCols;
     const int y0 = ty * a.th;
     const int y1 = min(y0 + a.th, a.ny);
@@ -208,65 +243,57 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
     const float lam = a.lam, tau = a.tau, sig = a.sigma, th = a.theta;
     const float opt = 1.0f + tau;
 
-    const int ys = y0 > 0 ? y0 - 1 : 0;
-    F4 cf = zero4(), cb = zero4();
-    float lf = 0.f, lb = 0.f, rf = 0.f, rb = 0.f;
-    {
-      const int64_t o = (int64_t)ys * P + xc;
-      if (lin) {
-        cf = ld4(fk + o);
-        const F4 m = ld4(fkm + o);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cb.v[j] = cf.v[j] + th * (cf.v[j] - m.v[j]);
-      }
-      if (hl) {
-        lf = fk[(int64_t)ys * P + xl];
-        lb = lf + th * (lf - fkm[(int64_t)ys * P + xl]);
-      }
-      if (hr) {
-        rf = fk[(int64_t)ys * P + xr];
-        rb = rf + th * (rf - fkm[(int64_t)ys * P + xr]);
-      }
-    }
+    // Row data.  In the steady state every lane issues every load (padding
+    // lanes and the edge columns read clamped, valid addresses; their values
+    // are masked out below), so the loads prefetched for the next row stay
+    // in flight while this row is computed.
+    const int xcl = min(xc, a.pitch - kColsPerLane);
+    const int xlc = max(xl, 0);
+    const int xrc = min(xr, a.pitch - 1);
+    auto loadF = [&](int y, RowF& r) {
+      const int64_t ro = (int64_t)y * P;
+      r.f = ld4(fk + ro + xcl);
+      r.m = ld4(fkm + ro + xcl);
+      r.lf = fk[ro + xlc];
+      r.lm = fkm[ro + xlc];
+      r.rf = fk[ro + xrc];
+      r.rm = fkm[ro + xrc];
+    };
+    auto loadP = [&](int y, RowP& r) {
+      const int64_t ro = (int64_t)y * P;
+      r.px = ld4(pxk + ro + xcl);
+      r.py = ld4(pyk + ro + xcl);
+      r.g = ld4(g + (int64_t)max(y, y0) * P + xcl);
+      r.lpx = pxk[ro + xlc];
+      r.lpy = pyk[ro + xlc];
+    };
+
     F4 up_pyn = zero4();  // p_y^{k+1} of the row above (0 above row 0)
     F4 up_pyo = zero4();  // p_y^k of the row above
 
-    for (int y = ys; y < y1; ++y) {
+    // Row y from `cur` (f of row y), `nxt` (f of row y+1, unused on the
+    // last image row) and `pc` (p, g of row y).
+    auto compute = [&](int y, const RowF& cur, const RowF& nxt,
+                       const RowP& pc) {
       const bool dn = (y + 1 < ny);
       const bool own = (y >= y0);
       const int64_t o = (int64_t)y * P + xc;
-      const int64_t ro = (int64_t)y * P;
-
-      F4 nf = cf, nb4 = cb;
-      float lnf = lf, lnb = lb, rnf = rf, rnb = rb;
-      if (dn) {
-        if (lin) {
-          nf = ld4(fk + o + P);
-          const F4 m = ld4(fkm + o + P);
+      const F4& cf = cur.f;
+      const F4& nf = nxt.f;
+      const F4& opx = pc.px;
+      const F4& opy = pc.py;
+      const F4& gg = pc.g;
+      // extrapolation of rows y and y+1 (and of the halo columns)
+      F4 cb, nb4;
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            nb4.v[j] = nf.v[j] + th * (nf.v[j] - m.v[j]);
-        }
-        if (hl) {
-          lnf = fk[ro + P + xl];
-          lnb = lnf + th * (lnf - fkm[ro + P + xl]);
-        }
-        if (hr) {
-          rnf = fk[ro + P + xr];
-          rnb = rnf + th * (rnf - fkm[ro + P + xr]);
-        }
+      for (int j = 0; j < 4; ++j) {
+        cb.v[j] = cur.f.v[j] + th * (cur.f.v[j] - cur.m.v[j]);
+        nb4.v[j] = nxt.f.v[j] + th * (nxt.f.v[j] - nxt.m.v[j]);
       }
-      F4 opx = zero4(), opy = zero4(), gg = zero4();
-      if (lin) {
-        opx = ld4(pxk + o);
-        opy = ld4(pyk + o);
-        if (own) gg = ld4(g + o);
-      }
-      float lpx = 0.f, lpy = 0.f;
-      if (hl) {
-        lpx = pxk[ro + xl];
-        lpy = pyk[ro + xl];
-      }
+      const float lb = cur.lf + th * (cur.lf - cur.lm);
+      const float rb = cur.rf + th * (cur.rf - cur.rm);
+      const float lnb = nxt.lf + th * (nxt.lf - nxt.lm);
+      const float rf = cur.rf;
 
       // dual ascent on the extrapolated gradient, then the projection
       F4 npx, npy;
@@ -290,9 +317,9 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
           const float gx = cb.v[0] - lb;
           const float gy = dn ? lnb - lb : 0.0f;
           float hx, hy;
-          project2(lpx + sig * gx, lpy + sig * gy, lam, hx, hy);
+          project2(pc.lpx + sig * gx, pc.lpy + sig * gy, lam, hx, hy);
           left_n = hx;
-          left_o = lpx;
+          left_o = pc.lpx;
         } else {
           left_n = 0.0f;
           left_o = 0.0f;
@@ -337,19 +364,52 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
           }
         } else {
           (void)rf;
+          (void)nf;
         }
       }
 
       up_pyn = npy;
       up_pyo = opy;
-      cf = nf;
-      cb = nb4;
-      lf = lnf;
-      lb = lnb;
-      rf = rnf;
-      rb = rnb;
+    };
+
+    const int ys = y0 > 0 ? y0 - 1 : 0;
+    // rows y < ymain have a next row in the band and a row y+2 in the image
+    const int ymain = min(y1 - 1, ny - 2);
+    RowF F0 = zeroF(), F1 = zeroF(), F2 = zeroF();
+    RowP Q0 = zeroP(), Q1 = zeroP(), Q2 = zeroP();
+    loadF(ys, F0);
+    if (ys + 1 < ny) loadF(ys + 1, F1);
+    loadP(ys, Q0);
+    int y = ys;
+    // steady state: whole groups of three rows, the row buffers rotating
+    // roles by name, so that no register copy has to wait on a load
+    const int ngroups = ymain > ys ? (ymain - ys) / 3 : 0;
+    for (int grp = 0; grp < ngroups; ++grp, y += 3) {
+      loadF(y + 2, F2);
+      loadP(y + 1, Q1);
+      compute(y, F0, F1, Q0);
+      loadF(y + 3, F0);
+      loadP(y + 2, Q2);
+      compute(y + 1, F1, F2, Q1);
+      loadF(y + 4, F1);
+      loadP(y + 3, Q0);
+      compute(y + 2, F2, F0, Q2);
     }
-    (void)lf;
+    RowF cur = F0, nxt = F1;
+    RowP pc = Q0;
+    // the remaining rows of the band (at most four)
+    for (; y < y1; ++y) {
+      RowF nn = zeroF();
+      RowP pn = zeroP();
+      if (y + 1 < y1) {
+        if (y + 2 < ny) loadF(y + 2, nn);
+        loadP(y + 1, pn);
+      }
+      compute(y, cur, nxt, pc);
+      cur = nxt;
+      nxt = nn;
+      pc = pn;
+    }
   }
   finish_sweep<GAP>(st, a.partials, k, acc_gap, acc_P);
 }
@@ -519,6 +579,7 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   a.pitch = L.pitch;
   a.th = t.th;
   a.wpb = t.wpb;
+  a.order = t.order;
   a.ntx = (L.nx + kStripCols - 1) / kStripCols;
   a.nty = (L.ny + t.th - 1) / t.th;
   a.ntiles = a.ntx * a.nty;

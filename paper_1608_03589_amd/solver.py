@@ -155,16 +155,44 @@ class PlainSolver:
                       float(s if sigma is None else sigma), float(theta))
 
 
-def set_tile(shape, th: int, wpb: int = 4):
-    """Force the 2D sweep tile for ``shape`` (rows per wave band, waves per
-    block) in this process."""
-    call("tvpd_set_tile", C.byref(make_shape(shape)), int(th), int(wpb))
+def set_tile(shape, th: int, wpb: int = 4, order: int = 1):
+    """Force the 2D sweep tile for ``shape`` in this process: rows per wave
+    band, waves per block, tile order (0 band by band, 1 strip by strip)."""
+    call("tvpd_set_tile", C.byref(make_shape(shape)), int(th), int(wpb),
+         int(order))
 
 
 def get_tile(shape):
-    th, wpb = C.c_int32(), C.c_int32()
-    call("tvpd_get_tile", C.byref(make_shape(shape)), C.byref(th), C.byref(wpb))
-    return th.value, wpb.value
+    th, wpb, order = C.c_int32(), C.c_int32(), C.c_int32()
+    call("tvpd_get_tile", C.byref(make_shape(shape)), C.byref(th),
+         C.byref(wpb), C.byref(order))
+    return th.value, wpb.value, order.value
+
+
+def autotune(shape, device="cuda", cache_path: str | None = None,
+             g: torch.Tensor | None = None):
+    """Time the candidate sweep tiles for ``shape`` and keep the fastest for
+    this process (optionally appending it to ``cache_path``).  Returns
+    ``((th, wpb, order), microseconds_per_sweep)``."""
+    s = PlainSolver(shape, device)
+    if g is None:
+        g = torch.rand(s.shape, dtype=torch.float32, device=s.device)
+    s.init(g)
+    th, wpb, order = C.c_int32(), C.c_int32(), C.c_int32()
+    us = C.c_float()
+    call("tvpd_autotune", C.byref(s.cshape), C.c_void_p(s.ws.data_ptr()),
+         s.nbytes, cache_path.encode() if cache_path else None, C.byref(th),
+         C.byref(wpb), C.byref(order), C.byref(us),
+         C.c_void_p(_stream(s.device)))
+    return (th.value, wpb.value, order.value), us.value
+
+
+def tune_load(cache_path: str) -> int:
+    """Load autotuned tiles for this device's architecture from a cache
+    file; returns how many entries were taken."""
+    n = C.c_int32()
+    call("tvpd_tune_load", cache_path.encode(), C.byref(n))
+    return n.value
 
 
 def solve(g: torch.Tensor, lam: float = 0.1, **kw):

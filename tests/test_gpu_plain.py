@@ -58,9 +58,9 @@ def test_parity_denoise_256_1000_iterations():
 
 
 @pytest.mark.parametrize("shape,tile", [
-    ((1, 1), None), ((1, 7), None), ((7, 1), None), ((5, 3), (2, 1)),
-    ((37, 301), (3, 2)), ((130, 513), (7, 4)), ((300, 260), (64, 1)),
-    ((64, 1029), (5, 4)), ((2, 2), (1, 1)),
+    ((1, 1), None), ((1, 7), None), ((7, 1), None), ((5, 3), (2, 1, 1)),
+    ((37, 301), (3, 2, 0)), ((130, 513), (7, 4, 1)), ((300, 260), (64, 1, 0)),
+    ((64, 1029), (5, 4, 0)), ((2, 2), (1, 1, 1)), ((41, 1100), (4, 2, 1)),
 ])
 def test_parity_ragged_shapes(shape, tile):
     print(f"case: ragged {shape} tile {tile}", flush=True)
@@ -81,7 +81,8 @@ def test_tile_invariance_bitwise():
     shape = (300, 517)
     g32 = scene32(*shape, 10, 0.1, 77)
     outs = []
-    for tile in [(1, 1), (3, 2), (8, 4), (64, 4), (300, 1)]:
+    for tile in [(1, 1, 1), (3, 2, 0), (8, 4, 1), (64, 4, 0), (300, 1, 1),
+                 (7, 2, 0)]:
         print(f"case: tile {tile}", flush=True)
         f, p, _ = gpu_fixed(g32, 40, 0.1, tile)
         outs.append((f, p))
@@ -183,7 +184,7 @@ def test_full_size_4096_sampled_windows():
     N = 12
     print(f"case: 4096 sampled windows, tile {tv.get_tile(g32.shape)}", flush=True)
     f, p, _ = gpu_fixed(g32, N, w["lam"])
-    th, _ = tv.get_tile(g32.shape)
+    th = tv.get_tile(g32.shape)[0]
     H, W = g32.shape
     rng = np.random.default_rng(7)
     centres = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, 255),
@@ -234,3 +235,19 @@ def test_full_size_4096_properties():
                                    float(np.float32(w["lam"])))
     assert abs(res.primal - Pr) <= 1e-9 * Pr
     assert abs(res.gap - gr) <= 1e-9 * Pr
+
+
+def test_autotune_choice_and_cache_roundtrip(tmp_path):
+    shape = (512, 700)
+    cache = str(tmp_path / "tiles.txt")
+    print("case: autotune 512x700", flush=True)
+    (th, wpb, order), us = tv.autotune(shape, DEV, cache)
+    assert us > 0 and th >= 1 and wpb in (1, 2, 4) and order in (0, 1)
+    assert tv.get_tile(shape) == (th, wpb, order)
+    tv.set_tile(shape, 5, 1, 1)
+    assert tv.tune_load(cache) == 1
+    assert tv.get_tile(shape) == (th, wpb, order)
+    g32 = scene32(*shape, 12, 0.1, 81)
+    f, _, _ = gpu_fixed(g32, 30, 0.1)
+    f_ref, _, _ = oracle.run_fixed(g32.astype(np.float64), 0.1, S2, S2, 30)
+    assert rel(f, f_ref) <= RTOL
