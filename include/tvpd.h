@@ -181,6 +181,55 @@ int tvpd_autotune(const tvpd_shape* shape, void* ws, size_t ws_bytes,
  * *count (host) receives the number of entries taken. */
 int tvpd_tune_load(const char* cache_path, int32_t* count);
 
+/* ---------------------------------------------------------------------
+ * Batched solver: n images of different sizes (2D), each solved exactly as
+ * tvpd_solve would solve it alone -- same iterates, same stopping iteration
+ * -- but together on the device.  Images are packed in caller-owned arenas:
+ * image i occupies ny_i * nx_i floats starting at element offsets[i] of both
+ * g_arena (input) and f_arena (output).
+ * ------------------------------------------------------------------- */
+
+/* Driver and tiling of a batched solve.  mode 0: one persistent cooperative
+ * launch runs every iteration (grid barriers between iterations, per-image
+ * stopping on the device); mode 1: one launch per iteration, replayed from
+ * HIP graphs of check_every iterations with the host polling a flag; mode 2:
+ * plain launches, one per iteration (reference driver).  th: rows per wave
+ * band (0 = the autotuned or default value); wpb: waves per block (0 =
+ * autotuned or default, else 1, 2 or 4). */
+typedef struct tvpd_batch_opts {
+  int32_t mode;
+  int32_t th;
+  int32_t wpb;
+  int32_t reserved;
+} tvpd_batch_opts;
+
+/* Workspace bytes for a batch of n shapes (host arrays; ndim must be 2). */
+int tvpd_batch_workspace_size(int32_t n, const tvpd_shape* shapes,
+                              size_t* bytes);
+
+/* Solve n images.  shapes, offsets (element offsets into the arenas), prm
+ * (one tvpd_params per image; max_iter and check_every must agree) and res
+ * (n results) are host arrays; g_arena, f_arena and ws are device memory.
+ * opts may be NULL (mode 0, autotuned tiles).  Synchronises the stream.
+ * TVPD_ERR_DEVICE: a grid barrier of the persistent driver timed out (the
+ * grid could not be made co-resident); results are then invalid. */
+int tvpd_solve_batched(int32_t n, const tvpd_shape* shapes,
+                       const int64_t* offsets, const float* g_arena,
+                       float* f_arena, const tvpd_params* prm,
+                       const tvpd_batch_opts* opts, void* ws, size_t ws_bytes,
+                       tvpd_result* res, void* stream);
+
+/* Batch tile autotuner: times 30 iterations of the persistent driver on this
+ * batch for th in {8, 16, 32, 64, 128} and wpb in {1, 2, 4}, and makes the
+ * fastest the default of later batched solves in this process.  f_arena is
+ * overwritten.  Outputs (host, may be NULL): th, wpb, milliseconds of the
+ * 30 iterations.  Synchronises the stream. */
+int tvpd_batch_autotune(int32_t n, const tvpd_shape* shapes,
+                        const int64_t* offsets, const float* g_arena,
+                        float* f_arena, const tvpd_params* prm, void* ws,
+                        size_t ws_bytes, int32_t* th, int32_t* wpb,
+                        float* ms, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

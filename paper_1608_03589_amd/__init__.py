@@ -7,13 +7,15 @@ The compute path is ``libtvpd.so`` (HIP, gfx950) behind the C ABI in
 memory and streams through PyTorch.
 """
 from ._lib import TVPDError, lib  # noqa: F401
+from .batch import BatchedSolver  # noqa: F401
 from .solver import (  # noqa: F401
     PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
     get_tile, make_shape, set_tile, solve, tune_load, workspace_size,
 )
 
 __all__ = [
-    "PlainSolver", "SolveResult", "TVPDError", "alloc_workspace", "autotune",
+    "BatchedSolver", "PlainSolver", "SolveResult", "TVPDError",
+    "alloc_workspace", "autotune",
     "tune_load",
     "default_step", "get_tile", "lib", "make_shape", "set_tile", "solve",
     "workspace_size",

@@ -35,6 +35,11 @@ class Params(C.Structure):
                 ("use_graph", C.c_int32), ("reserved", C.c_int32)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("th", C.c_int32), ("wpb", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32),
                 ("primal", C.c_double), ("dual", C.c_double),
@@ -72,6 +77,14 @@ SIGNATURES = {
                                 C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                                 C.POINTER(C.c_float), _P]),
     "tvpd_tune_load": (C.c_int, [C.c_char_p, C.POINTER(_I32)]),
+    "tvpd_batch_workspace_size": (C.c_int, [_I32, C.POINTER(Shape), C.POINTER(_SZ)]),
+    "tvpd_solve_batched": (C.c_int, [_I32, C.POINTER(Shape), C.POINTER(C.c_int64),
+                                     _P, _P, C.POINTER(Params), C.POINTER(BatchOpts),
+                                     _P, _SZ, C.POINTER(Result), _P]),
+    "tvpd_batch_autotune": (C.c_int, [_I32, C.POINTER(Shape), C.POINTER(C.c_int64),
+                                      _P, _P, C.POINTER(Params), _P, _SZ,
+                                      C.POINTER(_I32), C.POINTER(_I32),
+                                      C.POINTER(C.c_float), _P]),
 }
 
 _lib = None

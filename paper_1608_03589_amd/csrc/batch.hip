@@ -1,0 +1,344 @@
+// Batched solver: many 2D images of different sizes solved together, each
+// exactly as the plain solver would solve it alone (same per-pixel
+// arithmetic, same stopping rule, its own stopping iteration).
+//
+// All images live in one arena; a tile table lists every (image, strip,
+// band) tile, and an active list holds the tiles of the images that have not
+// stopped.  All running images are at the same iteration k, so the ring
+// slots are shared; an image that stops at k keeps f^k and p^k in the slots
+// of k and is never touched again.
+//
+// Two drivers share the tile code:
+//  - persistent: one cooperative launch runs every iteration; waves take
+//    active tiles grid-stride, a grid barrier separates iterations, and on
+//    check iterations the blocks reduce the per-image gaps, stop images and
+//    rebuild the active list;
+//  - graph blocks: one launch per iteration over the active list, the last
+//    block to finish doing the per-image bookkeeping; launches are replayed
+//    from HIP graphs of check_every iterations.
+#include "batch.h"
+#include "tile2d.h"
+
+namespace tvpd {
+namespace {
+
+using namespace dev;
+
+constexpr long kSpinLimit = 1L << 24;  // ~1 s of s_sleep before giving up
+
+__device__ __forceinline__ int load_i32(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for a co-resident grid.  Every wait is bounded: after
+// kSpinLimit polls the barrier flags an error and every block leaves.
+__device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned g = gen;
+    int ok = 1;
+    const unsigned arrived = atomicAdd(&h->bar_count, 1u);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&h->bar_count, 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&h->bar_gen, 1u);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(&h->bar_gen, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > kSpinLimit) {
+          atomicOr(&h->flags, kBatchErrBarrier);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+    gen = g + 1;
+    s_ok = ok && !(load_i32(&h->flags) & kBatchErrBarrier);
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+__device__ __forceinline__ void tile_ctx(const BatchArgs& a, int t, int k,
+                                         TileCtx& c) {
+  const TileDesc T = a.tiles[t];
+  const ImgDesc& D = a.imgs[T.img];
+  ring2d(a.arena + D.off, D.plane, k, c);
+  c.ny = D.ny;
+  c.nx = D.nx;
+  c.pitch = D.pitch;
+  c.x0 = T.x0;
+  c.y0 = T.y0;
+  c.y1 = T.y1;
+  c.lam = D.lam;
+  c.tau = D.tau;
+  c.sig = D.sigma;
+  c.th = D.theta;
+}
+
+// Sweep one tile; on check iterations lane 0 stores the tile's partials.
+__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
+                                        bool check) {
+  TileCtx c;
+  tile_ctx(a, t, k, c);
+  if (check) {
+    double sg = 0.0, sp = 0.0;
+    sweep_tile<true>(c, sg, sp);
+    sg = wave_sum(sg);
+    sp = wave_sum(sp);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      store_agent(&a.partials[2 * t], sg);
+      store_agent(&a.partials[2 * t + 1], sp);
+    }
+  } else {
+    double sg = 0.0, sp = 0.0;
+    sweep_tile<false>(c, sg, sp);
+  }
+}
+
+// Reduce the gap partials of image i in a fixed order (whole block) and
+// apply the stopping rule; thread 0 updates the image state.
+__device__ void reduce_image(const BatchArgs& a, int i, int k,
+                             double (*red)[kMaxBlock / kWave]) {
+  const ImgDesc& D = a.imgs[i];
+  double sg = 0.0, sp = 0.0;
+  for (int j = threadIdx.x; j < D.tile_count; j += blockDim.x) {
+    sg += load_agent(&a.partials[2 * (D.tile_first + j)]);
+    sp += load_agent(&a.partials[2 * (D.tile_first + j) + 1]);
+  }
+  block_sum2(sg, sp, red);
+  if (threadIdx.x == 0) {
+    ImgState& S = a.state[i];
+    S.gap = sg;
+    S.P = sp;
+    S.D = sp - sg;
+    if (D.tol >= 0.0 && sg <= D.tol * sp) {
+      S.converged = 1;
+      S.iters = k;
+    }
+  }
+  __syncthreads();
+}
+
+// Rebuild the active tile list from the images that still run (one block).
+__device__ void compact_active(const BatchArgs& a) {
+  __shared__ int s_pos;
+  if (threadIdx.x == 0) s_pos = 0;
+  __syncthreads();
+  for (int i = 0; i < a.nimg; ++i) {
+    const ImgDesc& D = a.imgs[i];
+    const int conv = a.state[i].converged;
+    const int pos = s_pos;
+    if (!conv)
+      for (int j = threadIdx.x; j < D.tile_count; j += blockDim.x)
+        a.active[pos + j] = D.tile_first + j;
+    __syncthreads();
+    if (threadIdx.x == 0 && !conv) s_pos = pos + D.tile_count;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(&a.hdr->n_active, s_pos, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
+    BatchArgs a) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  BatchHdr* h = a.hdr;
+  unsigned gen = __hip_atomic_load(&h->bar_gen, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+  const int wave = threadIdx.x / kWave;
+  const int nw = gridDim.x * a.wpb;
+  const int gw = blockIdx.x * a.wpb + wave;
+  int k = 0;
+  for (; k < a.max_iter; ++k) {
+    const bool check = a.check_every > 0 && (k % a.check_every) == 0;
+    const int nact = load_i32(&h->n_active);
+    if (nact == 0) break;
+    if (wave < a.wpb)
+      for (int idx = gw; idx < nact; idx += nw)
+        do_tile(a, a.active[idx], k, check);
+    if (!grid_barrier(h, gen)) return;
+    if (check) {
+      for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
+        if (!a.state[i].converged) reduce_image(a, i, k, red);
+      if (!grid_barrier(h, gen)) return;
+      if (blockIdx.x == 0) compact_active(a);
+      if (!grid_barrier(h, gen)) return;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) h->k = k;
+}
+
+// One iteration over the active list (graph-block driver).  The last block
+// to finish advances k and, on check iterations, reduces every running
+// image, stops the converged ones and rebuilds the active list.
+template <bool CHECK>
+__global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  __shared__ int s_last;
+  BatchHdr* h = a.hdr;
+  const int k = h->k;
+  if (k >= a.max_iter) return;
+  const int nact = h->n_active;
+  if (nact == 0) return;
+  const int wave = threadIdx.x / kWave;
+  const int nw = gridDim.x * a.wpb;
+  const int gw = blockIdx.x * a.wpb + wave;
+  if (wave < a.wpb)
+    for (int idx = gw; idx < nact; idx += nw)
+      do_tile(a, a.active[idx], k, CHECK);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&h->blocks_done, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (CHECK) {
+    for (int i = 0; i < a.nimg; ++i)
+      if (!a.state[i].converged) reduce_image(a, i, k, red);
+    compact_active(a);
+  }
+  if (threadIdx.x == 0) {
+    h->blocks_done = 0;
+    h->k = k + 1;
+  }
+}
+
+__global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
+                                  const int64_t* __restrict__ offs) {
+  const int i = blockIdx.y;
+  const ImgDesc& D = a.imgs[i];
+  float* base = a.arena + D.off;
+  const int64_t PL = D.plane;
+  const int64_t n = (int64_t)D.ny * D.pitch;
+  const float* gi = g + offs[i];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(e / D.pitch);
+    const int x = (int)(e - (int64_t)y * D.pitch);
+    const float v = (x < D.nx) ? gi[(int64_t)y * D.nx + x] : 0.0f;
+    base[e] = v;
+    base[PL + e] = 0.0f;
+    base[2 * PL + e] = v;
+    base[3 * PL + e] = 0.0f;
+    base[4 * PL + e] = 0.0f;
+    base[5 * PL + e] = 0.0f;
+    base[6 * PL + e] = 0.0f;
+    base[7 * PL + e] = v;
+  }
+}
+
+// Energies of the final pair of every image that did not stop (one block
+// per image), then the read-out of every image's returned iterate.
+__global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
+    BatchArgs a, float* __restrict__ f_out, const int64_t* __restrict__ offs) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  const int i = blockIdx.x;
+  const ImgDesc& D = a.imgs[i];
+  ImgState& S = a.state[i];
+  const int conv = S.converged;
+  const int k = conv ? S.iters : a.hdr->k;
+  const float* base = a.arena + D.off;
+  const int64_t PL = D.plane;
+  const float* f = base + (k % 3) * PL;
+  const float* px = base + (3 + 2 * (k & 1)) * PL;
+  const float* py = px + PL;
+  const float* g = base + 7 * PL;
+  const int64_t n = (int64_t)D.ny * D.nx;
+  const int P = D.pitch;
+  double sg = 0.0, sp = 0.0;
+  float* fo = f_out + offs[i];
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int y = (int)(e / D.nx);
+    const int x = (int)(e - (int64_t)y * D.nx);
+    const int64_t s = (int64_t)y * P + x;
+    fo[e] = f[s];
+    if (!conv) {
+      const double fv = f[s];
+      const double gx = (x < D.nx - 1) ? (double)f[s + 1] - fv : 0.0;
+      const double gy = (y < D.ny - 1) ? (double)f[s + P] - fv : 0.0;
+      const double dxl = (x > 0) ? (double)px[s - 1] : 0.0;
+      const double dyl = (y > 0) ? (double)py[s - P] : 0.0;
+      const double d = ((double)px[s] - dxl) + ((double)py[s] - dyl);
+      const double ee = fv - (double)g[s];
+      const double r = ee - d;
+      const double nrm = sqrt(gx * gx + gy * gy);
+      sg += 0.5 * r * r + (double)D.lam * nrm - (gx * px[s] + gy * py[s]);
+      sp += 0.5 * ee * ee + (double)D.lam * nrm;
+    }
+  }
+  block_sum2(sg, sp, red);
+  if (threadIdx.x == 0) {
+    if (!conv) {
+      S.gap = sg;
+      S.P = sp;
+      S.D = sp - sg;
+      S.iters = k;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_batch_init(const BatchArgs& a, const float* g,
+                             const int64_t* offs_dev, hipStream_t s) {
+  dim3 grid(64, a.nimg);
+  hipLaunchKernelGGL(batch_init_kernel, grid, dim3(256), 0, s, a, g, offs_dev);
+  return hipGetLastError();
+}
+
+int batch_persistent_grid(int wpb) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(batch_persistent_kernel),
+          wpb * kWave, 0) != hipSuccess)
+    return 0;
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipGetDeviceProperties(&p, dev) != hipSuccess)
+    return 0;
+  return per_cu * p.multiProcessorCount;
+}
+
+hipError_t launch_batch_persistent(const BatchArgs& a, int grid,
+                                   hipStream_t s) {
+  BatchArgs arg = a;
+  void* params[] = {&arg};
+  return hipLaunchCooperativeKernel(
+      reinterpret_cast<const void*>(batch_persistent_kernel), dim3(grid),
+      dim3(a.wpb * kWave), params, 0, s);
+}
+
+hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
+                              hipStream_t s) {
+  if (check)
+    hipLaunchKernelGGL(batch_sweep_kernel<true>, dim3(grid),
+                       dim3(a.wpb * kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL(batch_sweep_kernel<false>, dim3(grid),
+                       dim3(a.wpb * kWave), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_final(const BatchArgs& a, float* f_out,
+                              const int64_t* offs_dev, hipStream_t s) {
+  hipLaunchKernelGGL(batch_final_kernel, dim3(a.nimg), dim3(kMaxBlock), 0, s,
+                     a, f_out, offs_dev);
+  return hipGetLastError();
+}
+
+}  // namespace tvpd
