@@ -230,6 +230,47 @@ int tvpd_batch_autotune(int32_t n, const tvpd_shape* shapes,
                         size_t ws_bytes, int32_t* th, int32_t* wpb,
                         float* ms, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Unrolled (differentiable) solver.  `batch` images or volumes of one shape
+ * ([batch][ny][nx] or [batch][nz][ny][nx], dense) run K iterations of the
+ * method from f^0 = f^{-1} = g, p^0 = 0, each with its own coefficients
+ * (lam_k, tau_k, sigma_k) = coeffs[3k .. 3k+2] (device, float32, shared by
+ * the batch; theta fixed).  The output is f^K.  The backward call returns
+ * dL/dg and dL/dcoeffs for a given dL/df^K by the reverse-mode adjoint of
+ * the iteration (the derivative of the projection at |q| = lam is taken
+ * from the identity branch).
+ *
+ * Checkpointing: iterations are grouped in segments of ckpt_every; the
+ * forward keeps one checkpoint (f^s, f^{s-1}, p^s) per segment start and the
+ * states of the last segment; the backward recomputes each earlier segment
+ * from its checkpoint.  Memory grows like K/ckpt_every + ckpt_every state
+ * planes; ckpt_every >= K stores every iterate and recomputes nothing.
+ * ckpt_every must be >= 2 (or >= K).  No step-size check is made: the
+ * coefficients are the caller's (learnable) parameters.
+ * ------------------------------------------------------------------- */
+
+/* Workspace bytes of an unrolled forward/backward pair (host out). */
+int tvpd_unrolled_workspace_size(const tvpd_shape* shape, int32_t batch,
+                                 int32_t K, int32_t ckpt_every, size_t* bytes);
+
+/* Forward: g (device, dense) -> f_out = f^K (device, dense).  Leaves the
+ * checkpoints in ws for tvpd_unrolled_backward. */
+int tvpd_unrolled_forward(const tvpd_shape* shape, int32_t batch,
+                          const float* g, const float* coeffs, int32_t K,
+                          int32_t ckpt_every, float theta, float* f_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Backward: needs the workspace of a forward call with the same shape,
+ * batch, coeffs, K, ckpt_every and theta.  grad_f = dL/df^K (device, dense);
+ * outputs grad_g (device, dense, same shape as g) and grad_coeffs (device,
+ * float32 [K][3], summed over the batch).  The workspace's checkpoints stay
+ * valid, so the backward may be called again. */
+int tvpd_unrolled_backward(const tvpd_shape* shape, int32_t batch,
+                           const float* coeffs, int32_t K, int32_t ckpt_every,
+                           float theta, const float* grad_f, float* grad_g,
+                           float* grad_coeffs, void* ws, size_t ws_bytes,
+                           void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,9 @@ memory and streams through PyTorch.
 """
 from ._lib import TVPDError, lib  # noqa: F401
 from .batch import BatchedSolver  # noqa: F401
+from .unrolled import (  # noqa: F401
+    UnrolledSolver, UnrolledTV, default_coeffs, unrolled_tv,
+)
 from .solver import (  # noqa: F401
     PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
     get_tile, make_shape, set_tile, solve, tune_load, workspace_size,
@@ -15,6 +18,7 @@ from .solver import (  # noqa: F401
 
 __all__ = [
     "BatchedSolver", "PlainSolver", "SolveResult", "TVPDError",
+    "UnrolledSolver", "UnrolledTV", "default_coeffs", "unrolled_tv",
     "alloc_workspace", "autotune",
     "tune_load",
     "default_step", "get_tile", "lib", "make_shape", "set_tile", "solve",

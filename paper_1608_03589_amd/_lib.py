@@ -77,6 +77,12 @@ SIGNATURES = {
                                 C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                                 C.POINTER(C.c_float), _P]),
     "tvpd_tune_load": (C.c_int, [C.c_char_p, C.POINTER(_I32)]),
+    "tvpd_unrolled_workspace_size": (C.c_int, [C.POINTER(Shape), _I32, _I32, _I32,
+                                               C.POINTER(_SZ)]),
+    "tvpd_unrolled_forward": (C.c_int, [C.POINTER(Shape), _I32, _P, _P, _I32, _I32, _F,
+                                        _P, _P, _SZ, _P]),
+    "tvpd_unrolled_backward": (C.c_int, [C.POINTER(Shape), _I32, _P, _I32, _I32, _F,
+                                         _P, _P, _P, _P, _SZ, _P]),
     "tvpd_batch_workspace_size": (C.c_int, [_I32, C.POINTER(Shape), C.POINTER(_SZ)]),
     "tvpd_solve_batched": (C.c_int, [_I32, C.POINTER(Shape), C.POINTER(C.c_int64),
                                      _P, _P, C.POINTER(Params), C.POINTER(BatchOpts),

@@ -1,0 +1,486 @@
+// Kernels of the unrolled solver and of its hand-written adjoint.
+//
+// Forward step k (coefficients c_k = (lam_k, tau_k, sigma_k) read from device
+// memory, theta fixed):
+//     fbar    = f^k + theta (f^k - f^{k-1})
+//     p^{k+1} = P_lam(p^k + sigma grad fbar)
+//     f^{k+1} = (f^k + tau div p^{k+1} + tau g) / (1 + tau)
+// 2D images use the fused tile sweep (tile2d.h); 3D volumes use two passes,
+// a forward-difference pass writing p^{k+1} and a backward-difference pass
+// writing f^{k+1}.
+//
+// Adjoint step k (reverse-mode derivative of the forward step; a = dL/df^{k+1},
+// b = the part of dL/df^k collected from step k+1's extrapolation, r =
+// dL/dp^{k+1}), in two passes that recompute the forward quantities with the
+// forward's exact arithmetic, so the projection takes the same branch:
+//   pass A (forward differences):  alpha = a / (1 + tau);
+//       s = r - grad(tau alpha);  q = p^k + sigma grad fbar;  p^{k+1} = P(q);
+//       t = s where |q| <= lam, else (lam/|q|)(s - n (n.s)) with n = q/|q|;
+//       partial sums of  lambar = sum_{|q|>lam} n.s  and  sigmabar = sum t.grad fbar
+//   pass B (backward differences):  d = div p^{k+1};  f^{k+1} recomputed;
+//       gbar += tau alpha;  taubar = sum alpha (d + g - f^{k+1});
+//       w = -sigma div t;  a' = alpha + b + (1 + theta) w;  b' = -theta w;  r' = t.
+// After step 0, dL/dg = gbar + a + b (f^0 = f^{-1} = g).
+//
+// Per-pixel kernels run one pixel per thread, rows of up to 256 pixels per
+// block; neighbour values are read directly (they are cache hits).
+#include "tile2d.h"
+#include "unrolled.h"
+
+namespace tvpd {
+namespace {
+
+using namespace dev;
+
+constexpr int kRowBlock = 256;
+
+struct Pix {
+  int b, z, y, x;
+  int64_t o;   // offset within the image plane
+  bool ok;
+};
+
+__device__ __forceinline__ Pix pixel_of(const PlaneSet& P) {
+  Pix q;
+  const int xc = (P.nx + kRowBlock - 1) / kRowBlock;
+  const int64_t blk = blockIdx.x;
+  const int64_t row = blk / xc;
+  const int xchunk = (int)(blk - row * xc);
+  q.x = xchunk * kRowBlock + threadIdx.x;
+  const int64_t per = (int64_t)P.nz * P.ny;
+  q.b = (int)(row / per);
+  const int64_t rem = row - (int64_t)q.b * per;
+  q.z = (int)(rem / P.ny);
+  q.y = (int)(rem - (int64_t)q.z * P.ny);
+  q.ok = q.x < P.nx && q.b < P.nb;
+  q.o = ((int64_t)q.z * P.ny + q.y) * P.pitch + q.x;
+  return q;
+}
+
+__device__ __forceinline__ int64_t row_blocks(const PlaneSet& P) {
+  return (int64_t)((P.nx + kRowBlock - 1) / kRowBlock) * P.nb * P.nz * P.ny;
+}
+
+__device__ __forceinline__ const float* cplane(const PlaneSet& P, int b,
+                                               int id) {
+  return P.base + (int64_t)b * P.istride + (int64_t)id * P.plane;
+}
+__device__ __forceinline__ float* plane(const PlaneSet& P, int b, int id) {
+  return P.base + (int64_t)b * P.istride + (int64_t)id * P.plane;
+}
+
+template <int ND>
+__device__ __forceinline__ void project(const float* q, float lam, float* p) {
+  float n2 = q[0] * q[0] + q[1] * q[1];
+  if (ND == 3) n2 = n2 + q[2] * q[2];
+  const float n = sqrtf(n2);
+  if (n > lam) {
+    const float s = lam / n;
+#pragma unroll
+    for (int c = 0; c < ND; ++c) p[c] = q[c] * s;
+  } else {
+#pragma unroll
+    for (int c = 0; c < ND; ++c) p[c] = q[c];
+  }
+}
+
+// Strides along x, y, z of a pixel offset, and whether the pixel has a
+// forward neighbour along each axis.
+template <int ND>
+__device__ __forceinline__ void axes(const PlaneSet& P, const Pix& q,
+                                     int64_t* st, bool* fwd, bool* bwd) {
+  st[0] = 1;
+  st[1] = P.pitch;
+  fwd[0] = q.x < P.nx - 1;
+  fwd[1] = q.y < P.ny - 1;
+  bwd[0] = q.x > 0;
+  bwd[1] = q.y > 0;
+  if (ND == 3) {
+    st[2] = (int64_t)P.ny * P.pitch;
+    fwd[2] = q.z < P.nz - 1;
+    bwd[2] = q.z > 0;
+  }
+}
+
+// q = p^k + sigma grad fbar at one pixel (forward differences, Neumann).
+template <int ND>
+__device__ __forceinline__ void dual_point(const float* fk, const float* fkm,
+                                           const float* pk, int64_t PL,
+                                           int64_t o, const int64_t* st,
+                                           const bool* fwd, float sig,
+                                           float th, float* q, float* gfb) {
+  const float f0 = fk[o];
+  const float fb = f0 + th * (f0 - fkm[o]);
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    float gc = 0.0f;
+    if (fwd[c]) {
+      const float f1 = fk[o + st[c]];
+      const float fb1 = f1 + th * (f1 - fkm[o + st[c]]);
+      gc = fb1 - fb;
+    }
+    gfb[c] = gc;
+    q[c] = pk[c * PL + o] + sig * gc;
+  }
+}
+
+// div v at one pixel (backward differences; v_c vanishes at the last index)
+template <int ND>
+__device__ __forceinline__ float div_point(const float* v, int64_t PL,
+                                           int64_t o, const int64_t* st,
+                                           const bool* bwd) {
+  float d = 0.0f;
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    const float here = v[c * PL + o];
+    const float prev = bwd[c] ? v[c * PL + o - st[c]] : 0.0f;
+    d = (c == 0) ? (here - prev) : d + (here - prev);
+  }
+  return d;
+}
+
+// ----------------------------- forward ------------------------------------
+
+__global__ __launch_bounds__(kMaxBlock) void u_sweep2d_kernel(
+    PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k,
+    float theta, int th_rows, int wpb, int ntx, int nty) {
+  const int b = blockIdx.y;
+  const int wave = threadIdx.x / kWave;
+  const int nbx = gridDim.x, bx = blockIdx.x;
+  const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
+  const int wt = bt * wpb + wave;
+  if (wt >= ntx * nty) return;
+  const int ty = wt / ntx, tx = wt - ty * ntx;
+  TileCtx c;
+  c.fk = cplane(P, b, ids.fk);
+  c.fkm = cplane(P, b, ids.fkm);
+  c.pxk = cplane(P, b, ids.pk);
+  c.pyk = cplane(P, b, ids.pk + 1);
+  c.g = cplane(P, b, 0);
+  c.fn = plane(P, b, ids.fn);
+  c.pxn = plane(P, b, ids.pn);
+  c.pyn = plane(P, b, ids.pn + 1);
+  c.ny = P.ny;
+  c.nx = P.nx;
+  c.pitch = P.pitch;
+  c.x0 = tx * kStripCols;
+  c.y0 = ty * th_rows;
+  c.y1 = min(c.y0 + th_rows, P.ny);
+  c.lam = coeffs[3 * k];
+  c.tau = coeffs[3 * k + 1];
+  c.sig = coeffs[3 * k + 2];
+  c.th = theta;
+  double sg = 0.0, sp = 0.0;
+  sweep_tile<false>(c, sg, sp);
+}
+
+template <int ND>
+__global__ __launch_bounds__(kRowBlock) void u_dual_kernel(
+    PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k,
+    float theta) {
+  const Pix q = pixel_of(P);
+  if (!q.ok) return;
+  int64_t st[3];
+  bool fwd[3], bwd[3];
+  axes<ND>(P, q, st, fwd, bwd);
+  const float lam = coeffs[3 * k], sig = coeffs[3 * k + 2];
+  float qq[ND], gfb[ND], pn[ND];
+  dual_point<ND>(cplane(P, q.b, ids.fk), cplane(P, q.b, ids.fkm),
+                 cplane(P, q.b, ids.pk), P.plane, q.o, st, fwd, sig, theta,
+                 qq, gfb);
+  project<ND>(qq, lam, pn);
+  float* out = plane(P, q.b, ids.pn);
+#pragma unroll
+  for (int c = 0; c < ND; ++c) out[c * P.plane + q.o] = pn[c];
+}
+
+template <int ND>
+__global__ __launch_bounds__(kRowBlock) void u_primal_kernel(
+    PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k) {
+  const Pix q = pixel_of(P);
+  if (!q.ok) return;
+  int64_t st[3];
+  bool fwd[3], bwd[3];
+  axes<ND>(P, q, st, fwd, bwd);
+  const float tau = coeffs[3 * k + 1];
+  const float d = div_point<ND>(cplane(P, q.b, ids.pn), P.plane, q.o, st, bwd);
+  const float f = cplane(P, q.b, ids.fk)[q.o];
+  const float g = cplane(P, q.b, 0)[q.o];
+  const float v = f + tau * d;
+  plane(P, q.b, ids.fn)[q.o] = (v + tau * g) / (1.0f + tau);
+}
+
+// ----------------------------- adjoint ------------------------------------
+
+__device__ __forceinline__ void block_sum(double& a, double& b,
+                                          double (*red)[kMaxBlock / kWave]) {
+  block_sum2(a, b, red);
+}
+
+template <int ND>
+__global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
+    PlaneSet P, AdjIds ids, const float* __restrict__ coeffs, int k,
+    float theta, double* __restrict__ partials) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  const Pix q = pixel_of(P);
+  double lb = 0.0, sb = 0.0;
+  if (q.ok) {
+    int64_t st[3];
+    bool fwd[3], bwd[3];
+    axes<ND>(P, q, st, fwd, bwd);
+    const float lam = coeffs[3 * k], tau = coeffs[3 * k + 1],
+                sig = coeffs[3 * k + 2];
+    const float opt = 1.0f + tau;
+    const float* a = cplane(P, q.b, ids.a_in);
+    const float* r = cplane(P, q.b, ids.r_in);
+    const float ta0 = tau * (a[q.o] / opt);
+    float s[ND];
+#pragma unroll
+    for (int c = 0; c < ND; ++c) {
+      const float gc = fwd[c] ? tau * (a[q.o + st[c]] / opt) - ta0 : 0.0f;
+      s[c] = r[c * P.plane + q.o] - gc;
+    }
+    float qq[ND], gfb[ND], pn[ND];
+    dual_point<ND>(cplane(P, q.b, ids.fk), cplane(P, q.b, ids.fkm),
+                   cplane(P, q.b, ids.pk), P.plane, q.o, st, fwd, sig, theta,
+                   qq, gfb);
+    project<ND>(qq, lam, pn);
+    float n2 = qq[0] * qq[0] + qq[1] * qq[1];
+    if (ND == 3) n2 = n2 + qq[2] * qq[2];
+    const float nrm = sqrtf(n2);
+    float t[ND];
+    if (nrm > lam) {
+      float nv[ND];
+      float ns = 0.0f;
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+        nv[c] = qq[c] / nrm;
+        ns = (c == 0) ? nv[c] * s[c] : ns + nv[c] * s[c];
+      }
+      const float sc = lam / nrm;
+#pragma unroll
+      for (int c = 0; c < ND; ++c) t[c] = sc * (s[c] - nv[c] * ns);
+      lb = ns;
+    } else {
+#pragma unroll
+      for (int c = 0; c < ND; ++c) t[c] = s[c];
+    }
+    float* pno = plane(P, q.b, ids.pn);
+    float* to = plane(P, q.b, ids.t_out);
+#pragma unroll
+    for (int c = 0; c < ND; ++c) {
+      pno[c * P.plane + q.o] = pn[c];
+      to[c * P.plane + q.o] = t[c];
+      sb += (double)t[c] * (double)gfb[c];
+    }
+  }
+  block_sum(lb, sb, red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = lb;
+    partials[2 * blockIdx.x + 1] = sb;
+  }
+}
+
+template <int ND>
+__global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
+    PlaneSet P, AdjIds ids, const float* __restrict__ coeffs, int k,
+    float theta, double* __restrict__ partials) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  const Pix q = pixel_of(P);
+  double tb = 0.0, unused = 0.0;
+  if (q.ok) {
+    int64_t st[3];
+    bool fwd[3], bwd[3];
+    axes<ND>(P, q, st, fwd, bwd);
+    const float tau = coeffs[3 * k + 1], sig = coeffs[3 * k + 2];
+    const float opt = 1.0f + tau;
+    const float d =
+        div_point<ND>(cplane(P, q.b, ids.pn), P.plane, q.o, st, bwd);
+    const float f = cplane(P, q.b, ids.fk)[q.o];
+    const float g = cplane(P, q.b, ids.g)[q.o];
+    const float v = f + tau * d;
+    const float fn = (v + tau * g) / opt;
+    const float alpha = cplane(P, q.b, ids.a_in)[q.o] / opt;
+    float* gbar = plane(P, q.b, ids.gbar);
+    gbar[q.o] = gbar[q.o] + tau * alpha;
+    tb = (double)alpha * (((double)d + (double)g) - (double)fn);
+    const float dt =
+        div_point<ND>(cplane(P, q.b, ids.t_out), P.plane, q.o, st, bwd);
+    const float w = -sig * dt;
+    const float bb = cplane(P, q.b, ids.b_in)[q.o];
+    plane(P, q.b, ids.a_out)[q.o] = (alpha + bb) + (1.0f + theta) * w;
+    plane(P, q.b, ids.b_out)[q.o] = -theta * w;
+  }
+  block_sum(tb, unused, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tb;
+}
+
+// grad_coeffs[k] = (lambar, taubar, sigmabar) from the block partials of the
+// two adjoint passes, summed in a fixed order.
+__global__ __launch_bounds__(kMaxBlock) void u_coeff_reduce_kernel(
+    const double* __restrict__ pa, const double* __restrict__ pb, int nblk,
+    float* __restrict__ grad_coeffs, int k) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  double l = 0.0, s = 0.0, t = 0.0, unused = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    l += pa[2 * i];
+    s += pa[2 * i + 1];
+    t += pb[i];
+  }
+  block_sum2(l, s, red);
+  __syncthreads();
+  block_sum2(t, unused, red);
+  if (threadIdx.x == 0) {
+    grad_coeffs[3 * k] = (float)l;
+    grad_coeffs[3 * k + 1] = (float)t;
+    grad_coeffs[3 * k + 2] = (float)s;
+  }
+}
+
+// ------------------------------ plumbing ----------------------------------
+
+__global__ void u_init_kernel(PlaneSet P, const float* __restrict__ g,
+                              int id_g, int id_zero, int nzero) {
+  const Pix q = pixel_of(P);
+  if (!q.ok) return;
+  const int64_t dense = (((int64_t)q.b * P.nz + q.z) * P.ny + q.y) * P.nx + q.x;
+  plane(P, q.b, id_g)[q.o] = g[dense];
+  for (int i = 0; i < nzero; ++i) plane(P, q.b, id_zero + i)[q.o] = 0.0f;
+}
+
+__global__ void u_zero_pitch_kernel(PlaneSet P, int id, int n) {
+  // zero whole planes, padding included
+  const int64_t total = (int64_t)P.nb * n * P.plane;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / ((int64_t)n * P.plane);
+    const int64_t rem = e - b * n * P.plane;
+    P.base[b * P.istride + (int64_t)id * P.plane + rem] = 0.0f;
+  }
+}
+
+__global__ void u_read_kernel(PlaneSet P, int id, float* __restrict__ out) {
+  const Pix q = pixel_of(P);
+  if (!q.ok) return;
+  const int64_t dense = (((int64_t)q.b * P.nz + q.z) * P.ny + q.y) * P.nx + q.x;
+  out[dense] = cplane(P, q.b, id)[q.o];
+}
+
+__global__ void u_load_kernel(PlaneSet P, const float* __restrict__ in,
+                              int id) {
+  const Pix q = pixel_of(P);
+  if (!q.ok) return;
+  const int64_t dense = (((int64_t)q.b * P.nz + q.z) * P.ny + q.y) * P.nx + q.x;
+  plane(P, q.b, id)[q.o] = in[dense];
+}
+
+__global__ void u_final_grad_kernel(PlaneSet P, int gbar, int a, int b,
+                                    float* __restrict__ out) {
+  const Pix q = pixel_of(P);
+  if (!q.ok) return;
+  const int64_t dense = (((int64_t)q.b * P.nz + q.z) * P.ny + q.y) * P.nx + q.x;
+  out[dense] = cplane(P, q.b, gbar)[q.o] +
+               (cplane(P, q.b, a)[q.o] + cplane(P, q.b, b)[q.o]);
+}
+
+int64_t nrow_blocks(const PlaneSet& P) {
+  return (int64_t)((P.nx + kRowBlock - 1) / kRowBlock) * P.nb * P.nz * P.ny;
+}
+
+}  // namespace
+
+int64_t u_partials_needed(const PlaneSet& P) { return 3 * nrow_blocks(P) + 1; }
+
+hipError_t launch_u_init(const PlaneSet& P, const float* g, int id_g,
+                         int id_zero, int nzero, hipStream_t s) {
+  // zero every plane first so that padding columns hold zeros
+  hipLaunchKernelGGL(u_zero_pitch_kernel, dim3(4096), dim3(256), 0, s, P, 0,
+                     (int)(P.istride / P.plane));
+  hipLaunchKernelGGL(u_init_kernel, dim3((unsigned)nrow_blocks(P)),
+                     dim3(kRowBlock), 0, s, P, g, id_g, id_zero, nzero);
+  return hipGetLastError();
+}
+
+hipError_t launch_u_zero(const PlaneSet& P, int id, int n, hipStream_t s) {
+  hipLaunchKernelGGL(u_zero_pitch_kernel, dim3(4096), dim3(256), 0, s, P, id,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_u_step(const PlaneSet& P, const StepIds& ids,
+                         const float* coeffs, int k, float theta,
+                         hipStream_t s) {
+  if (P.ndim == 2) {
+    const int ntx = (P.nx + kStripCols - 1) / kStripCols;
+    Layout L;
+    L.ndim = 2;
+    L.nz = 1;
+    L.ny = P.ny;
+    L.nx = P.nx;
+    // bands tall enough for about one block of four waves per CU overall
+    int64_t th = ((int64_t)ntx * P.ny * P.nb + 1023) / 1024;
+    if (th < 8) th = 8;
+    if (th > 256) th = 256;
+    const int nty = (P.ny + (int)th - 1) / (int)th;
+    const int wpb = 4;
+    const int nbx = (ntx * nty + wpb - 1) / wpb;
+    hipLaunchKernelGGL(u_sweep2d_kernel, dim3(nbx, P.nb), dim3(wpb * kWave), 0,
+                       s, P, ids, coeffs, k, theta, (int)th, wpb, ntx, nty);
+  } else {
+    const dim3 grid((unsigned)nrow_blocks(P));
+    hipLaunchKernelGGL(u_dual_kernel<3>, grid, dim3(kRowBlock), 0, s, P, ids,
+                       coeffs, k, theta);
+    hipLaunchKernelGGL(u_primal_kernel<3>, grid, dim3(kRowBlock), 0, s, P, ids,
+                       coeffs, k);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_u_read(const PlaneSet& P, int id, float* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(u_read_kernel, dim3((unsigned)nrow_blocks(P)),
+                     dim3(kRowBlock), 0, s, P, id, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_u_load(const PlaneSet& P, const float* in, int id,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(u_load_kernel, dim3((unsigned)nrow_blocks(P)),
+                     dim3(kRowBlock), 0, s, P, in, id);
+  return hipGetLastError();
+}
+
+hipError_t launch_u_adjoint(const PlaneSet& P, const AdjIds& ids,
+                            const float* coeffs, int k, float theta,
+                            double* partials, int64_t max_partials,
+                            float* grad_coeffs, hipStream_t s) {
+  const int64_t nblk = nrow_blocks(P);
+  if (3 * nblk > max_partials) return hipErrorInvalidValue;
+  double* pa = partials;
+  double* pb = partials + 2 * nblk;
+  const dim3 grid((unsigned)nblk);
+  if (P.ndim == 2) {
+    hipLaunchKernelGGL(u_adjA_kernel<2>, grid, dim3(kRowBlock), 0, s, P, ids,
+                       coeffs, k, theta, pa);
+    hipLaunchKernelGGL(u_adjB_kernel<2>, grid, dim3(kRowBlock), 0, s, P, ids,
+                       coeffs, k, theta, pb);
+  } else {
+    hipLaunchKernelGGL(u_adjA_kernel<3>, grid, dim3(kRowBlock), 0, s, P, ids,
+                       coeffs, k, theta, pa);
+    hipLaunchKernelGGL(u_adjB_kernel<3>, grid, dim3(kRowBlock), 0, s, P, ids,
+                       coeffs, k, theta, pb);
+  }
+  hipLaunchKernelGGL(u_coeff_reduce_kernel, dim3(1), dim3(kMaxBlock), 0, s, pa,
+                     pb, (int)nblk, grad_coeffs, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_u_final_grad(const PlaneSet& P, int gbar, int a, int b,
+                               float* grad_g, hipStream_t s) {
+  hipLaunchKernelGGL(u_final_grad_kernel, dim3((unsigned)nrow_blocks(P)),
+                     dim3(kRowBlock), 0, s, P, gbar, a, b, grad_g);
+  return hipGetLastError();
+}
+
+}  // namespace tvpd
