@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 BYTES_PER_PIXEL_ITER = 32      # 20 B read + 12 B written per pixel and sweep
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_denoise4096_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1608_03589_amd", "csrc", "kernels2d.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1608_03589_amd", "csrc", f)
+               for f in ("kernels2d.hip", "tile2d.h")]
 
 
 def log(msg):
@@ -35,8 +36,11 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(pixels: int):
@@ -76,6 +80,149 @@ def cpu_baseline(g64, lam, s, budget_s=15.0, max_iter=30):
     return n, t
 
 
+def timed(fn, stream, reps=1):
+    """Run fn reps times between HIP events on `stream`; returns ms/rep."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    out = None
+    for _ in range(reps):
+        out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, out
+
+
+def bench_batched(dev):
+    """64 uneven images to relative gap 1e-4: one persistent launch, graph
+    blocks, and the plain solver looping over the images."""
+    import torch
+    import paper_1608_03589_amd as tv
+    from scenes import WORKLOADS, batch_scenes
+    w = WORKLOADS["batch64_uneven"]
+    data = batch_scenes(w["n"], w["seed"], w["n_shapes"])
+    imgs = [torch.from_numpy(d[1].astype(np.float32)).to(dev) for d in data]
+    stream = torch.cuda.current_stream(dev)
+    b = tv.BatchedSolver([tuple(i.shape) for i in imgs], dev)
+    b.pack(imgs)
+    tile, _ = b.autotune()
+    kw = dict(lam=w["lam"], max_iter=w["max_iter"], check_every=w["check_every"],
+              gap_tol=w["gap_tol"])
+    b.solve(None, mode="persistent", **kw)
+    ms_p, (_, res) = timed(lambda: b.solve(None, mode="persistent", **kw), stream, 3)
+    ms_g, (_, res_g) = timed(lambda: b.solve(None, mode="graph", **kw), stream, 2)
+    solvers = [tv.PlainSolver(tuple(i.shape), dev) for i in imgs]
+    outs = [torch.empty_like(i) for i in imgs]
+
+    def loop():
+        return [s.solve(i, out=o, **kw)[1] for s, i, o in zip(solvers, imgs, outs)]
+    loop()
+    ms_l, res_l = timed(loop, stream, 2)
+    work = sum(int(i.numel()) * r.iters for i, r in zip(imgs, res))
+    log(f"batched: persistent {ms_p:.1f} ms, graph {ms_g:.1f} ms, plain loop {ms_l:.1f} ms")
+    return {
+        "workload": "batch64_uneven",
+        "images": len(imgs),
+        "pixels": int(sum(int(i.numel()) for i in imgs)),
+        "pixel_iters": work,
+        "iters_min_max": [min(r.iters for r in res), max(r.iters for r in res)],
+        "all_converged": all(r.converged for r in res),
+        "max_rel_gap": max(r.rel_gap for r in res),
+        "tile": list(tile),
+        "persistent_ms": ms_p,
+        "graph_blocks_ms": ms_g,
+        "plain_loop_ms": ms_l,
+        "mpix_its_persistent": work / (ms_p * 1e-3) / 1e6,
+        "mpix_its_graph_blocks": work / (ms_g * 1e-3) / 1e6,
+        "mpix_its_plain_loop": work / (ms_l * 1e-3) / 1e6,
+        "effective_GBs_persistent": BYTES_PER_PIXEL_ITER * work / (ms_p * 1e-3) / 1e9,
+        "speedup_vs_plain_loop": ms_l / ms_p,
+        "same_iters_as_plain": all(a.iters == c.iters for a, c in zip(res, res_l)),
+    }
+
+
+def bench_unrolled_2d(dev, plain_mpix):
+    """32 x 512^2, K = 20 unrolled iterations: forward, and forward plus the
+    adjoint backward (store-all: ckpt_every = K)."""
+    import torch
+    import paper_1608_03589_amd as tv
+    from scenes import WORKLOADS, scene2d
+    w = WORKLOADS["unrolled_32x512"]
+    pairs = [scene2d(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"] + i)
+             for i in range(w["B"])]
+    g = torch.from_numpy(np.stack([p[1] for p in pairs]).astype(np.float32)).to(dev)
+    clean = torch.from_numpy(np.stack([p[0] for p in pairs]).astype(np.float32)).to(dev)
+    K = w["K"]
+    c = tv.default_coeffs(K, 2, 0.1, dev)
+    stream = torch.cuda.current_stream(dev)
+    s = tv.UnrolledSolver(tuple(g.shape), K, K, 1.0, dev)
+    f = s.forward(g, c)
+    grad_f = 2 * (f - clean) / f.numel()
+    s.backward(c, grad_f)
+    ms_f, _ = timed(lambda: s.forward(g, c), stream, 5)
+
+    def fb():
+        s.forward(g, c)
+        return s.backward(c, grad_f)
+    ms_fb, _ = timed(fb, stream, 5)
+    work = int(g.numel()) * K
+    log(f"unrolled 2d: fwd {ms_f:.2f} ms, fwd+bwd {ms_fb:.2f} ms")
+    return {
+        "workload": "unrolled_32x512",
+        "batch": w["B"], "image": [w["H"], w["W"]], "K": K, "ckpt_every": K,
+        "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb,
+        "mpix_its_fwd": work / (ms_f * 1e-3) / 1e6,
+        "mpix_its_fwd_bwd": work / (ms_fb * 1e-3) / 1e6,
+        "fwd_vs_plain_4096": work / (ms_f * 1e-3) / 1e6 / plain_mpix,
+        "fwd_bwd_vs_plain_4096": work / (ms_fb * 1e-3) / 1e6 / plain_mpix,
+    }
+
+
+def bench_unrolled_3d(dev):
+    """256^3, K = 100, checkpoint every 10: forward and forward + backward,
+    with the peak device memory."""
+    import torch
+    import paper_1608_03589_amd as tv
+    from scenes import WORKLOADS, scene3d
+    w = WORKLOADS["unrolled_256cube"]
+    clean, noisy = scene3d(w["D"], w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    g = torch.from_numpy(noisy[None].astype(np.float32)).to(dev)
+    cl = torch.from_numpy(clean[None].astype(np.float32)).to(dev)
+    del clean, noisy
+    K = w["K"]
+    c = tv.default_coeffs(K, 3, 0.1, dev)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    base = torch.cuda.memory_allocated(dev)
+    s = tv.UnrolledSolver(tuple(g.shape), K, w["ckpt_every"], 1.0, dev)
+    f = s.forward(g, c)
+    grad_f = 2 * (f - cl) / f.numel()
+    s.backward(c, grad_f)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated(dev)
+    ms_f, _ = timed(lambda: s.forward(g, c), stream, 2)
+
+    def fb():
+        s.forward(g, c)
+        return s.backward(c, grad_f)
+    ms_fb, _ = timed(fb, stream, 2)
+    work = int(g.numel()) * K
+    log(f"unrolled 3d: fwd {ms_f:.1f} ms, fwd+bwd {ms_fb:.1f} ms, peak {peak / 2**30:.2f} GiB")
+    return {
+        "workload": "unrolled_256cube",
+        "volume": [w["D"], w["H"], w["W"]], "K": K, "ckpt_every": w["ckpt_every"],
+        "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb,
+        "mvox_its_fwd": work / (ms_f * 1e-3) / 1e6,
+        "mvox_its_fwd_bwd": work / (ms_fb * 1e-3) / 1e6,
+        "peak_device_memory_GiB": peak / 2 ** 30,
+        "memory_before_GiB": base / 2 ** 30,
+        "workspace_GiB": s.nbytes / 2 ** 30,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +231,8 @@ def main():
     ap.add_argument("--iters", type=int, default=None,
                     help="iterations per step (default: the workload's 2000)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and unrolled workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size "
                          "(for scaling HBM counters)")
@@ -150,6 +299,12 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 5 copies of 256 MiB done")
 
+    extra = {}
+    if not args.no_extra:
+        extra["batched"] = bench_batched(dev)
+        extra["unrolled_2d"] = bench_unrolled_2d(dev, mpix_its)
+        extra["unrolled_3d"] = bench_unrolled_3d(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         n_cpu, t_cpu = cpu_baseline(g32.astype(np.float64), lam, s)
@@ -192,11 +347,14 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_vs_algorithmic": (traffic / alg_bytes) if traffic else None,
             "kernel": "sweep2d_kernel (fused sweep; 1 in 10 launches also reduces the gap)",
             "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": launch_s * 1e6,
         },
         "cpu_baseline": cpu,
+        **extra,
         "final_rel_gap": res.rel_gap if res else None,
         "wall_s": wall,
     }
