@@ -6,15 +6,15 @@
 namespace tvpd {
 
 constexpr int kBatchErrBarrier = 1;  // a grid barrier wait ran out
+constexpr int kBatchStopped = 2;     // an image stopped at the last check
 
 // Per-image description (device, read-only during a solve).
 struct ImgDesc {
   int64_t off;       // float offset of the image's plane block in the arena
   int64_t plane;     // floats per plane
   int32_t ny, nx, pitch;
-  int32_t tile_first, tile_count;
+  int32_t tile_first[2], tile_count[2];  // per tile table
   float lam, tau, sigma, theta;
-  int32_t pad;
   double tol;        // relative gap tolerance (< 0: never stop)
 };
 
@@ -31,14 +31,13 @@ struct TileDesc {
 };
 
 // Batch header at the workspace start (device).
+// Arrival counters and the barrier generation live in a SyncArea (sync.h)
+// at byte kSyncOffset of the header.
 struct BatchHdr {
   int32_t k;             // iteration of the running images
   int32_t n_active;      // entries of the active tile list
-  uint32_t bar_count;    // grid barrier arrivals
-  uint32_t bar_gen;      // grid barrier generation
-  uint32_t blocks_done;  // completion counter (graph-block driver)
   int32_t flags;         // error bits
-  int32_t pad[2];
+  int32_t table;         // tile table in use: 0 tall bands, 1 short bands
 };
 
 struct BatchArgs {
@@ -48,11 +47,15 @@ struct BatchArgs {
   const TileDesc* tiles;
   int32_t* active;
   double* partials;  // 2 per tile
+  double* fparts;    // 2 per (image, final block)
   float* arena;
   int32_t nimg, ntiles;
   int32_t max_iter, check_every;
   int32_t wpb;
+  int32_t switch_tiles;  // use short bands once fewer tall tiles are active
 };
+
+constexpr int kFinalBlocks = 32;  // blocks per image of the final pass
 
 hipError_t launch_batch_init(const BatchArgs& a, const float* g,
                              const int64_t* offs_dev, hipStream_t s);
@@ -63,5 +66,6 @@ hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
                               hipStream_t s);
 hipError_t launch_batch_final(const BatchArgs& a, float* f_out,
                               const int64_t* offs_dev, hipStream_t s);
+int batch_max_blocks_per_cu(int wpb);
 
 }  // namespace tvpd

@@ -17,6 +17,7 @@
 //    block to finish doing the per-image bookkeeping; launches are replayed
 //    from HIP graphs of check_every iterations.
 #include "batch.h"
+#include "sync.h"
 #include "tile2d.h"
 
 namespace tvpd {
@@ -30,26 +31,29 @@ __device__ __forceinline__ int load_i32(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier for a co-resident grid.  Every wait is bounded: after
+__device__ __forceinline__ SyncArea* sync_of(BatchHdr* h) {
+  return reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(h) + kSyncOffset);
+}
+
+// Grid-wide barrier for a co-resident grid (hierarchical arrival, one
+// generation word polled with a short sleep).  Every wait is bounded: after
 // kSpinLimit polls the barrier flags an error and every block leaves.
 __device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
+    SyncArea* sa = sync_of(h);
     __threadfence();
     const unsigned g = gen;
     int ok = 1;
-    const unsigned arrived = atomicAdd(&h->bar_count, 1u);
-    if (arrived == gridDim.x - 1) {
-      __hip_atomic_store(&h->bar_count, 0u, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    if (arrive_last(sa, gridDim.x)) {
       __threadfence();
-      atomicAdd(&h->bar_gen, 1u);
+      atomicAdd(&sa->gen.v, 1u);
     } else {
       long spins = 0;
-      while (__hip_atomic_load(&h->bar_gen, __ATOMIC_RELAXED,
+      while (__hip_atomic_load(&sa->gen.v, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(4);
         if (++spins > kSpinLimit) {
           atomicOr(&h->flags, kBatchErrBarrier);
           ok = 0;
@@ -103,14 +107,16 @@ __device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
 }
 
 // Reduce the gap partials of image i in a fixed order (whole block) and
-// apply the stopping rule; thread 0 updates the image state.
-__device__ void reduce_image(const BatchArgs& a, int i, int k,
+// apply the stopping rule; thread 0 updates the image state.  `tbl` is the
+// tile table the check iteration was swept with.
+__device__ void reduce_image(const BatchArgs& a, int i, int k, int tbl,
                              double (*red)[kMaxBlock / kWave]) {
   const ImgDesc& D = a.imgs[i];
+  const int first = D.tile_first[tbl], count = D.tile_count[tbl];
   double sg = 0.0, sp = 0.0;
-  for (int j = threadIdx.x; j < D.tile_count; j += blockDim.x) {
-    sg += load_agent(&a.partials[2 * (D.tile_first + j)]);
-    sp += load_agent(&a.partials[2 * (D.tile_first + j) + 1]);
+  for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    sg += load_agent(&a.partials[2 * (first + j)]);
+    sp += load_agent(&a.partials[2 * (first + j) + 1]);
   }
   block_sum2(sg, sp, red);
   if (threadIdx.x == 0) {
@@ -121,25 +127,43 @@ __device__ void reduce_image(const BatchArgs& a, int i, int k,
     if (D.tol >= 0.0 && sg <= D.tol * sp) {
       S.converged = 1;
       S.iters = k;
+      atomicOr(&a.hdr->flags, kBatchStopped);  // the active list must shrink
     }
   }
   __syncthreads();
 }
 
 // Rebuild the active tile list from the images that still run (one block).
+// Once fewer tall-band tiles than waves remain, switch for good to the
+// short-band table: the iterates do not depend on the tiling, and short
+// bands keep the GPU busy while only a few images are left.
 __device__ void compact_active(const BatchArgs& a) {
   __shared__ int s_pos;
-  if (threadIdx.x == 0) s_pos = 0;
+  __shared__ int s_tbl;
+  if (threadIdx.x == 0) {
+    int tbl = a.hdr->table;
+    if (tbl == 0) {
+      int n0 = 0;
+      for (int i = 0; i < a.nimg; ++i)
+        if (!a.state[i].converged) n0 += a.imgs[i].tile_count[0];
+      if (n0 < a.switch_tiles) tbl = 1;
+    }
+    a.hdr->table = tbl;
+    s_tbl = tbl;
+    s_pos = 0;
+  }
   __syncthreads();
+  const int tbl = s_tbl;
   for (int i = 0; i < a.nimg; ++i) {
     const ImgDesc& D = a.imgs[i];
     const int conv = a.state[i].converged;
     const int pos = s_pos;
+    const int first = D.tile_first[tbl], count = D.tile_count[tbl];
     if (!conv)
-      for (int j = threadIdx.x; j < D.tile_count; j += blockDim.x)
-        a.active[pos + j] = D.tile_first + j;
+      for (int j = threadIdx.x; j < count; j += blockDim.x)
+        a.active[pos + j] = first + j;
     __syncthreads();
-    if (threadIdx.x == 0 && !conv) s_pos = pos + D.tile_count;
+    if (threadIdx.x == 0 && !conv) s_pos = pos + count;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -154,7 +178,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
     BatchArgs a) {
   __shared__ double red[2][kMaxBlock / kWave];
   BatchHdr* h = a.hdr;
-  unsigned gen = __hip_atomic_load(&h->bar_gen, __ATOMIC_RELAXED,
+  unsigned gen = __hip_atomic_load(&sync_of(h)->gen.v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   const int wave = threadIdx.x / kWave;
   const int nw = gridDim.x * a.wpb;
@@ -169,11 +193,19 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
         do_tile(a, a.active[idx], k, check);
     if (!grid_barrier(h, gen)) return;
     if (check) {
+      const int tbl = load_i32(&h->table);
       for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
-        if (!a.state[i].converged) reduce_image(a, i, k, red);
+        if (!a.state[i].converged) reduce_image(a, i, k, tbl, red);
       if (!grid_barrier(h, gen)) return;
-      if (blockIdx.x == 0) compact_active(a);
-      if (!grid_barrier(h, gen)) return;
+      // rebuild the active list only when an image stopped at this check
+      if (load_i32(&h->flags) & kBatchStopped) {
+        if (!grid_barrier(h, gen)) return;  // every block has read the flag
+        if (blockIdx.x == 0) {
+          compact_active(a);
+          if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
+        }
+        if (!grid_barrier(h, gen)) return;
+      }
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) h->k = k;
@@ -200,21 +232,21 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
-    const unsigned prev = atomicAdd(&h->blocks_done, 1u);
-    s_last = (prev == gridDim.x - 1);
+    s_last = arrive_last(sync_of(h), gridDim.x) ? 1 : 0;
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
   if (CHECK) {
+    const int tbl = h->table;
     for (int i = 0; i < a.nimg; ++i)
-      if (!a.state[i].converged) reduce_image(a, i, k, red);
-    compact_active(a);
+      if (!a.state[i].converged) reduce_image(a, i, k, tbl, red);
+    if (load_i32(&h->flags) & kBatchStopped) {
+      compact_active(a);
+      if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
+    }
   }
-  if (threadIdx.x == 0) {
-    h->blocks_done = 0;
-    h->k = k + 1;
-  }
+  if (threadIdx.x == 0) h->k = k + 1;
 }
 
 __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
@@ -241,14 +273,15 @@ __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
   }
 }
 
-// Energies of the final pair of every image that did not stop (one block
-// per image), then the read-out of every image's returned iterate.
+// Energies of the final pair of every image that did not stop, and the
+// read-out of every image's returned iterate: kFinalBlocks blocks per image
+// write float64 partials, then one block per image sums them in order.
 __global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
     BatchArgs a, float* __restrict__ f_out, const int64_t* __restrict__ offs) {
   __shared__ double red[2][kMaxBlock / kWave];
-  const int i = blockIdx.x;
+  const int i = blockIdx.y;
   const ImgDesc& D = a.imgs[i];
-  ImgState& S = a.state[i];
+  const ImgState& S = a.state[i];
   const int conv = S.converged;
   const int k = conv ? S.iters : a.hdr->k;
   const float* base = a.arena + D.off;
@@ -261,7 +294,8 @@ __global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
   const int P = D.pitch;
   double sg = 0.0, sp = 0.0;
   float* fo = f_out + offs[i];
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
     const int y = (int)(e / D.nx);
     const int x = (int)(e - (int64_t)y * D.nx);
     const int64_t s = (int64_t)y * P + x;
@@ -282,13 +316,25 @@ __global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
   }
   block_sum2(sg, sp, red);
   if (threadIdx.x == 0) {
-    if (!conv) {
-      S.gap = sg;
-      S.P = sp;
-      S.D = sp - sg;
-      S.iters = k;
-    }
+    a.fparts[2 * (i * kFinalBlocks + blockIdx.x)] = sg;
+    a.fparts[2 * (i * kFinalBlocks + blockIdx.x) + 1] = sp;
   }
+}
+
+__global__ void batch_final_reduce_kernel(BatchArgs a) {
+  const int i = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  ImgState& S = a.state[i];
+  if (S.converged) return;
+  double sg = 0.0, sp = 0.0;
+  for (int b = 0; b < kFinalBlocks; ++b) {
+    sg += a.fparts[2 * (i * kFinalBlocks + b)];
+    sp += a.fparts[2 * (i * kFinalBlocks + b) + 1];
+  }
+  S.gap = sg;
+  S.P = sp;
+  S.D = sp - sg;
+  S.iters = a.hdr->k;
 }
 
 }  // namespace
@@ -336,9 +382,20 @@ hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
 
 hipError_t launch_batch_final(const BatchArgs& a, float* f_out,
                               const int64_t* offs_dev, hipStream_t s) {
-  hipLaunchKernelGGL(batch_final_kernel, dim3(a.nimg), dim3(kMaxBlock), 0, s,
-                     a, f_out, offs_dev);
+  hipLaunchKernelGGL(batch_final_kernel, dim3(kFinalBlocks, a.nimg),
+                     dim3(kMaxBlock), 0, s, a, f_out, offs_dev);
+  hipLaunchKernelGGL(batch_final_reduce_kernel, dim3(a.nimg), dim3(64), 0, s,
+                     a);
   return hipGetLastError();
+}
+
+int batch_max_blocks_per_cu(int wpb) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(batch_persistent_kernel),
+          wpb * kWave, 0) != hipSuccess)
+    return 0;
+  return per_cu;
 }
 
 }  // namespace tvpd

@@ -16,7 +16,7 @@ struct BatchLayout {
   int n;
   int64_t tmax;              // tile slots (enough for th = 1)
   size_t off_imgs, off_state, off_offs, off_tiles, off_active, off_part;
-  size_t off_arena;
+  size_t off_fpart, off_arena;
   size_t bytes;
   std::vector<int64_t> img_off;    // float offset of each plane block
   std::vector<int64_t> img_plane;  // floats per plane
@@ -47,7 +47,8 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
     L.img_plane.push_back(plane);
     L.img_off.push_back(arena);
     arena += 8 * plane;
-    L.tmax += (int64_t)((s[i].nx + kStripCols - 1) / kStripCols) * s[i].ny;
+    // both tile tables together hold at most two tiles per (strip, row)
+    L.tmax += 2 * (int64_t)((s[i].nx + kStripCols - 1) / kStripCols) * s[i].ny;
   }
   size_t o = kHeaderBytes;
   L.off_imgs = o;
@@ -62,6 +63,8 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
   o = align_up(o + L.tmax * sizeof(int32_t), kAlign);
   L.off_part = o;
   o = align_up(o + L.tmax * 2 * sizeof(double), kAlign);
+  L.off_fpart = o;
+  o = align_up(o + (size_t)n * kFinalBlocks * 2 * sizeof(double), kAlign);
   L.off_arena = o;
   L.bytes = o + (size_t)arena * sizeof(float);
   return L;
@@ -107,16 +110,37 @@ struct BatchSetup {
   int ntiles;
 };
 
+constexpr int kShortBand = 4;  // rows per band of the short-band table
+
 void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
                  const int64_t* offsets, const tvpd_params* prm, int th,
-                 int wpb, char* ws, BatchSetup& B) {
+                 int wpb, int nwaves, char* ws, BatchSetup& B) {
   B.host.assign(L.off_part, 0);
   char* h = B.host.data();
   ImgDesc* imgs = reinterpret_cast<ImgDesc*>(h + L.off_imgs);
   int64_t* offs = reinterpret_cast<int64_t*>(h + L.off_offs);
   TileDesc* tiles = reinterpret_cast<TileDesc*>(h + L.off_tiles);
   int32_t* active = reinterpret_cast<int32_t*>(h + L.off_active);
+  const int ths[2] = {th, std::min(th, kShortBand)};
   int t = 0;
+  for (int tbl = 0; tbl < 2; ++tbl) {
+    for (int i = 0; i < n; ++i) {
+      ImgDesc& D = imgs[i];
+      D.tile_first[tbl] = t;
+      const int ntx = (s[i].nx + kStripCols - 1) / kStripCols;
+      const int nty = (s[i].ny + ths[tbl] - 1) / ths[tbl];
+      for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) {
+          tiles[t].img = i;
+          tiles[t].x0 = tx * kStripCols;
+          tiles[t].y0 = ty * ths[tbl];
+          tiles[t].y1 = std::min((ty + 1) * ths[tbl], s[i].ny);
+          ++t;
+        }
+      D.tile_count[tbl] = t - D.tile_first[tbl];
+    }
+  }
+  int n0 = 0;
   for (int i = 0; i < n; ++i) {
     ImgDesc& D = imgs[i];
     D.off = L.img_off[i];
@@ -124,28 +148,23 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
     D.ny = s[i].ny;
     D.nx = s[i].nx;
     D.pitch = L.img_pitch[i];
-    D.tile_first = t;
     D.lam = prm[i].c.lam;
     D.tau = prm[i].c.tau;
     D.sigma = prm[i].c.sigma;
     D.theta = prm[i].c.theta;
     D.tol = prm[i].gap_tol;
     offs[i] = offsets[i];
-    const int ntx = (s[i].nx + kStripCols - 1) / kStripCols;
-    const int nty = (s[i].ny + th - 1) / th;
-    for (int ty = 0; ty < nty; ++ty)
-      for (int tx = 0; tx < ntx; ++tx) {
-        tiles[t].img = i;
-        tiles[t].x0 = tx * kStripCols;
-        tiles[t].y0 = ty * th;
-        tiles[t].y1 = std::min((ty + 1) * th, s[i].ny);
-        active[t] = t;
-        ++t;
-      }
-    D.tile_count = t - D.tile_first;
+    n0 += D.tile_count[0];
   }
+  // start on the short bands when the tall ones cannot fill the grid
+  const int tbl0 = n0 < nwaves ? 1 : 0;
+  int na = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < imgs[i].tile_count[tbl0]; ++j)
+      active[na++] = imgs[i].tile_first[tbl0] + j;
   BatchHdr* hdr = reinterpret_cast<BatchHdr*>(h);
-  hdr->n_active = t;
+  hdr->n_active = na;
+  hdr->table = tbl0;
   B.ntiles = t;
   BatchArgs& a = B.args;
   a.hdr = reinterpret_cast<BatchHdr*>(ws);
@@ -154,12 +173,14 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   a.tiles = reinterpret_cast<const TileDesc*>(ws + L.off_tiles);
   a.active = reinterpret_cast<int32_t*>(ws + L.off_active);
   a.partials = reinterpret_cast<double*>(ws + L.off_part);
+  a.fparts = reinterpret_cast<double*>(ws + L.off_fpart);
   a.arena = reinterpret_cast<float*>(ws + L.off_arena);
   a.nimg = n;
   a.ntiles = t;
   a.max_iter = prm[0].max_iter;
   a.check_every = prm[0].check_every;
   a.wpb = wpb;
+  a.switch_tiles = nwaves;
 }
 
 struct PinnedHdr {
@@ -253,31 +274,42 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
   if (!ws) return TVPD_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
   if (ws_bytes < L.bytes) return TVPD_ERR_WORKSPACE;
+  // grid of the driver: the persistent one is capped by co-residency
+  // grid of the driver: about two blocks per CU (the persistent one is also
+  // capped by co-residency); every block sweeps tiles grid-stride
+  int cus = 0;
+  {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipGetDeviceProperties(&p, dev) != hipSuccess)
+      return TVPD_ERR_HIP;
+    cus = p.multiProcessorCount;
+  }
+  int grid = 2 * cus;
+  if (mode == 0) {
+    const int cap = batch_persistent_grid(wpb);
+    if (cap <= 0) return TVPD_ERR_HIP;
+    grid = std::min(grid, cap);
+  }
   BatchSetup B;
-  build_setup(L, n, shapes, offsets, prm, th, wpb, static_cast<char*>(ws), B);
+  build_setup(L, n, shapes, offsets, prm, th, wpb, grid * wpb,
+              static_cast<char*>(ws), B);
   BHIP(hipMemcpyAsync(ws, B.host.data(), B.host.size(), hipMemcpyHostToDevice,
                       s));
   const int64_t* offs_dev = reinterpret_cast<const int64_t*>(
       static_cast<char*>(ws) + L.off_offs);
   BHIP(launch_batch_init(B.args, g, offs_dev, s));
   if (B.args.max_iter > 0) {
-    const int want = (B.ntiles + wpb - 1) / wpb;
     if (mode == 0) {
-      const int cap = batch_persistent_grid(wpb);
-      if (cap <= 0) return TVPD_ERR_HIP;
-      const int grid = std::min(cap, want);
       BHIP(launch_batch_persistent(B.args, grid, s));
     } else if (mode == 1) {
-      const int grid = std::min(want, 2048);
       if (int rc = run_graph_blocks(B.args, grid, s)) return rc;
     } else {
-      const int grid = std::min(want, 2048);
       const int ce = B.args.check_every;
       for (int k = 0; k < B.args.max_iter; ++k)
         BHIP(launch_batch_sweep(B.args, grid, ce > 0 && (k % ce) == 0, s));
     }
-  } else {
-    // no iterations: k stays 0
   }
   BHIP(launch_batch_final(B.args, f, offs_dev, s));
   std::vector<ImgState> st(n);

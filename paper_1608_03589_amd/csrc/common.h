@@ -23,7 +23,7 @@ struct DevState {
   int32_t k_end;         // sweeps do nothing once k >= k_end
   int32_t converged;     // set by a passing gap check (k is then frozen)
   int32_t iters;         // k at which the passing check happened
-  uint32_t blocks_done;  // completion counter of the running sweep
+  uint32_t unused0;      // (arrival counters: SyncArea at kSyncOffset)
   int32_t checks;        // number of gap checks performed
   int32_t nblocks;       // block count of the last gap sweep
   int32_t flags;         // device-side error bits

@@ -6,6 +6,7 @@
 // writes 12 (f^{k+1}, p^{k+1} x2).  The last block to finish advances the
 // iteration counter kept in device memory, or on a gap check reduces the
 // per-block partials in a fixed order and applies the stopping rule.
+#include "sync.h"
 #include "tile2d.h"
 
 namespace tvpd {
@@ -34,17 +35,15 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
   __syncthreads();  // every wave of the block has read k and finished
   if (threadIdx.x == 0) {
     __threadfence();
-    const unsigned prev = atomicAdd(&st->blocks_done, 1u);
-    s_last = (prev == nb - 1);
+    SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
+                                               kSyncOffset);
+    s_last = arrive_last(sa, nb) ? 1 : 0;
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
   if constexpr (!GAP) {
-    if (threadIdx.x == 0) {
-      st->blocks_done = 0;
-      st->k = k + 1;
-    }
+    if (threadIdx.x == 0) st->k = k + 1;
   } else {
     double sg = 0.0, sp = 0.0;
     for (unsigned i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -64,7 +63,6 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
       } else {
         st->k = k + 1;
       }
-      st->blocks_done = 0;
     }
   }
 }
@@ -135,12 +133,16 @@ __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
     st->k_end = 0x7fffffff;
     st->converged = 0;
     st->iters = 0;
-    st->blocks_done = 0;
     st->checks = 0;
     st->nblocks = 0;
     st->flags = 0;
     st->P = st->D = st->gap = 0.0;
     st->tol = -1.0;
+    SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
+                                               kSyncOffset);
+    for (int i = 0; i < kSyncGroups; ++i) sa->sub[i].v = 0;
+    sa->top.v = 0;
+    sa->gen.v = 0;
   }
 }
 
@@ -148,7 +150,10 @@ __global__ void set_params_kernel(DevState* st, int32_t k_end, double tol) {
   st->k_end = k_end;
   st->tol = tol;
   st->converged = 0;
-  st->blocks_done = 0;
+  SyncArea* sa =
+      reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) + kSyncOffset);
+  for (int i = 0; i < kSyncGroups; ++i) sa->sub[i].v = 0;
+  sa->top.v = 0;
 }
 
 __global__ void read2d_kernel(const float* base, int64_t plane, int ny,

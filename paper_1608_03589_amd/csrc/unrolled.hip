@@ -40,10 +40,9 @@ struct Pix {
   bool ok;
 };
 
-__device__ __forceinline__ Pix pixel_of(const PlaneSet& P) {
+__device__ __forceinline__ Pix pixel_at(const PlaneSet& P, int64_t blk) {
   Pix q;
   const int xc = (P.nx + kRowBlock - 1) / kRowBlock;
-  const int64_t blk = blockIdx.x;
   const int64_t row = blk / xc;
   const int xchunk = (int)(blk - row * xc);
   q.x = xchunk * kRowBlock + threadIdx.x;
@@ -55,6 +54,10 @@ __device__ __forceinline__ Pix pixel_of(const PlaneSet& P) {
   q.ok = q.x < P.nx && q.b < P.nb;
   q.o = ((int64_t)q.z * P.ny + q.y) * P.pitch + q.x;
   return q;
+}
+
+__device__ __forceinline__ Pix pixel_of(const PlaneSet& P) {
+  return pixel_at(P, blockIdx.x);
 }
 
 __device__ __forceinline__ int64_t row_blocks(const PlaneSet& P) {
@@ -223,9 +226,11 @@ __global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
     PlaneSet P, AdjIds ids, const float* __restrict__ coeffs, int k,
     float theta, double* __restrict__ partials) {
   __shared__ double red[2][kMaxBlock / kWave];
-  const Pix q = pixel_of(P);
   double lb = 0.0, sb = 0.0;
-  if (q.ok) {
+  const int64_t nrow = row_blocks(P);
+  for (int64_t rb = blockIdx.x; rb < nrow; rb += gridDim.x) {
+    const Pix q = pixel_at(P, rb);
+    if (!q.ok) continue;
     int64_t st[3];
     bool fwd[3], bwd[3];
     axes<ND>(P, q, st, fwd, bwd);
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
       const float sc = lam / nrm;
 #pragma unroll
       for (int c = 0; c < ND; ++c) t[c] = sc * (s[c] - nv[c] * ns);
-      lb = ns;
+      lb += ns;
     } else {
 #pragma unroll
       for (int c = 0; c < ND; ++c) t[c] = s[c];
@@ -287,9 +292,11 @@ __global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
     PlaneSet P, AdjIds ids, const float* __restrict__ coeffs, int k,
     float theta, double* __restrict__ partials) {
   __shared__ double red[2][kMaxBlock / kWave];
-  const Pix q = pixel_of(P);
   double tb = 0.0, unused = 0.0;
-  if (q.ok) {
+  const int64_t nrow = row_blocks(P);
+  for (int64_t rb = blockIdx.x; rb < nrow; rb += gridDim.x) {
+    const Pix q = pixel_at(P, rb);
+    if (!q.ok) continue;
     int64_t st[3];
     bool fwd[3], bwd[3];
     axes<ND>(P, q, st, fwd, bwd);
@@ -304,7 +311,7 @@ __global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
     const float alpha = cplane(P, q.b, ids.a_in)[q.o] / opt;
     float* gbar = plane(P, q.b, ids.gbar);
     gbar[q.o] = gbar[q.o] + tau * alpha;
-    tb = (double)alpha * (((double)d + (double)g) - (double)fn);
+    tb += (double)alpha * (((double)d + (double)g) - (double)fn);
     const float dt =
         div_point<ND>(cplane(P, q.b, ids.t_out), P.plane, q.o, st, bwd);
     const float w = -sig * dt;
@@ -388,9 +395,17 @@ int64_t nrow_blocks(const PlaneSet& P) {
   return (int64_t)((P.nx + kRowBlock - 1) / kRowBlock) * P.nb * P.nz * P.ny;
 }
 
+// Blocks of the adjoint passes: grid-stride over row blocks, so that the
+// per-step coefficient reduction sums a few thousand partials at most.
+constexpr int64_t kAdjBlocks = 4096;
+int64_t adj_blocks(const PlaneSet& P) {
+  const int64_t n = nrow_blocks(P);
+  return n < kAdjBlocks ? n : kAdjBlocks;
+}
+
 }  // namespace
 
-int64_t u_partials_needed(const PlaneSet& P) { return 3 * nrow_blocks(P) + 1; }
+int64_t u_partials_needed(const PlaneSet& P) { return 3 * adj_blocks(P) + 1; }
 
 hipError_t launch_u_init(const PlaneSet& P, const float* g, int id_g,
                          int id_zero, int nzero, hipStream_t s) {
@@ -455,7 +470,7 @@ hipError_t launch_u_adjoint(const PlaneSet& P, const AdjIds& ids,
                             const float* coeffs, int k, float theta,
                             double* partials, int64_t max_partials,
                             float* grad_coeffs, hipStream_t s) {
-  const int64_t nblk = nrow_blocks(P);
+  const int64_t nblk = adj_blocks(P);
   if (3 * nblk > max_partials) return hipErrorInvalidValue;
   double* pa = partials;
   double* pb = partials + 2 * nblk;
