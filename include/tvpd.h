@@ -164,6 +164,14 @@ int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
 int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb,
                   int32_t* order);
 
+/* Temporal blocking of the plain 2D solver: with on = 1 (the default) the
+ * iterations run as two-iteration passes (f^k, f^{k-1}, p^k, g read once,
+ * f^{k+1}, f^{k+2}, p^{k+2} written once: 36 bytes per two pixel-iterations)
+ * wherever no gap check falls on a pass's second iteration; with on = 0 every
+ * launch is one iteration (32 bytes per pixel-iteration).  The iterates are
+ * bit-identical either way.  Process-wide setting. */
+int tvpd_set_blocking(int32_t on);
+
 /* Autotuner.  Times every candidate tile (th from 4 to 256, wpb 1/2/4, both
  * orders) of the sweep on `ws`, an initialised workspace of this shape, and
  * keeps the fastest for `shape` in this process.  The workspace state is

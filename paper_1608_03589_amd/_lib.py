@@ -77,6 +77,7 @@ SIGNATURES = {
                                 C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32),
                                 C.POINTER(C.c_float), _P]),
     "tvpd_tune_load": (C.c_int, [C.c_char_p, C.POINTER(_I32)]),
+    "tvpd_set_blocking": (C.c_int, [_I32]),
     "tvpd_unrolled_workspace_size": (C.c_int, [C.POINTER(Shape), _I32, _I32, _I32,
                                                C.POINTER(_SZ)]),
     "tvpd_unrolled_forward": (C.c_int, [C.POINTER(Shape), _I32, _P, _P, _I32, _I32, _F,

@@ -3,6 +3,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 
 #include "common.h"
@@ -64,7 +65,7 @@ Layout make_layout(const tvpd_shape& s) {
   L.nx = s.nx;
   L.pitch = (int)round_up(s.nx, kColsPerLane);
   L.plane = round_up((int64_t)s.nz * s.ny * L.pitch, 64) + TVPD_PLANE_PAD;
-  L.nplanes = 3 + 2 * s.ndim + 1;
+  L.nplanes = s.ndim == 2 ? kPlainPlanes2D : 4 + 3 * s.ndim + 1;
   // enough reduction slots for one block per (strip, row) and for the
   // one-pixel-per-thread energy kernel
   const int64_t ntx = (s.nx + kStripCols - 1) / kStripCols;
@@ -127,16 +128,37 @@ int poller_get(Poller** out) {
     if ((call) != hipSuccess) return TVPD_ERR_HIP;        \
   } while (0)
 
+// Enqueue iterations k_first .. k_first+n-1.  Two-iteration passes are used
+// wherever no gap check falls on a pass's second iteration (checks are
+// evaluated at the first iteration of a pass only).
 int enqueue_sweeps2d(const Layout& L, const Tile2D& t, const tvpd_coeffs& c,
-                     int64_t k_first, int n, int check_every, void* ws,
-                     hipStream_t s) {
-  for (int i = 0; i < n; ++i) {
+                     int64_t k_first, int n, int check_every, bool blocked,
+                     void* ws, hipStream_t s) {
+  int i = 0;
+  while (i < n) {
     const int64_t kk = k_first + i;
     const bool gap = check_every > 0 && (kk % check_every) == 0;
-    TVPD_HIP(launch_sweep2d(L, t, c, gap, ws, s));
+    const bool gap_next = check_every > 0 && ((kk + 1) % check_every) == 0;
+    if (blocked && n - i >= 2 && !gap_next) {
+      TVPD_HIP(launch_sweep2d(L, t, c, gap, true, ws, s));
+      i += 2;
+    } else {
+      TVPD_HIP(launch_sweep2d(L, t, c, gap, false, ws, s));
+      i += 1;
+    }
   }
   return TVPD_OK;
 }
+
+// Two-iteration passes (temporal blocking) are on unless switched off for
+// this process by tvpd_set_blocking(0).
+std::atomic<int> g_blocking{1};
+
+}  // namespace
+
+bool blocking_enabled() { return g_blocking.load() != 0; }
+
+namespace {
 
 int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
             float* f_out, const tvpd_params& prm, void* ws, tvpd_result* res,
@@ -150,6 +172,7 @@ int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
 
   const int ce = prm.check_every;
   const bool can_stop = ce > 0 && prm.gap_tol >= 0.0;
+  const bool blocked = g_blocking.load() != 0;
   // chunk of iterations between host polls: a multiple of check_every
   int chunk = 64;
   if (ce > 0) chunk = ce * ((64 + ce - 1) / ce);
@@ -162,7 +185,8 @@ int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
   hipGraph_t graph = nullptr;
   if (use_graph && prm.max_iter >= chunk) {
     TVPD_HIP(hipStreamBeginCapture(poll->capture, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_sweeps2d(L, t, prm.c, 0, chunk, ce, ws, poll->capture);
+    rc = enqueue_sweeps2d(L, t, prm.c, 0, chunk, ce, blocked, ws,
+                          poll->capture);
     hipGraph_t gtmp = nullptr;
     const hipError_t e = hipStreamEndCapture(poll->capture, &gtmp);
     if (rc || e != hipSuccess) {
@@ -193,7 +217,7 @@ int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
         return TVPD_ERR_HIP;
       }
     } else {
-      rc = enqueue_sweeps2d(L, t, prm.c, launched, n, ce, ws, s);
+      rc = enqueue_sweeps2d(L, t, prm.c, launched, n, ce, blocked, ws, s);
       if (rc) {
         cleanup();
         return rc;
@@ -293,7 +317,8 @@ int tvpd_step(const tvpd_shape* shape, const tvpd_coeffs* c, int32_t n_iter,
   hipStream_t s = (hipStream_t)stream;
   TVPD_HIP(launch_set_params(ws, INT_MAX, -1.0, s));
   const Tile2D t = tile2d_for(L);
-  return enqueue_sweeps2d(L, t, *c, 0, n_iter, 0, ws, s);
+  return enqueue_sweeps2d(L, t, *c, 0, n_iter, 0, g_blocking.load() != 0, ws,
+                          s);
 }
 
 int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
@@ -405,6 +430,12 @@ int tvpd_tune_load(const char* cache_path, int32_t* count) {
   int n = 0;
   if (int rc = tune_load(cache_path, &n)) return rc;
   *count = n;
+  return TVPD_OK;
+}
+
+int tvpd_set_blocking(int32_t on) {
+  if (on != 0 && on != 1) return TVPD_ERR_INVALID_ARG;
+  g_blocking.store(on);
   return TVPD_OK;
 }
 

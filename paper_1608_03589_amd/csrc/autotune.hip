@@ -86,8 +86,9 @@ void remember_tile2d(const tvpd_shape& s, const Tile2D& t) {
   g_table.push_back({s, t});
 }
 
-// Time one tile: warm up, then enough sweeps for about 2 ms of work.
-static int time_tile(const Layout& L, const Tile2D& t, void* ws,
+// Time one tile: warm up, then enough launches for about 2 ms of work.  With
+// `two`, launches are two-iteration passes; the result is per iteration.
+static int time_tile(const Layout& L, const Tile2D& t, bool two, void* ws,
                      hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* us) {
   tvpd_coeffs c;
   c.lam = 0.1f;
@@ -95,13 +96,13 @@ static int time_tile(const Layout& L, const Tile2D& t, void* ws,
   c.theta = 1.0f;
   if (sweep2d_blocks(L, t) > L.max_partials) return TVPD_ERR_INVALID_ARG;
   for (int i = 0; i < 2; ++i)
-    if (launch_sweep2d(L, t, c, false, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+    if (launch_sweep2d(L, t, c, false, two, ws, s) != hipSuccess) return TVPD_ERR_HIP;
   int n = 2;
   float ms = 0.0f;
   for (int round = 0; round < 2; ++round) {
     if (hipEventRecord(e0, s) != hipSuccess) return TVPD_ERR_HIP;
     for (int i = 0; i < n; ++i)
-      if (launch_sweep2d(L, t, c, false, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+      if (launch_sweep2d(L, t, c, false, two, ws, s) != hipSuccess) return TVPD_ERR_HIP;
     if (hipEventRecord(e1, s) != hipSuccess) return TVPD_ERR_HIP;
     if (hipEventSynchronize(e1) != hipSuccess) return TVPD_ERR_HIP;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TVPD_ERR_HIP;
@@ -112,7 +113,7 @@ static int time_tile(const Layout& L, const Tile2D& t, void* ws,
       if (n > 200) n = 200;
     }
   }
-  *us = ms * 1000.0f / n;
+  *us = ms * 1000.0f / n / (two ? 2.0f : 1.0f);
   return TVPD_OK;
 }
 
@@ -136,7 +137,7 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
         t.wpb = w;
         t.order = order;
         float us = 0.0f;
-        rc = time_tile(L, t, ws, s, e0, e1, &us);
+        rc = time_tile(L, t, blocking_enabled(), ws, s, e0, e1, &us);
         if (rc == TVPD_ERR_INVALID_ARG) {
           rc = TVPD_OK;
           continue;

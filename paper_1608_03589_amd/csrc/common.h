@@ -39,7 +39,7 @@ struct Layout {
   int nz, ny, nx;
   int pitch;              // floats per stored row (multiple of 4, >= nx)
   int64_t plane;          // floats per plane (multiple of 64)
-  int nplanes;            // 3 (f ring) + 2*ndim (dual ring) + 1 (g)
+  int nplanes;            // 4 (f ring) + 3*ndim (dual ring) + 1 (g)
   int64_t max_partials;   // reduction slots (2 doubles each)
   size_t partial_off;     // byte offset of the partials
   size_t plane_off;       // byte offset of plane 0
@@ -47,6 +47,15 @@ struct Layout {
 };
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Plane block of the plain 2D solver: f^k in slot k mod 4 (planes 0..3),
+// p^k in slot k mod 3 (planes 4 + 2 (k mod 3), x then y), g in plane 10.  A
+// two-iteration pass reads f^k, f^{k-1}, p^k and writes f^{k+1}, f^{k+2},
+// p^{k+2}: with these ring sizes it never overwrites its own inputs.
+constexpr int kPlainPlanes2D = 11;
+constexpr int kPlainG = 10;
+__host__ __device__ inline int plain_f(int k) { return ((k % 4) + 4) % 4; }
+__host__ __device__ inline int plain_p(int k) { return 4 + 2 * (k % 3); }
 
 // Tile configuration of the 2D sweep: each wave owns a strip of 256 columns
 // and a band of `th` rows; a block holds `wpb` consecutive wave tiles.
@@ -76,8 +85,8 @@ struct Sweep2DArgs {
 hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
                          hipStream_t s);
 hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
-                          const tvpd_coeffs& c, bool with_gap, void* ws,
-                          hipStream_t s);
+                          const tvpd_coeffs& c, bool with_gap, bool two,
+                          void* ws, hipStream_t s);
 hipError_t launch_read2d(const Layout& L, const void* ws, float* f_out,
                          float* p_out, hipStream_t s);
 hipError_t launch_energy2d(const Layout& L, float lam, void* ws,
@@ -94,5 +103,6 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
                Tile2D* best, float* best_us);
 int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t, float us);
 int tune_load(const char* path, int* count);
+bool blocking_enabled();  // two-iteration passes in use (api.hip)
 
 }  // namespace tvpd

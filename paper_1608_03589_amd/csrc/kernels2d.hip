@@ -8,6 +8,7 @@
 // per-block partials in a fixed order and applies the stopping rule.
 #include "sync.h"
 #include "tile2d.h"
+#include "tile2d_x2.h"
 
 namespace tvpd {
 namespace {
@@ -18,7 +19,7 @@ using namespace dev;
 // Completion of a sweep: the last block to finish advances k, or on a gap
 // check reduces the per-block partials (fixed order, float64), records the
 // energies and either freezes k (converged) or advances it.
-template <bool GAP>
+template <bool GAP, int STEP>
 __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
                                              int k, double acc_gap,
                                              double acc_P) {
@@ -43,7 +44,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
   if (!s_last) return;
   __threadfence();
   if constexpr (!GAP) {
-    if (threadIdx.x == 0) st->k = k + 1;
+    if (threadIdx.x == 0) st->k = k + STEP;
   } else {
     double sg = 0.0, sp = 0.0;
     for (unsigned i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -61,7 +62,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
         st->converged = 1;
         st->iters = k;
       } else {
-        st->k = k + 1;
+        st->k = k + STEP;
       }
     }
   }
@@ -86,7 +87,15 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
   double acc_gap = 0.0, acc_P = 0.0;
   if (wt < a.ntiles) {
     TileCtx c;
-    ring2d(a.base, a.plane, k, c);
+    const int64_t PL = a.plane;
+    c.fk = a.base + plain_f(k) * PL;
+    c.fkm = a.base + plain_f(k - 1) * PL;
+    c.fn = a.base + plain_f(k + 1) * PL;
+    c.pxk = a.base + plain_p(k) * PL;
+    c.pyk = c.pxk + PL;
+    c.pxn = a.base + plain_p(k + 1) * PL;
+    c.pyn = c.pxn + PL;
+    c.g = a.base + kPlainG * PL;
     int tx, ty;
     if (a.order == 0) {
       ty = wt / a.ntx;
@@ -107,7 +116,55 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
     c.th = a.theta;
     sweep_tile<GAP>(c, acc_gap, acc_P);
   }
-  finish_sweep<GAP>(st, a.partials, k, acc_gap, acc_P);
+  finish_sweep<GAP, 1>(st, a.partials, k, acc_gap, acc_P);
+}
+
+// Two iterations k -> k+2 per launch (tile2d_x2.h); the gap, when asked
+// for, is that of (f^k, p^k).
+template <bool GAP>
+__global__ __launch_bounds__(kMaxBlock) void sweep2d_x2_kernel(Sweep2DArgs a) {
+  DevState* st = a.st;
+  const int k = st->k;
+  if (st->converged || k + 2 > st->k_end) return;
+  const int wave = threadIdx.x / kWave;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (b >> 3);
+  const int wt = bt * a.wpb + wave;
+  double acc_gap = 0.0, acc_P = 0.0;
+  if (wt < a.ntiles) {
+    TileCtx2 c;
+    const int64_t PL = a.plane;
+    c.F = a.base + plain_f(k) * PL;
+    c.M = a.base + plain_f(k - 1) * PL;
+    c.FA = a.base + plain_f(k + 1) * PL;
+    c.FB = a.base + plain_f(k + 2) * PL;
+    c.PX = a.base + plain_p(k) * PL;
+    c.PY = c.PX + PL;
+    c.BX = a.base + plain_p(k + 2) * PL;
+    c.BY = c.BX + PL;
+    c.G = a.base + kPlainG * PL;
+    int tx, ty;
+    if (a.order == 0) {
+      ty = wt / a.ntx;
+      tx = wt - ty * a.ntx;
+    } else {
+      tx = wt / a.nty;
+      ty = wt - tx * a.nty;
+    }
+    c.ny = a.ny;
+    c.nx = a.nx;
+    c.pitch = a.pitch;
+    c.x0 = tx * kStripCols;
+    c.y0 = ty * a.th;
+    c.y1 = min(c.y0 + a.th, a.ny);
+    c.lam = a.lam;
+    c.tau = a.tau;
+    c.sig = a.sigma;
+    c.th = a.theta;
+    sweep_tile_x2<GAP>(c, acc_gap, acc_P);
+  }
+  finish_sweep<GAP, 2>(st, a.partials, k, acc_gap, acc_P);
 }
 
 __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
@@ -119,14 +176,10 @@ __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
     const int y = (int)(i / pitch);
     const int x = (int)(i - (int64_t)y * pitch);
     const float v = (x < nx) ? g[(int64_t)y * nx + x] : 0.0f;
-    base[i] = v;                 // f^0    (slot 0)
-    base[plane + i] = 0.0f;      // slot 1
-    base[2 * plane + i] = v;     // f^{-1} (slot 2)
-    base[3 * plane + i] = 0.0f;  // p^0
-    base[4 * plane + i] = 0.0f;
-    base[5 * plane + i] = 0.0f;
-    base[6 * plane + i] = 0.0f;
-    base[7 * plane + i] = v;     // g
+    for (int s = 0; s < kPlainPlanes2D; ++s) base[s * plane + i] = 0.0f;
+    base[plain_f(0) * plane + i] = v;   // f^0
+    base[plain_f(-1) * plane + i] = v;  // f^{-1}
+    base[kPlainG * plane + i] = v;      // g (p^0 = 0)
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->k = 0;
@@ -160,8 +213,8 @@ __global__ void read2d_kernel(const float* base, int64_t plane, int ny,
                               int nx, int pitch, const DevState* st,
                               float* f_out, float* p_out) {
   const int k = st->k;
-  const float* f = base + (k % 3) * plane;
-  const float* px = base + (3 + 2 * (k & 1)) * plane;
+  const float* f = base + plain_f(k) * plane;
+  const float* px = base + plain_p(k) * plane;
   const float* py = px + plane;
   const int64_t n = (int64_t)ny * nx;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -185,10 +238,10 @@ __global__ __launch_bounds__(kMaxBlock) void energy2d_kernel(
   if (skip_if_converged && st->converged) return;
   __shared__ double red[2][kMaxBlock / kWave];
   const int k = st->k;
-  const float* f = base + (k % 3) * plane;
-  const float* px = base + (3 + 2 * (k & 1)) * plane;
+  const float* f = base + plain_f(k) * plane;
+  const float* px = base + plain_p(k) * plane;
   const float* py = px + plane;
-  const float* g = base + 7 * plane;
+  const float* g = base + kPlainG * plane;
   const int64_t n = (int64_t)ny * nx;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double sg = 0.0, sp = 0.0;
@@ -272,8 +325,8 @@ hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
 }
 
 hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
-                          const tvpd_coeffs& c, bool with_gap, void* ws,
-                          hipStream_t s) {
+                          const tvpd_coeffs& c, bool with_gap, bool two,
+                          void* ws, hipStream_t s) {
   Sweep2DArgs a;
   a.base = planes_of(L, ws);
   a.plane = L.plane;
@@ -294,12 +347,18 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   a.partials = partials_of(L, ws);
   const int nb = (a.ntiles + t.wpb - 1) / t.wpb;
   if (nb > L.max_partials) return hipErrorInvalidValue;
-  if (with_gap)
-    hipLaunchKernelGGL(sweep2d_kernel<true>, dim3(nb), dim3(t.wpb * kWave), 0,
-                       s, a);
-  else
-    hipLaunchKernelGGL(sweep2d_kernel<false>, dim3(nb), dim3(t.wpb * kWave), 0,
-                       s, a);
+  const dim3 grid(nb), block(t.wpb * kWave);
+  if (two) {
+    if (with_gap)
+      hipLaunchKernelGGL(sweep2d_x2_kernel<true>, grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(sweep2d_x2_kernel<false>, grid, block, 0, s, a);
+  } else {
+    if (with_gap)
+      hipLaunchKernelGGL(sweep2d_kernel<true>, grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL(sweep2d_kernel<false>, grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -169,6 +169,12 @@ def get_tile(shape):
     return th.value, wpb.value, order.value
 
 
+def set_blocking(on: bool):
+    """Two-iteration passes (temporal blocking) for the plain 2D solver on or
+    off, process-wide; the iterates are the same either way."""
+    call("tvpd_set_blocking", 1 if on else 0)
+
+
 def autotune(shape, device="cuda", cache_path: str | None = None,
              g: torch.Tensor | None = None):
     """Time the candidate sweep tiles for ``shape`` and keep the fastest for

@@ -251,3 +251,34 @@ def test_autotune_choice_and_cache_roundtrip(tmp_path):
     f, _, _ = gpu_fixed(g32, 30, 0.1)
     f_ref, _, _ = oracle.run_fixed(g32.astype(np.float64), 0.1, S2, S2, 30)
     assert rel(f, f_ref) <= RTOL
+
+
+@pytest.mark.parametrize("shape,tile", [
+    ((300, 517), (1, 1, 1)), ((300, 517), (2, 2, 0)), ((300, 517), (3, 4, 0)),
+    ((300, 517), (64, 4, 0)), ((37, 1030), (5, 2, 1)), ((1, 9), (1, 1, 0)),
+    ((2, 300), (1, 4, 0)), ((3, 3), (2, 1, 1)), ((513, 257), (300, 1, 0)),
+])
+def test_two_iteration_passes_are_bitwise_equal(shape, tile):
+    """Temporal blocking (two iterations per pass) reproduces one-iteration
+    passes bit for bit, for even and odd iteration counts and with a
+    stopping solve."""
+    g32 = scene32(*shape, 10, 0.1, 90 + shape[0])
+    tv.set_tile(shape, *tile)
+    out = {}
+    try:
+        for blocked in (False, True):
+            tv.set_blocking(blocked)
+            for n in (7, 20):
+                f, p, _ = gpu_fixed(g32, n, 0.1)
+                out[(blocked, n)] = (f, p)
+            s = tv.PlainSolver(shape, DEV)
+            fs, rs = s.solve(torch.from_numpy(g32).to(DEV), 0.1, max_iter=400,
+                             check_every=10, gap_tol=2e-3)
+            out[(blocked, "solve")] = (fs.cpu().numpy(), rs.iters, rs.gap)
+    finally:
+        tv.set_blocking(True)
+    for n in (7, 20):
+        assert np.array_equal(out[(True, n)][0], out[(False, n)][0])
+        assert np.array_equal(out[(True, n)][1], out[(False, n)][1])
+    a, b = out[(True, "solve")], out[(False, "solve")]
+    assert a[1] == b[1] and np.array_equal(a[0], b[0])
