@@ -53,6 +53,7 @@ struct BatchArgs {
   int32_t max_iter, check_every;
   int32_t wpb;
   int32_t switch_tiles;  // use short bands once fewer tall tiles are active
+  int32_t blocked;       // two-iteration passes (check_every even or 0)
 };
 
 constexpr int kFinalBlocks = 32;  // blocks per image of the final pass
@@ -63,7 +64,7 @@ int batch_persistent_grid(int wpb);
 hipError_t launch_batch_persistent(const BatchArgs& a, int grid,
                                    hipStream_t s);
 hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
-                              hipStream_t s);
+                              bool two, hipStream_t s);
 hipError_t launch_batch_final(const BatchArgs& a, float* f_out,
                               const int64_t* offs_dev, hipStream_t s);
 int batch_max_blocks_per_cu(int wpb);

@@ -19,6 +19,7 @@
 #include "batch.h"
 #include "sync.h"
 #include "tile2d.h"
+#include "tile2d_x2.h"
 
 namespace tvpd {
 namespace {
@@ -69,40 +70,69 @@ __device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
   return s_ok != 0;
 }
 
-__device__ __forceinline__ void tile_ctx(const BatchArgs& a, int t, int k,
-                                         TileCtx& c) {
+// Sweep one tile: one iteration k -> k+1, or with `two` the two-iteration
+// pass k -> k+2 (tile2d_x2.h); on check iterations lane 0 stores the tile's
+// partials (the gap of (f^k, p^k)).  Plane block of an image: the plain
+// solver's 11-plane layout (f ring of 4, dual ring of 3, g).
+template <bool CHECK>
+__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
+                                        bool two) {
   const TileDesc T = a.tiles[t];
   const ImgDesc& D = a.imgs[T.img];
-  ring2d(a.arena + D.off, D.plane, k, c);
-  c.ny = D.ny;
-  c.nx = D.nx;
-  c.pitch = D.pitch;
-  c.x0 = T.x0;
-  c.y0 = T.y0;
-  c.y1 = T.y1;
-  c.lam = D.lam;
-  c.tau = D.tau;
-  c.sig = D.sigma;
-  c.th = D.theta;
-}
-
-// Sweep one tile; on check iterations lane 0 stores the tile's partials.
-__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
-                                        bool check) {
-  TileCtx c;
-  tile_ctx(a, t, k, c);
-  if (check) {
-    double sg = 0.0, sp = 0.0;
-    sweep_tile<true>(c, sg, sp);
+  float* base = a.arena + D.off;
+  const int64_t PL = D.plane;
+  double sg = 0.0, sp = 0.0;
+  if (two) {
+    TileCtx2 c;
+    c.F = base + plain_f(k) * PL;
+    c.M = base + plain_f(k - 1) * PL;
+    c.FA = base + plain_f(k + 1) * PL;
+    c.FB = base + plain_f(k + 2) * PL;
+    c.PX = base + plain_p(k) * PL;
+    c.PY = c.PX + PL;
+    c.BX = base + plain_p(k + 2) * PL;
+    c.BY = c.BX + PL;
+    c.G = base + kPlainG * PL;
+    c.ny = D.ny;
+    c.nx = D.nx;
+    c.pitch = D.pitch;
+    c.x0 = T.x0;
+    c.y0 = T.y0;
+    c.y1 = T.y1;
+    c.lam = D.lam;
+    c.tau = D.tau;
+    c.sig = D.sigma;
+    c.th = D.theta;
+    sweep_tile_x2<CHECK>(c, sg, sp);
+  } else {
+    TileCtx c;
+    c.fk = base + plain_f(k) * PL;
+    c.fkm = base + plain_f(k - 1) * PL;
+    c.fn = base + plain_f(k + 1) * PL;
+    c.pxk = base + plain_p(k) * PL;
+    c.pyk = c.pxk + PL;
+    c.pxn = base + plain_p(k + 1) * PL;
+    c.pyn = c.pxn + PL;
+    c.g = base + kPlainG * PL;
+    c.ny = D.ny;
+    c.nx = D.nx;
+    c.pitch = D.pitch;
+    c.x0 = T.x0;
+    c.y0 = T.y0;
+    c.y1 = T.y1;
+    c.lam = D.lam;
+    c.tau = D.tau;
+    c.sig = D.sigma;
+    c.th = D.theta;
+    sweep_tile<CHECK>(c, sg, sp);
+  }
+  if (CHECK) {
     sg = wave_sum(sg);
     sp = wave_sum(sp);
     if ((threadIdx.x & (kWave - 1)) == 0) {
       store_agent(&a.partials[2 * t], sg);
       store_agent(&a.partials[2 * t + 1], sp);
     }
-  } else {
-    double sg = 0.0, sp = 0.0;
-    sweep_tile<false>(c, sg, sp);
   }
 }
 
@@ -184,13 +214,18 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
   const int nw = gridDim.x * a.wpb;
   const int gw = blockIdx.x * a.wpb + wave;
   int k = 0;
-  for (; k < a.max_iter; ++k) {
+  while (k < a.max_iter) {
     const bool check = a.check_every > 0 && (k % a.check_every) == 0;
+    const bool two = a.blocked && k + 2 <= a.max_iter;
     const int nact = load_i32(&h->n_active);
     if (nact == 0) break;
     if (wave < a.wpb)
-      for (int idx = gw; idx < nact; idx += nw)
-        do_tile(a, a.active[idx], k, check);
+      for (int idx = gw; idx < nact; idx += nw) {
+        if (check)
+          do_tile<true>(a, a.active[idx], k, two);
+        else
+          do_tile<false>(a, a.active[idx], k, two);
+      }
     if (!grid_barrier(h, gen)) return;
     if (check) {
       const int tbl = load_i32(&h->table);
@@ -207,6 +242,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
         if (!grid_barrier(h, gen)) return;
       }
     }
+    k += two ? 2 : 1;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) h->k = k;
 }
@@ -214,13 +250,13 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
 // One iteration over the active list (graph-block driver).  The last block
 // to finish advances k and, on check iterations, reduces every running
 // image, stops the converged ones and rebuilds the active list.
-template <bool CHECK>
+template <bool CHECK, bool TWO>
 __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
   __shared__ double red[2][kMaxBlock / kWave];
   __shared__ int s_last;
   BatchHdr* h = a.hdr;
   const int k = h->k;
-  if (k >= a.max_iter) return;
+  if (k + (TWO ? 2 : 1) > a.max_iter) return;
   const int nact = h->n_active;
   if (nact == 0) return;
   const int wave = threadIdx.x / kWave;
@@ -228,7 +264,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
   const int gw = blockIdx.x * a.wpb + wave;
   if (wave < a.wpb)
     for (int idx = gw; idx < nact; idx += nw)
-      do_tile(a, a.active[idx], k, CHECK);
+      do_tile<CHECK>(a, a.active[idx], k, TWO);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -246,7 +282,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
       if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
     }
   }
-  if (threadIdx.x == 0) h->k = k + 1;
+  if (threadIdx.x == 0) h->k = k + (TWO ? 2 : 1);
 }
 
 __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
@@ -262,14 +298,10 @@ __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
     const int y = (int)(e / D.pitch);
     const int x = (int)(e - (int64_t)y * D.pitch);
     const float v = (x < D.nx) ? gi[(int64_t)y * D.nx + x] : 0.0f;
-    base[e] = v;
-    base[PL + e] = 0.0f;
-    base[2 * PL + e] = v;
-    base[3 * PL + e] = 0.0f;
-    base[4 * PL + e] = 0.0f;
-    base[5 * PL + e] = 0.0f;
-    base[6 * PL + e] = 0.0f;
-    base[7 * PL + e] = v;
+    for (int s = 0; s < kPlainPlanes2D; ++s) base[s * PL + e] = 0.0f;
+    base[plain_f(0) * PL + e] = v;   // f^0
+    base[plain_f(-1) * PL + e] = v;  // f^{-1}
+    base[kPlainG * PL + e] = v;      // g
   }
 }
 
@@ -286,10 +318,10 @@ __global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
   const int k = conv ? S.iters : a.hdr->k;
   const float* base = a.arena + D.off;
   const int64_t PL = D.plane;
-  const float* f = base + (k % 3) * PL;
-  const float* px = base + (3 + 2 * (k & 1)) * PL;
+  const float* f = base + plain_f(k) * PL;
+  const float* px = base + plain_p(k) * PL;
   const float* py = px + PL;
-  const float* g = base + 7 * PL;
+  const float* g = base + kPlainG * PL;
   const int64_t n = (int64_t)D.ny * D.nx;
   const int P = D.pitch;
   double sg = 0.0, sp = 0.0;
@@ -370,13 +402,19 @@ hipError_t launch_batch_persistent(const BatchArgs& a, int grid,
 }
 
 hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
-                              hipStream_t s) {
-  if (check)
-    hipLaunchKernelGGL(batch_sweep_kernel<true>, dim3(grid),
-                       dim3(a.wpb * kWave), 0, s, a);
-  else
-    hipLaunchKernelGGL(batch_sweep_kernel<false>, dim3(grid),
-                       dim3(a.wpb * kWave), 0, s, a);
+                              bool two, hipStream_t s) {
+  const dim3 g(grid), blk(a.wpb * kWave);
+  if (two) {
+    if (check)
+      hipLaunchKernelGGL((batch_sweep_kernel<true, true>), g, blk, 0, s, a);
+    else
+      hipLaunchKernelGGL((batch_sweep_kernel<false, true>), g, blk, 0, s, a);
+  } else {
+    if (check)
+      hipLaunchKernelGGL((batch_sweep_kernel<true, false>), g, blk, 0, s, a);
+    else
+      hipLaunchKernelGGL((batch_sweep_kernel<false, false>), g, blk, 0, s, a);
+  }
   return hipGetLastError();
 }
 

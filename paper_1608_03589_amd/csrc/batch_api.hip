@@ -46,7 +46,7 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
     L.img_pitch.push_back(pitch);
     L.img_plane.push_back(plane);
     L.img_off.push_back(arena);
-    arena += 8 * plane;
+    arena += kPlainPlanes2D * plane;
     // both tile tables together hold at most two tiles per (strip, row)
     L.tmax += 2 * (int64_t)((s[i].nx + kStripCols - 1) / kStripCols) * s[i].ny;
   }
@@ -181,6 +181,8 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   a.check_every = prm[0].check_every;
   a.wpb = wpb;
   a.switch_tiles = nwaves;
+  a.blocked = blocking_enabled() &&
+              (a.check_every == 0 || a.check_every % 2 == 0) ? 1 : 0;
 }
 
 struct PinnedHdr {
@@ -214,6 +216,24 @@ int pinned_get(PinnedHdr** out) {
   return TVPD_OK;
 }
 
+// Launches of one block of `chunk` iterations starting at an iteration
+// k0 with k0 % chunk == 0: two-iteration passes when blocked, a check on the
+// first iteration of a pass whenever it is due.
+hipError_t enqueue_batch_iters(const BatchArgs& a, int grid, int k0, int n,
+                               hipStream_t s) {
+  const int ce = a.check_every;
+  int i = 0;
+  while (i < n) {
+    const int k = k0 + i;
+    const bool check = ce > 0 && (k % ce) == 0;
+    const bool two = a.blocked && n - i >= 2;
+    const hipError_t e = launch_batch_sweep(a, grid, check, two, s);
+    if (e != hipSuccess) return e;
+    i += two ? 2 : 1;
+  }
+  return hipSuccess;
+}
+
 int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
   PinnedHdr* pin = nullptr;
   if (int rc = pinned_get(&pin)) return rc;
@@ -223,9 +243,7 @@ int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   BHIP(hipStreamBeginCapture(pin->capture, hipStreamCaptureModeThreadLocal));
-  hipError_t err = hipSuccess;
-  for (int i = 0; i < chunk && err == hipSuccess; ++i)
-    err = launch_batch_sweep(a, grid, ce > 0 && (i % ce) == 0, pin->capture);
+  const hipError_t err = enqueue_batch_iters(a, grid, 0, chunk, pin->capture);
   const hipError_t e2 = hipStreamEndCapture(pin->capture, &graph);
   if (err != hipSuccess || e2 != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -238,7 +256,7 @@ int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
   int rc = TVPD_OK;
   int64_t launched = 0;
   int slot = 0, inflight = 0;
-  while (launched < a.max_iter) {
+  while (launched + chunk <= a.max_iter) {
     if (hipGraphLaunch(exec, s) != hipSuccess) {
       rc = TVPD_ERR_HIP;
       break;
@@ -261,6 +279,11 @@ int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
     }
     slot ^= 1;
   }
+  // the last partial block, launched directly (no-ops once all stopped)
+  if (rc == TVPD_OK && launched < a.max_iter &&
+      enqueue_batch_iters(a, grid, (int)launched, (int)(a.max_iter - launched),
+                          s) != hipSuccess)
+    rc = TVPD_ERR_HIP;
   (void)hipGraphExecDestroy(exec);
   (void)hipGraphDestroy(graph);
   return rc;
@@ -306,9 +329,7 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
     } else if (mode == 1) {
       if (int rc = run_graph_blocks(B.args, grid, s)) return rc;
     } else {
-      const int ce = B.args.check_every;
-      for (int k = 0; k < B.args.max_iter; ++k)
-        BHIP(launch_batch_sweep(B.args, grid, ce > 0 && (k % ce) == 0, s));
+      BHIP(enqueue_batch_iters(B.args, grid, 0, B.args.max_iter, s));
     }
   }
   BHIP(launch_batch_final(B.args, f, offs_dev, s));

@@ -170,8 +170,8 @@ def get_tile(shape):
 
 
 def set_blocking(on: bool):
-    """Two-iteration passes (temporal blocking) for the plain 2D solver on or
-    off, process-wide; the iterates are the same either way."""
+    """Two-iteration passes (temporal blocking) for the plain and batched 2D
+    solvers on or off, process-wide; the iterates are the same either way."""
     call("tvpd_set_blocking", 1 if on else 0)
 
 
