@@ -154,17 +154,28 @@ int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
  * summation order of the gap do.
  * ------------------------------------------------------------------- */
 
-/* Use this tile for `shape` from now on in this process (overrides the
- * default and any autotuned choice).  th in [1, 65536], wpb in {1, 2, 4},
- * order in {0, 1}. */
+/* Use this tile for the 2D `shape` from now on in this process (overrides
+ * the default and any autotuned choice).  th in [1, 65536], wpb in {1, 2, 4},
+ * order in {0, 1}.  TVPD_ERR_UNSUPPORTED for a 3D shape. */
 int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
                   int32_t order);
 
-/* Tile the library will use for `shape` (host out). */
+/* Tile the library will use for the 2D `shape` (host out). */
 int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb,
                   int32_t* order);
 
-/* Temporal blocking of the plain 2D solver: with on = 1 (the default) the
+/* Tiling of the fused 3D sweep.  A wave owns a 256-column strip and a band
+ * of th rows (2 or 4) and marches through a segment of tz planes (it
+ * recomputes the dual of the plane above its segment); a block holds wpb
+ * consecutive wave tiles (strip fastest, then band, then segment).  The
+ * iterates do not depend on the tile.  set: th in {2, 4}, tz in
+ * [1, 65536], wpb in {1, 2, 4}; TVPD_ERR_UNSUPPORTED for a 2D shape. */
+int tvpd_set_tile3d(const tvpd_shape* shape, int32_t th, int32_t tz,
+                    int32_t wpb);
+int tvpd_get_tile3d(const tvpd_shape* shape, int32_t* th, int32_t* tz,
+                    int32_t* wpb);
+
+/* Temporal blocking of the plain and batched 2D solvers: with on = 1 (the default) the
  * iterations run as two-iteration passes (f^k, f^{k-1}, p^k, g read once,
  * f^{k+1}, f^{k+2}, p^{k+2} written once: 36 bytes per two pixel-iterations)
  * wherever no gap check falls on a pass's second iteration; with on = 0 every
@@ -172,14 +183,16 @@ int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb,
  * bit-identical either way.  Process-wide setting. */
 int tvpd_set_blocking(int32_t on);
 
-/* Autotuner.  Times every candidate tile (th from 4 to 256, wpb 1/2/4, both
- * orders) of the sweep on `ws`, an initialised workspace of this shape, and
- * keeps the fastest for `shape` in this process.  The workspace state is
+/* Autotuner.  Times every candidate tile of the sweep on `ws`, an
+ * initialised workspace of this shape, and keeps the fastest for `shape` in
+ * this process.  2D: th from 4 to 256, wpb 1/2/4, both orders, timing the
+ * two-iteration pass when blocking is on.  3D: th 2/4, tz from 2 to 128,
+ * wpb 1/2/4; the chosen tz is returned in *order.  The workspace state is
  * advanced by the timing runs: call tvpd_init before solving with it.  If
  * cache_path is not NULL the choice is appended to that text file (one line
- * per shape: arch ndim nz ny nx th wpb order microseconds).  Outputs (host,
- * each may be NULL): the chosen tile and its time per sweep in microseconds.
- * Synchronises the stream. */
+ * per shape: arch ndim nz ny nx th wpb order-or-tz microseconds).  Outputs
+ * (host, each may be NULL): the chosen tile and its time per iteration in
+ * microseconds.  Synchronises the stream. */
 int tvpd_autotune(const tvpd_shape* shape, void* ws, size_t ws_bytes,
                   const char* cache_path, int32_t* th, int32_t* wpb,
                   int32_t* order, float* us, void* stream);

@@ -221,7 +221,7 @@ def solve(g, lam, tau=None, sigma=None, theta=1.0, max_iter=1000,
     result is f^{max_iter}, iters = max_iter, converged = False, with (P, D,
     gap) evaluated at that final pair.  gap_tol < 0 never stops.
 
-    tau and sigma default to 1 / sqrt(2 ndim), for which
+    tau and sigma default to 1 / sqrt(4 ndim), for which
     tau sigma ||grad||^2 < 1 holds on every grid (step_bound < 4 ndim).
     """
     g = np.asarray(g, dtype=np.float64)

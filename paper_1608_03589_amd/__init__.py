@@ -13,8 +13,8 @@ from .unrolled import (  # noqa: F401
 )
 from .solver import (  # noqa: F401
     PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
-    get_tile, make_shape, set_blocking, set_tile, solve, tune_load,
-    workspace_size,
+    get_tile, get_tile3d, make_shape, set_blocking, set_tile, set_tile3d,
+    solve, tune_load, workspace_size,
 )
 
 __all__ = [
@@ -22,7 +22,7 @@ __all__ = [
     "UnrolledSolver", "UnrolledTV", "default_coeffs", "unrolled_tv",
     "alloc_workspace", "autotune",
     "tune_load",
-    "default_step", "get_tile", "lib", "make_shape", "set_blocking",
-    "set_tile", "solve",
+    "default_step", "get_tile", "get_tile3d", "lib", "make_shape",
+    "set_blocking", "set_tile", "set_tile3d", "solve",
     "workspace_size",
 ]

@@ -65,7 +65,7 @@ Layout make_layout(const tvpd_shape& s) {
   L.nx = s.nx;
   L.pitch = (int)round_up(s.nx, kColsPerLane);
   L.plane = round_up((int64_t)s.nz * s.ny * L.pitch, 64) + TVPD_PLANE_PAD;
-  L.nplanes = s.ndim == 2 ? kPlainPlanes2D : 4 + 3 * s.ndim + 1;
+  L.nplanes = s.ndim == 2 ? kPlainPlanes2D : kPlainPlanes3D;
   // enough reduction slots for one block per (strip, row) and for the
   // one-pixel-per-thread energy kernel
   const int64_t ntx = (s.nx + kStripCols - 1) / kStripCols;
@@ -128,12 +128,23 @@ int poller_get(Poller** out) {
     if ((call) != hipSuccess) return TVPD_ERR_HIP;        \
   } while (0)
 
-// Enqueue iterations k_first .. k_first+n-1.  Two-iteration passes are used
+// Enqueue iterations k_first .. k_first+n-1.  2D: two-iteration passes
 // wherever no gap check falls on a pass's second iteration (checks are
-// evaluated at the first iteration of a pass only).
-int enqueue_sweeps2d(const Layout& L, const Tile2D& t, const tvpd_coeffs& c,
-                     int64_t k_first, int n, int check_every, bool blocked,
-                     void* ws, hipStream_t s) {
+// evaluated at the first iteration of a pass only).  3D: one iteration per
+// launch.
+int enqueue_sweeps(const Layout& L, const tvpd_coeffs& c, int64_t k_first,
+                   int n, int check_every, bool blocked, void* ws,
+                   hipStream_t s) {
+  if (L.ndim == 3) {
+    const Tile3D t = tile3d_for(L);
+    for (int i = 0; i < n; ++i) {
+      const int64_t kk = k_first + i;
+      const bool gap = check_every > 0 && (kk % check_every) == 0;
+      TVPD_HIP(launch_sweep3d(L, t, c, gap, ws, s));
+    }
+    return TVPD_OK;
+  }
+  const Tile2D t = tile2d_for(L);
   int i = 0;
   while (i < n) {
     const int64_t kk = k_first + i;
@@ -150,6 +161,23 @@ int enqueue_sweeps2d(const Layout& L, const Tile2D& t, const tvpd_coeffs& c,
   return TVPD_OK;
 }
 
+hipError_t launch_init(const Layout& L, const float* g, void* ws,
+                       hipStream_t s) {
+  return L.ndim == 2 ? launch_init2d(L, g, ws, s) : launch_init3d(L, g, ws, s);
+}
+
+hipError_t launch_energy(const Layout& L, float lam, void* ws,
+                         bool skip_if_converged, hipStream_t s) {
+  return L.ndim == 2 ? launch_energy2d(L, lam, ws, skip_if_converged, s)
+                     : launch_energy3d(L, lam, ws, skip_if_converged, s);
+}
+
+hipError_t launch_read(const Layout& L, const void* ws, float* f_out,
+                       float* p_out, hipStream_t s) {
+  return L.ndim == 2 ? launch_read2d(L, ws, f_out, p_out, s)
+                     : launch_read3d(L, ws, f_out, p_out, s);
+}
+
 // Two-iteration passes (temporal blocking) are on unless switched off for
 // this process by tvpd_set_blocking(0).
 std::atomic<int> g_blocking{1};
@@ -160,14 +188,13 @@ bool blocking_enabled() { return g_blocking.load() != 0; }
 
 namespace {
 
-int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
-            float* f_out, const tvpd_params& prm, void* ws, tvpd_result* res,
-            hipStream_t s) {
+int solve_plain(const Layout& L, const float* g, float* f_out,
+                const tvpd_params& prm, void* ws, tvpd_result* res,
+                hipStream_t s) {
   Poller* poll = nullptr;
   int rc = poller_get(&poll);
   if (rc) return rc;
-  const Tile2D t = tile2d_for(L);
-  TVPD_HIP(launch_init2d(L, g, ws, s));
+  TVPD_HIP(launch_init(L, g, ws, s));
   TVPD_HIP(launch_set_params(ws, prm.max_iter, prm.gap_tol, s));
 
   const int ce = prm.check_every;
@@ -179,14 +206,14 @@ int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
   bool use_graph = prm.use_graph == 1;
   if (prm.use_graph < 0) {
     // graphs pay off when launches are short, i.e. on small images
-    use_graph = (int64_t)L.ny * L.nx <= (1 << 20) && prm.max_iter >= 2 * chunk;
+    use_graph = (int64_t)L.nz * L.ny * L.nx <= (1 << 20) &&
+                prm.max_iter >= 2 * chunk;
   }
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   if (use_graph && prm.max_iter >= chunk) {
     TVPD_HIP(hipStreamBeginCapture(poll->capture, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_sweeps2d(L, t, prm.c, 0, chunk, ce, blocked, ws,
-                          poll->capture);
+    rc = enqueue_sweeps(L, prm.c, 0, chunk, ce, blocked, ws, poll->capture);
     hipGraph_t gtmp = nullptr;
     const hipError_t e = hipStreamEndCapture(poll->capture, &gtmp);
     if (rc || e != hipSuccess) {
@@ -217,7 +244,7 @@ int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
         return TVPD_ERR_HIP;
       }
     } else {
-      rc = enqueue_sweeps2d(L, t, prm.c, launched, n, ce, blocked, ws, s);
+      rc = enqueue_sweeps(L, prm.c, launched, n, ce, blocked, ws, s);
       if (rc) {
         cleanup();
         return rc;
@@ -248,8 +275,8 @@ int solve2d(const tvpd_shape& sh, const Layout& L, const float* g,
   }
   cleanup();
   // final pair energies when no check passed
-  TVPD_HIP(launch_energy2d(L, prm.c.lam, ws, true, s));
-  TVPD_HIP(launch_read2d(L, ws, f_out, nullptr, s));
+  TVPD_HIP(launch_energy(L, prm.c.lam, ws, true, s));
+  TVPD_HIP(launch_read(L, ws, f_out, nullptr, s));
   TVPD_HIP(hipMemcpyAsync(&hst[0], dst, sizeof(DevState),
                           hipMemcpyDeviceToHost, s));
   TVPD_HIP(hipStreamSynchronize(s));
@@ -300,8 +327,7 @@ int tvpd_init(const tvpd_shape* shape, const float* g, void* ws,
   if (!g) return TVPD_ERR_INVALID_ARG;
   const Layout L = make_layout(*shape);
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
-  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
-  return launch_init2d(L, g, ws, (hipStream_t)stream) == hipSuccess
+  return launch_init(L, g, ws, (hipStream_t)stream) == hipSuccess
              ? TVPD_OK
              : TVPD_ERR_HIP;
 }
@@ -313,12 +339,9 @@ int tvpd_step(const tvpd_shape* shape, const tvpd_coeffs* c, int32_t n_iter,
   if (int rc = coeffs_ok(*shape, c)) return rc;
   const Layout L = make_layout(*shape);
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
-  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   TVPD_HIP(launch_set_params(ws, INT_MAX, -1.0, s));
-  const Tile2D t = tile2d_for(L);
-  return enqueue_sweeps2d(L, t, *c, 0, n_iter, 0, g_blocking.load() != 0, ws,
-                          s);
+  return enqueue_sweeps(L, *c, 0, n_iter, 0, g_blocking.load() != 0, ws, s);
 }
 
 int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
@@ -327,8 +350,7 @@ int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
   if (!f_out) return TVPD_ERR_INVALID_ARG;
   const Layout L = make_layout(*shape);
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
-  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
-  return launch_read2d(L, ws, f_out, p_out, (hipStream_t)stream) == hipSuccess
+  return launch_read(L, ws, f_out, p_out, (hipStream_t)stream) == hipSuccess
              ? TVPD_OK
              : TVPD_ERR_HIP;
 }
@@ -353,9 +375,8 @@ int tvpd_energy_gap(const tvpd_shape* shape, float lam, void* ws,
   if (!out || !(lam >= 0.0f)) return TVPD_ERR_INVALID_ARG;
   const Layout L = make_layout(*shape);
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
-  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  TVPD_HIP(launch_energy2d(L, lam, ws, false, s));
+  TVPD_HIP(launch_energy(L, lam, ws, false, s));
   DevState h;
   TVPD_HIP(hipMemcpyAsync(&h, ws, sizeof(DevState), hipMemcpyDeviceToHost, s));
   TVPD_HIP(hipStreamSynchronize(s));
@@ -375,13 +396,13 @@ int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
   if (int rc = coeffs_ok(*shape, &prm->c)) return rc;
   const Layout L = make_layout(*shape);
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
-  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
-  return solve2d(*shape, L, g, f_out, *prm, ws, res, (hipStream_t)stream);
+  return solve_plain(L, g, f_out, *prm, ws, res, (hipStream_t)stream);
 }
 
 int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
                   int32_t order) {
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
   if (th < 1 || th > 65536) return TVPD_ERR_INVALID_ARG;
   if (wpb != 1 && wpb != 2 && wpb != 4) return TVPD_ERR_INVALID_ARG;
   if (order != 0 && order != 1) return TVPD_ERR_INVALID_ARG;
@@ -396,11 +417,37 @@ int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
 int tvpd_get_tile(const tvpd_shape* shape, int32_t* th, int32_t* wpb,
                   int32_t* order) {
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
   if (!th || !wpb || !order) return TVPD_ERR_INVALID_ARG;
   const Tile2D t = tile2d_for(make_layout(*shape));
   *th = t.th;
   *wpb = t.wpb;
   *order = t.order;
+  return TVPD_OK;
+}
+
+int tvpd_set_tile3d(const tvpd_shape* shape, int32_t th, int32_t tz,
+                    int32_t wpb) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (shape->ndim != 3) return TVPD_ERR_UNSUPPORTED;
+  Tile3D t;
+  t.th = th;
+  t.tz = tz;
+  t.wpb = wpb;
+  if (!tile3d_ok(t) || tz > 65536) return TVPD_ERR_INVALID_ARG;
+  remember_tile3d(*shape, t);
+  return TVPD_OK;
+}
+
+int tvpd_get_tile3d(const tvpd_shape* shape, int32_t* th, int32_t* tz,
+                    int32_t* wpb) {
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (shape->ndim != 3) return TVPD_ERR_UNSUPPORTED;
+  if (!th || !tz || !wpb) return TVPD_ERR_INVALID_ARG;
+  const Tile3D t = tile3d_for(make_layout(*shape));
+  *th = t.th;
+  *tz = t.tz;
+  *wpb = t.wpb;
   return TVPD_OK;
 }
 
@@ -410,7 +457,20 @@ int tvpd_autotune(const tvpd_shape* shape, void* ws, size_t ws_bytes,
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
   const Layout L = make_layout(*shape);
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
-  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  if (shape->ndim == 3) {
+    Tile3D best;
+    float best_us = 0.0f;
+    if (int rc = autotune3d(*shape, L, ws, (hipStream_t)stream, &best, &best_us))
+      return rc;
+    if (cache_path) {
+      if (int rc = tune_save3d(cache_path, *shape, best, best_us)) return rc;
+    }
+    if (th) *th = best.th;
+    if (wpb) *wpb = best.wpb;
+    if (order) *order = best.tz;
+    if (us) *us = best_us;
+    return TVPD_OK;
+  }
   Tile2D best;
   float best_us = 0.0f;
   if (int rc = autotune2d(*shape, L, ws, (hipStream_t)stream, &best, &best_us))

@@ -16,8 +16,14 @@ struct TileEntry {
   Tile2D t;
 };
 
+struct TileEntry3 {
+  tvpd_shape s;
+  Tile3D t;
+};
+
 std::mutex g_mu;
 std::vector<TileEntry> g_table;
+std::vector<TileEntry3> g_table3;
 
 bool same(const tvpd_shape& a, const Layout& L) {
   return a.ndim == L.ndim && a.nz == L.nz && a.ny == L.ny && a.nx == L.nx;
@@ -84,6 +90,42 @@ void remember_tile2d(const tvpd_shape& s, const Tile2D& t) {
     }
   }
   g_table.push_back({s, t});
+}
+
+// Default 3D tile: bands of 4 rows, blocks of 4 waves, segments deep enough
+// for about 8 waves per CU (deeper segments re-read fewer prologue planes,
+// more waves hide more latency).
+Tile3D default_tile3d(const Layout& L) {
+  Tile3D t;
+  t.th = 4;
+  t.wpb = 4;
+  const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
+  const int64_t cols = ntx * ((L.ny + t.th - 1) / t.th);
+  const int64_t target_waves = 8LL * device_cus();
+  int64_t tz = (cols * L.nz + target_waves - 1) / target_waves;
+  if (tz < 4) tz = 4;
+  if (tz > L.nz) tz = L.nz;
+  t.tz = (int)tz;
+  return t;
+}
+
+Tile3D tile3d_for(const Layout& L) {
+  std::lock_guard<std::mutex> g(g_mu);
+  for (const TileEntry3& e : g_table3)
+    if (same(e.s, L)) return e.t;
+  return default_tile3d(L);
+}
+
+void remember_tile3d(const tvpd_shape& s, const Tile3D& t) {
+  std::lock_guard<std::mutex> g(g_mu);
+  for (TileEntry3& e : g_table3) {
+    if (e.s.ndim == s.ndim && e.s.nz == s.nz && e.s.ny == s.ny &&
+        e.s.nx == s.nx) {
+      e.t = t;
+      return;
+    }
+  }
+  g_table3.push_back({s, t});
 }
 
 // Time one tile: warm up, then enough launches for about 2 ms of work.  With
@@ -161,14 +203,100 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
   return TVPD_OK;
 }
 
+// Per-iteration time of one 3D tile (same scheme as time_tile).
+static int time_tile3d(const Layout& L, const Tile3D& t, void* ws,
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* us) {
+  tvpd_coeffs c;
+  c.lam = 0.1f;
+  c.tau = c.sigma = 0.28867513f;
+  c.theta = 1.0f;
+  if (sweep3d_blocks(L, t) > L.max_partials) return TVPD_ERR_INVALID_ARG;
+  for (int i = 0; i < 2; ++i)
+    if (launch_sweep3d(L, t, c, false, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+  int n = 2;
+  float ms = 0.0f;
+  for (int round = 0; round < 2; ++round) {
+    if (hipEventRecord(e0, s) != hipSuccess) return TVPD_ERR_HIP;
+    for (int i = 0; i < n; ++i)
+      if (launch_sweep3d(L, t, c, false, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+    if (hipEventRecord(e1, s) != hipSuccess) return TVPD_ERR_HIP;
+    if (hipEventSynchronize(e1) != hipSuccess) return TVPD_ERR_HIP;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TVPD_ERR_HIP;
+    if (round == 0) {
+      const float per = ms / n;
+      n = per > 0.0f ? (int)(2.0f / per) : 50;
+      if (n < 3) n = 3;
+      if (n > 200) n = 200;
+    }
+  }
+  *us = ms * 1000.0f / n;
+  return TVPD_OK;
+}
+
+int autotune3d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
+               Tile3D* best, float* best_us) {
+  if (launch_set_params(ws, 0x7fffffff, -1.0, s) != hipSuccess) return TVPD_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return TVPD_ERR_HIP;
+  static const int ths[] = {2, 4};
+  static const int tzs[] = {2, 4, 8, 16, 32, 64, 128};
+  static const int wpbs[] = {1, 2, 4};
+  float bu = 1e30f;
+  Tile3D bt = default_tile3d(L);
+  int rc = TVPD_OK;
+  for (int th : ths) {
+    for (int tz : tzs) {
+      if (tz > L.nz && tz != tzs[0]) break;
+      for (int w : wpbs) {
+        Tile3D t;
+        t.th = th;
+        t.tz = tz;
+        t.wpb = w;
+        float us = 0.0f;
+        rc = time_tile3d(L, t, ws, s, e0, e1, &us);
+        if (rc == TVPD_ERR_INVALID_ARG) {
+          rc = TVPD_OK;
+          continue;
+        }
+        if (rc) break;
+        if (us < bu) {
+          bu = us;
+          bt = t;
+        }
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  remember_tile3d(sh, bt);
+  *best = bt;
+  *best_us = bu;
+  return TVPD_OK;
+}
+
 // Cache file: one line per entry,
-//   <arch> <ndim> <nz> <ny> <nx> <th> <wpb> <order> <us>
+//   <arch> <ndim> <nz> <ny> <nx> <th> <wpb> <order> <us>      (ndim 2)
+//   <arch> <ndim> <nz> <ny> <nx> <th> <wpb> <tz> <us>         (ndim 3)
 int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t,
               float us) {
   FILE* f = std::fopen(path, "a");
   if (!f) return TVPD_ERR_INVALID_ARG;
   std::fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", device_arch().c_str(),
                s.ndim, s.nz, s.ny, s.nx, t.th, t.wpb, t.order, us);
+  std::fclose(f);
+  return TVPD_OK;
+}
+
+int tune_save3d(const char* path, const tvpd_shape& s, const Tile3D& t,
+                float us) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return TVPD_ERR_INVALID_ARG;
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %.3f\n", device_arch().c_str(),
+               s.ndim, s.nz, s.ny, s.nx, t.th, t.wpb, t.tz, us);
   std::fclose(f);
   return TVPD_OK;
 }
@@ -188,7 +316,17 @@ int tune_load(const char* path, int* count) {
                     &s.ny, &s.nx, &t.th, &t.wpb, &t.order, &us) != 9)
       continue;
     if (arch != a) continue;
-    if (t.th < 1 || (t.wpb != 1 && t.wpb != 2 && t.wpb != 4) ||
+    if (s.ndim == 3) {
+      Tile3D t3;
+      t3.th = t.th;
+      t3.wpb = t.wpb;
+      t3.tz = t.order;
+      if (!tile3d_ok(t3)) continue;
+      remember_tile3d(s, t3);
+      ++n;
+      continue;
+    }
+    if (s.ndim != 2 || t.th < 1 || (t.wpb != 1 && t.wpb != 2 && t.wpb != 4) ||
         (t.order != 0 && t.order != 1))
       continue;
     remember_tile2d(s, t);  // later lines override earlier ones

@@ -39,7 +39,7 @@ struct Layout {
   int nz, ny, nx;
   int pitch;              // floats per stored row (multiple of 4, >= nx)
   int64_t plane;          // floats per plane (multiple of 64)
-  int nplanes;            // 4 (f ring) + 3*ndim (dual ring) + 1 (g)
+  int nplanes;            // kPlainPlanes2D or kPlainPlanes3D
   int64_t max_partials;   // reduction slots (2 doubles each)
   size_t partial_off;     // byte offset of the partials
   size_t plane_off;       // byte offset of plane 0
@@ -56,6 +56,13 @@ constexpr int kPlainPlanes2D = 11;
 constexpr int kPlainG = 10;
 __host__ __device__ inline int plain_f(int k) { return ((k % 4) + 4) % 4; }
 __host__ __device__ inline int plain_p(int k) { return 4 + 2 * (k % 3); }
+
+// Plane block of the plain 3D solver: f^k in slot k mod 3 (planes 0..2),
+// p^k in slot k mod 2 (planes 3 + 3 (k mod 2), x, y, z), g in plane 9.
+constexpr int kPlainPlanes3D = 10;
+constexpr int kPlainG3D = 9;
+__host__ __device__ inline int plain3_f(int k) { return ((k % 3) + 3) % 3; }
+__host__ __device__ inline int plain3_p(int k) { return 3 + 3 * (k & 1); }
 
 // Tile configuration of the 2D sweep: each wave owns a strip of 256 columns
 // and a band of `th` rows; a block holds `wpb` consecutive wave tiles.
@@ -81,6 +88,28 @@ struct Sweep2DArgs {
   double* partials;   // 2 doubles per block (gap, P)
 };
 
+// Tile configuration of the 3D sweep: each wave owns a strip of 256 columns,
+// a band of `th` rows (2 or 4) and a segment of `tz` planes; a block holds
+// `wpb` consecutive wave tiles, numbered strip fastest, then band, then
+// segment.
+struct Tile3D {
+  int th;
+  int tz;
+  int wpb;
+};
+
+// Arguments of the fused 3D sweep kernel (passed by value).
+struct Sweep3DArgs {
+  float* base;
+  int64_t plane;
+  int32_t nz, ny, nx, pitch;
+  int32_t tz, wpb;
+  int32_t ntx, nty, ntz, ntiles;
+  float lam, tau, sigma, theta;
+  DevState* st;
+  double* partials;
+};
+
 // Host launchers (kernels2d.hip).
 hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
                          hipStream_t s);
@@ -94,6 +123,21 @@ hipError_t launch_energy2d(const Layout& L, float lam, void* ws,
 hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
                              hipStream_t s);
 int sweep2d_blocks(const Layout& L, const Tile2D& t);
+hipError_t launch_energy_final(const Layout& L, void* ws, int nparts,
+                               bool skip_if_converged, hipStream_t s);
+
+// Host launchers (kernels3d.hip).
+hipError_t launch_init3d(const Layout& L, const float* g, void* ws,
+                         hipStream_t s);
+hipError_t launch_sweep3d(const Layout& L, const Tile3D& t,
+                          const tvpd_coeffs& c, bool with_gap, void* ws,
+                          hipStream_t s);
+hipError_t launch_read3d(const Layout& L, const void* ws, float* f_out,
+                         float* p_out, hipStream_t s);
+hipError_t launch_energy3d(const Layout& L, float lam, void* ws,
+                           bool skip_if_converged, hipStream_t s);
+int sweep3d_blocks(const Layout& L, const Tile3D& t);
+bool tile3d_ok(const Tile3D& t);
 
 // Tile table and autotuner (autotune.hip).
 Tile2D default_tile2d(const Layout& L);
@@ -101,7 +145,14 @@ Tile2D tile2d_for(const Layout& L);
 void remember_tile2d(const tvpd_shape& s, const Tile2D& t);
 int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
                Tile2D* best, float* best_us);
+Tile3D default_tile3d(const Layout& L);
+Tile3D tile3d_for(const Layout& L);
+void remember_tile3d(const tvpd_shape& s, const Tile3D& t);
+int autotune3d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
+               Tile3D* best, float* best_us);
 int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t, float us);
+int tune_save3d(const char* path, const tvpd_shape& s, const Tile3D& t,
+                float us);
 int tune_load(const char* path, int* count);
 bool blocking_enabled();  // two-iteration passes in use (api.hip)
 

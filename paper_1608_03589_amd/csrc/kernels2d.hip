@@ -6,7 +6,7 @@
 // writes 12 (f^{k+1}, p^{k+1} x2).  The last block to finish advances the
 // iteration counter kept in device memory, or on a gap check reduces the
 // per-block partials in a fixed order and applies the stopping rule.
-#include "sync.h"
+#include "finish.h"
 #include "tile2d.h"
 #include "tile2d_x2.h"
 
@@ -14,59 +14,6 @@ namespace tvpd {
 namespace {
 
 using namespace dev;
-
-
-// Completion of a sweep: the last block to finish advances k, or on a gap
-// check reduces the per-block partials (fixed order, float64), records the
-// energies and either freezes k (converged) or advances it.
-template <bool GAP, int STEP>
-__device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
-                                             int k, double acc_gap,
-                                             double acc_P) {
-  __shared__ double red[2][kMaxBlock / kWave];
-  __shared__ int s_last;
-  const unsigned nb = gridDim.x;
-  if constexpr (GAP) {
-    block_sum2(acc_gap, acc_P, red);
-    if (threadIdx.x == 0) {
-      store_agent(&partials[2 * blockIdx.x], acc_gap);
-      store_agent(&partials[2 * blockIdx.x + 1], acc_P);
-    }
-  }
-  __syncthreads();  // every wave of the block has read k and finished
-  if (threadIdx.x == 0) {
-    __threadfence();
-    SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
-                                               kSyncOffset);
-    s_last = arrive_last(sa, nb) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if constexpr (!GAP) {
-    if (threadIdx.x == 0) st->k = k + STEP;
-  } else {
-    double sg = 0.0, sp = 0.0;
-    for (unsigned i = threadIdx.x; i < nb; i += blockDim.x) {
-      sg += load_agent(&partials[2 * i]);
-      sp += load_agent(&partials[2 * i + 1]);
-    }
-    block_sum2(sg, sp, red);
-    if (threadIdx.x == 0) {
-      st->gap = sg;
-      st->P = sp;
-      st->D = sp - sg;
-      st->checks += 1;
-      st->nblocks = (int)nb;
-      if (st->tol >= 0.0 && sg <= st->tol * sp) {
-        st->converged = 1;
-        st->iters = k;
-      } else {
-        st->k = k + STEP;
-      }
-    }
-  }
-}
 
 template <bool GAP>
 __global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
@@ -285,21 +232,6 @@ __global__ __launch_bounds__(kMaxBlock) void energy_final_kernel(
   }
 }
 
-inline DevState* state_of(void* ws) { return reinterpret_cast<DevState*>(ws); }
-
-inline float* planes_of(const Layout& L, void* ws) {
-  return reinterpret_cast<float*>(static_cast<char*>(ws) + L.plane_off);
-}
-
-inline double* partials_of(const Layout& L, void* ws) {
-  return reinterpret_cast<double*>(static_cast<char*>(ws) + L.partial_off);
-}
-
-inline int grid_for(int64_t n, int block, int cap = 8192) {
-  const int64_t b = (n + block - 1) / block;
-  return (int)(b < 1 ? 1 : (b > cap ? cap : b));
-}
-
 }  // namespace
 
 int sweep2d_blocks(const Layout& L, const Tile2D& t) {
@@ -368,6 +300,14 @@ hipError_t launch_read2d(const Layout& L, const void* ws, float* f_out,
   hipLaunchKernelGGL(read2d_kernel, dim3(grid_for((int64_t)L.ny * L.nx, 256)),
                      dim3(256), 0, s, planes_of(L, w), L.plane, L.ny, L.nx,
                      L.pitch, state_of(w), f_out, p_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_final(const Layout& L, void* ws, int nparts,
+                               bool skip_if_converged, hipStream_t s) {
+  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(kMaxBlock), 0, s,
+                     state_of(ws), partials_of(L, ws), nparts,
+                     skip_if_converged ? 1 : 0);
   return hipGetLastError();
 }
 

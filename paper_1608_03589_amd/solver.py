@@ -169,6 +169,20 @@ def get_tile(shape):
     return th.value, wpb.value, order.value
 
 
+def set_tile3d(shape, th: int, tz: int, wpb: int = 4):
+    """Force the 3D sweep tile for ``shape`` (nz, ny, nx) in this process:
+    rows per wave band (2 or 4), planes per wave segment, waves per block."""
+    call("tvpd_set_tile3d", C.byref(make_shape(shape)), int(th), int(tz),
+         int(wpb))
+
+
+def get_tile3d(shape):
+    th, tz, wpb = C.c_int32(), C.c_int32(), C.c_int32()
+    call("tvpd_get_tile3d", C.byref(make_shape(shape)), C.byref(th),
+         C.byref(tz), C.byref(wpb))
+    return th.value, tz.value, wpb.value
+
+
 def set_blocking(on: bool):
     """Two-iteration passes (temporal blocking) for the plain and batched 2D
     solvers on or off, process-wide; the iterates are the same either way."""
@@ -179,7 +193,8 @@ def autotune(shape, device="cuda", cache_path: str | None = None,
              g: torch.Tensor | None = None):
     """Time the candidate sweep tiles for ``shape`` and keep the fastest for
     this process (optionally appending it to ``cache_path``).  Returns
-    ``((th, wpb, order), microseconds_per_sweep)``."""
+    ``((th, wpb, order), microseconds_per_iteration)`` for a 2D shape and
+    ``((th, tz, wpb), microseconds_per_iteration)`` for a 3D one."""
     s = PlainSolver(shape, device)
     if g is None:
         g = torch.rand(s.shape, dtype=torch.float32, device=s.device)
@@ -190,6 +205,8 @@ def autotune(shape, device="cuda", cache_path: str | None = None,
          s.nbytes, cache_path.encode() if cache_path else None, C.byref(th),
          C.byref(wpb), C.byref(order), C.byref(us),
          C.c_void_p(_stream(s.device)))
+    if len(s.shape) == 3:
+        return (th.value, order.value, wpb.value), us.value
     return (th.value, wpb.value, order.value), us.value
 
 
