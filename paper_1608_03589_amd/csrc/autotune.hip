@@ -93,15 +93,15 @@ void remember_tile2d(const tvpd_shape& s, const Tile2D& t) {
 }
 
 // Default 3D tile: bands of 4 rows, blocks of 4 waves, segments deep enough
-// for about 8 waves per CU (deeper segments re-read fewer prologue planes,
-// more waves hide more latency).
+// for about 4 waves (one block) per CU: deeper segments re-read fewer
+// prologue planes, and the rolling prefetch of each wave hides the latency.
 Tile3D default_tile3d(const Layout& L) {
   Tile3D t;
   t.th = 4;
   t.wpb = 4;
   const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
   const int64_t cols = ntx * ((L.ny + t.th - 1) / t.th);
-  const int64_t target_waves = 8LL * device_cus();
+  const int64_t target_waves = 4LL * device_cus();
   int64_t tz = (cols * L.nz + target_waves - 1) / target_waves;
   if (tz < 4) tz = 4;
   if (tz > L.nz) tz = L.nz;

@@ -22,6 +22,7 @@
 #pragma once
 
 #include "common.h"
+#include "pointwise.h"
 
 namespace tvpd {
 namespace dev {
@@ -79,18 +80,12 @@ __device__ __forceinline__ RowP zeroP() {
   return r;
 }
 
-// Projection of q onto the disc of radius lam; |q| <= lam keeps q.
+// Projection of q onto the disc of radius lam (lam2 = lam * lam).
 __device__ __forceinline__ void project2(float qx, float qy, float lam,
-                                         float& px, float& py) {
-  const float n = sqrtf(qx * qx + qy * qy);
-  if (n > lam) {
-    const float s = lam / n;
-    px = qx * s;
-    py = qy * s;
-  } else {
-    px = qx;
-    py = qy;
-  }
+                                         float lam2, float& px, float& py) {
+  const float c = ball_scale(qx * qx + qy * qy, lam, lam2);
+  px = qx * c;
+  py = qy * c;
 }
 
 __device__ __forceinline__ float from_right(float v) {
@@ -188,7 +183,8 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
   const bool hr = (lane == kWave - 1) && (x0 + kStripCols < nx);
   const int xl = x0 - 1, xr = x0 + kStripCols;
   const float lam = c.lam, tau = c.tau, sig = c.sig, th = c.th;
-  const float opt = 1.0f + tau;
+  const float iopt = prox_factor(tau);
+  const float lam2 = lam * lam;
 
   // Row data.  In the steady state every lane issues every load (padding
   // lanes and the edge columns read clamped, valid addresses; their values
@@ -252,7 +248,7 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
             (j < 3) ? cb.v[(j + 1) & 3] : (lane == kWave - 1 ? rb : nbr);
         const float gx = (xc + j < nx - 1) ? right - cb.v[j] : 0.0f;
         const float gy = dn ? nb4.v[j] - cb.v[j] : 0.0f;
-        project2(opx.v[j] + sig * gx, opy.v[j] + sig * gy, lam, npx.v[j],
+        project2(opx.v[j] + sig * gx, opy.v[j] + sig * gy, lam, lam2, npx.v[j],
                  npy.v[j]);
       }
     }
@@ -264,7 +260,7 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
         const float gx = cb.v[0] - lb;
         const float gy = dn ? lnb - lb : 0.0f;
         float hx, hy;
-        project2(pc.lpx + sig * gx, pc.lpy + sig * gy, lam, hx, hy);
+        project2(pc.lpx + sig * gx, pc.lpy + sig * gy, lam, lam2, hx, hy);
         left_n = hx;
         left_o = pc.lpx;
       } else {
@@ -280,7 +276,7 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
         const float lp = (j == 0) ? left_n : npx.v[(j + 3) & 3];
         const float d = (npx.v[j] - lp) + (npy.v[j] - up_pyn.v[j]);
         const float v = cf.v[j] + tau * d;
-        fnew.v[j] = (v + tau * gg.v[j]) / opt;
+        fnew.v[j] = (v + tau * gg.v[j]) * iopt;
       }
       if (lin) {
         st4(fn + o, fnew);

@@ -44,18 +44,16 @@ struct Tile3DCtx {
   float lam, tau, sig, th;
 };
 
-// Projection of q onto the ball of radius lam; |q| <= lam keeps q.
+// Projection of q onto the ball of radius lam (lam2 = lam * lam).
 __device__ __forceinline__ void project3(float qx, float qy, float qz,
-                                         float lam, float& px, float& py,
-                                         float& pz) {
+                                         float lam, float lam2, float& px,
+                                         float& py, float& pz) {
   float n2 = qx * qx + qy * qy;
   n2 = n2 + qz * qz;
-  const float n = sqrtf(n2);
-  // q * 1 == q exactly, so the select equals keeping q inside the ball
-  const float s = (n > lam) ? lam / n : 1.0f;
-  px = qx * s;
-  py = qy * s;
-  pz = qz * s;
+  const float c = ball_scale(n2, lam, lam2);
+  px = qx * c;
+  py = qy * c;
+  pz = qz * c;
 }
 
 // f^k and f^{k-1} of one plane of the tile: rows y0-1 .. y0+TH (index r is
@@ -95,7 +93,8 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
   const bool lin = xc < c.pitch;
   const bool hl = x0 > 0;                       // a column x0-1 exists
   const float lam = c.lam, tau = c.tau, sig = c.sig, th = c.th;
-  const float opt = 1.0f + tau;
+  const float iopt = prox_factor(tau);
+  const float lam2 = lam * lam;
   const int xcl = min(xc, c.pitch - kColsPerLane);
   const int xlc = max(x0 - 1, 0);
   const int xrc = min(x0 + kStripCols, c.pitch - 1);
@@ -183,16 +182,17 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
           const float gy = dn ? db.v[j] - cb.v[j] : 0.0f;
           const float gz = zf ? zb.v[j] - cb.v[j] : 0.0f;
           project3(pc.px[r].v[j] + sig * gx, pc.py[r].v[j] + sig * gy,
-                   pc.pz[r].v[j] + sig * gz, lam, npx.v[j], npy.v[j],
+                   pc.pz[r].v[j] + sig * gz, lam, lam2, npx.v[j], npy.v[j],
                    npz.v[j]);
         }
         if (r > 0) {
           const int ri = r - 1;  // index among the band's rows
           if (own) {
-            // p_x^{k+1} of the column to the left: every lane evaluates it
-            // from the shared column values; lane 0 uses it
-            float hx, hy, hz;
-            {
+            // p_x^{k+1} of the column to the left (0 left of the image):
+            // every lane evaluates it from the shared column values, lane 0
+            // uses it; hl is the same for the whole wave
+            float left_n = from_left(npx.v[3]);
+            if (hl) {
               const float lb = cur.lf[r] + th * (cur.lf[r] - cur.lm[r]);
               const float ldb =
                   cur.lf[r + 1] + th * (cur.lf[r + 1] - cur.lm[r + 1]);
@@ -200,11 +200,13 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
               const float gx = cb.v[0] - lb;
               const float gy = dn ? ldb - lb : 0.0f;
               const float gz = zf ? lzb - lb : 0.0f;
+              float hx, hy, hz;
               project3(pc.lx[ri] + sig * gx, pc.ly[ri] + sig * gy,
-                       pc.lz[ri] + sig * gz, lam, hx, hy, hz);
+                       pc.lz[ri] + sig * gz, lam, lam2, hx, hy, hz);
+              if (lane == 0) left_n = hx;
+            } else if (lane == 0) {
+              left_n = 0.0f;
             }
-            float left_n = from_left(npx.v[3]);
-            if (lane == 0) left_n = hl ? hx : 0.0f;
             F4 fnew;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -212,7 +214,7 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
               float d = (npx.v[j] - lp) + (npy.v[j] - up.v[j]);
               d = d + (npz.v[j] - pzn[ri].v[j]);
               const float v = cur.f[r].v[j] + tau * d;
-              fnew.v[j] = (v + tau * pc.g[ri].v[j]) / opt;
+              fnew.v[j] = (v + tau * pc.g[ri].v[j]) * iopt;
             }
             if (lin) {
               const int64_t o = zo + (int64_t)y * P + xc;

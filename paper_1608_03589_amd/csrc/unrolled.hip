@@ -5,15 +5,15 @@
 //     fbar    = f^k + theta (f^k - f^{k-1})
 //     p^{k+1} = P_lam(p^k + sigma grad fbar)
 //     f^{k+1} = (f^k + tau div p^{k+1} + tau g) / (1 + tau)
-// 2D images use the fused tile sweep (tile2d.h); 3D volumes use two passes,
-// a forward-difference pass writing p^{k+1} and a backward-difference pass
-// writing f^{k+1}.
+// Both use the fused tile sweeps of the plain solver (tile2d.h, tile3d.h)
+// with the step's coefficients read from device memory.
 //
 // Adjoint step k (reverse-mode derivative of the forward step; a = dL/df^{k+1},
 // b = the part of dL/df^k collected from step k+1's extrapolation, r =
 // dL/dp^{k+1}), in two passes that recompute the forward quantities with the
 // forward's exact arithmetic, so the projection takes the same branch:
-//   pass A (forward differences):  alpha = a / (1 + tau);
+//   pass A (forward differences):  alpha = a / (1 + tau);  (times the
+//       reciprocal of 1 + tau, as in the forward's data prox)
 //       s = r - grad(tau alpha);  q = p^k + sigma grad fbar;  p^{k+1} = P(q);
 //       t = s where |q| <= lam, else (lam/|q|)(s - n (n.s)) with n = q/|q|;
 //       partial sums of  lambar = sum_{|q|>lam} n.s  and  sigmabar = sum t.grad fbar
@@ -25,6 +25,7 @@
 // Per-pixel kernels run one pixel per thread, rows of up to 256 pixels per
 // block; neighbour values are read directly (they are cache hits).
 #include "tile2d.h"
+#include "tile3d.h"
 #include "unrolled.h"
 
 namespace tvpd {
@@ -76,15 +77,9 @@ template <int ND>
 __device__ __forceinline__ void project(const float* q, float lam, float* p) {
   float n2 = q[0] * q[0] + q[1] * q[1];
   if (ND == 3) n2 = n2 + q[2] * q[2];
-  const float n = sqrtf(n2);
-  if (n > lam) {
-    const float s = lam / n;
+  const float c = ball_scale(n2, lam, lam * lam);
 #pragma unroll
-    for (int c = 0; c < ND; ++c) p[c] = q[c] * s;
-  } else {
-#pragma unroll
-    for (int c = 0; c < ND; ++c) p[c] = q[c];
-  }
+  for (int i = 0; i < ND; ++i) p[i] = q[i] * c;
 }
 
 // Strides along x, y, z of a pixel offset, and whether the pixel has a
@@ -178,40 +173,43 @@ __global__ __launch_bounds__(kMaxBlock) void u_sweep2d_kernel(
   sweep_tile<false>(c, sg, sp);
 }
 
-template <int ND>
-__global__ __launch_bounds__(kRowBlock) void u_dual_kernel(
+template <int TH>
+__global__ __launch_bounds__(kMaxBlock) void u_sweep3d_kernel(
     PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k,
-    float theta) {
-  const Pix q = pixel_of(P);
-  if (!q.ok) return;
-  int64_t st[3];
-  bool fwd[3], bwd[3];
-  axes<ND>(P, q, st, fwd, bwd);
-  const float lam = coeffs[3 * k], sig = coeffs[3 * k + 2];
-  float qq[ND], gfb[ND], pn[ND];
-  dual_point<ND>(cplane(P, q.b, ids.fk), cplane(P, q.b, ids.fkm),
-                 cplane(P, q.b, ids.pk), P.plane, q.o, st, fwd, sig, theta,
-                 qq, gfb);
-  project<ND>(qq, lam, pn);
-  float* out = plane(P, q.b, ids.pn);
-#pragma unroll
-  for (int c = 0; c < ND; ++c) out[c * P.plane + q.o] = pn[c];
-}
-
-template <int ND>
-__global__ __launch_bounds__(kRowBlock) void u_primal_kernel(
-    PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k) {
-  const Pix q = pixel_of(P);
-  if (!q.ok) return;
-  int64_t st[3];
-  bool fwd[3], bwd[3];
-  axes<ND>(P, q, st, fwd, bwd);
-  const float tau = coeffs[3 * k + 1];
-  const float d = div_point<ND>(cplane(P, q.b, ids.pn), P.plane, q.o, st, bwd);
-  const float f = cplane(P, q.b, ids.fk)[q.o];
-  const float g = cplane(P, q.b, 0)[q.o];
-  const float v = f + tau * d;
-  plane(P, q.b, ids.fn)[q.o] = (v + tau * g) / (1.0f + tau);
+    float theta, int tz, int wpb, int ntx, int nty, int ntiles) {
+  const int b = blockIdx.y;
+  const int wave = threadIdx.x / kWave;
+  const int nbx = gridDim.x, bx = blockIdx.x;
+  const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
+  const int wt = bt * wpb + wave;
+  if (wt >= ntiles) return;
+  const int per_seg = ntx * nty;
+  const int tzi = wt / per_seg;
+  const int rem = wt - tzi * per_seg;
+  const int ty = rem / ntx, tx = rem - ty * ntx;
+  Tile3DCtx c;
+  c.fk = cplane(P, b, ids.fk);
+  c.fkm = cplane(P, b, ids.fkm);
+  c.pk = cplane(P, b, ids.pk);
+  c.g = cplane(P, b, 0);
+  c.fn = plane(P, b, ids.fn);
+  c.pn = plane(P, b, ids.pn);
+  c.cs = P.plane;
+  c.nz = P.nz;
+  c.ny = P.ny;
+  c.nx = P.nx;
+  c.pitch = P.pitch;
+  c.x0 = tx * kStripCols;
+  c.y0 = ty * TH;
+  c.z0 = tzi * tz;
+  c.z1 = min(c.z0 + tz, P.nz);
+  c.lam = coeffs[3 * k];
+  c.tau = coeffs[3 * k + 1];
+  c.sig = coeffs[3 * k + 2];
+  c.th = theta;
+  double sg = 0.0, sp = 0.0;
+  sweep_tile3d<TH, false>(c, sg, sp);
 }
 
 // ----------------------------- adjoint ------------------------------------
@@ -236,14 +234,14 @@ __global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
     axes<ND>(P, q, st, fwd, bwd);
     const float lam = coeffs[3 * k], tau = coeffs[3 * k + 1],
                 sig = coeffs[3 * k + 2];
-    const float opt = 1.0f + tau;
+    const float iopt = prox_factor(tau);
     const float* a = cplane(P, q.b, ids.a_in);
     const float* r = cplane(P, q.b, ids.r_in);
-    const float ta0 = tau * (a[q.o] / opt);
+    const float ta0 = tau * (a[q.o] * iopt);
     float s[ND];
 #pragma unroll
     for (int c = 0; c < ND; ++c) {
-      const float gc = fwd[c] ? tau * (a[q.o + st[c]] / opt) - ta0 : 0.0f;
+      const float gc = fwd[c] ? tau * (a[q.o + st[c]] * iopt) - ta0 : 0.0f;
       s[c] = r[c * P.plane + q.o] - gc;
     }
     float qq[ND], gfb[ND], pn[ND];
@@ -253,17 +251,17 @@ __global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
     project<ND>(qq, lam, pn);
     float n2 = qq[0] * qq[0] + qq[1] * qq[1];
     if (ND == 3) n2 = n2 + qq[2] * qq[2];
-    const float nrm = sqrtf(n2);
     float t[ND];
-    if (nrm > lam) {
+    if (n2 > lam * lam) {  // the forward's branch (ball_scale)
+      const float rn = inv_norm(n2);
       float nv[ND];
       float ns = 0.0f;
 #pragma unroll
       for (int c = 0; c < ND; ++c) {
-        nv[c] = qq[c] / nrm;
+        nv[c] = qq[c] * rn;
         ns = (c == 0) ? nv[c] * s[c] : ns + nv[c] * s[c];
       }
-      const float sc = lam / nrm;
+      const float sc = lam * rn;
 #pragma unroll
       for (int c = 0; c < ND; ++c) t[c] = sc * (s[c] - nv[c] * ns);
       lb += ns;
@@ -301,14 +299,14 @@ __global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
     bool fwd[3], bwd[3];
     axes<ND>(P, q, st, fwd, bwd);
     const float tau = coeffs[3 * k + 1], sig = coeffs[3 * k + 2];
-    const float opt = 1.0f + tau;
+    const float iopt = prox_factor(tau);
     const float d =
         div_point<ND>(cplane(P, q.b, ids.pn), P.plane, q.o, st, bwd);
     const float f = cplane(P, q.b, ids.fk)[q.o];
     const float g = cplane(P, q.b, ids.g)[q.o];
     const float v = f + tau * d;
-    const float fn = (v + tau * g) / opt;
-    const float alpha = cplane(P, q.b, ids.a_in)[q.o] / opt;
+    const float fn = (v + tau * g) * iopt;
+    const float alpha = cplane(P, q.b, ids.a_in)[q.o] * iopt;
     float* gbar = plane(P, q.b, ids.gbar);
     gbar[q.o] = gbar[q.o] + tau * alpha;
     tb += (double)alpha * (((double)d + (double)g) - (double)fn);
@@ -443,11 +441,27 @@ hipError_t launch_u_step(const PlaneSet& P, const StepIds& ids,
     hipLaunchKernelGGL(u_sweep2d_kernel, dim3(nbx, P.nb), dim3(wpb * kWave), 0,
                        s, P, ids, coeffs, k, theta, (int)th, wpb, ntx, nty);
   } else {
-    const dim3 grid((unsigned)nrow_blocks(P));
-    hipLaunchKernelGGL(u_dual_kernel<3>, grid, dim3(kRowBlock), 0, s, P, ids,
-                       coeffs, k, theta);
-    hipLaunchKernelGGL(u_primal_kernel<3>, grid, dim3(kRowBlock), 0, s, P, ids,
-                       coeffs, k);
+    // the plain solver's tile for this volume shape
+    Layout L;
+    L.ndim = 3;
+    L.nz = P.nz;
+    L.ny = P.ny;
+    L.nx = P.nx;
+    const Tile3D t = tile3d_for(L);
+    if (!tile3d_ok(t)) return hipErrorInvalidValue;
+    const int ntx = (P.nx + kStripCols - 1) / kStripCols;
+    const int nty = (P.ny + t.th - 1) / t.th;
+    const int ntz = (P.nz + t.tz - 1) / t.tz;
+    const int64_t nt = (int64_t)ntx * nty * ntz;
+    if (nt > INT32_MAX / 2) return hipErrorInvalidValue;
+    const int nbx = (int)((nt + t.wpb - 1) / t.wpb);
+    const dim3 grid(nbx, P.nb), block(t.wpb * kWave);
+    if (t.th == 2)
+      hipLaunchKernelGGL(u_sweep3d_kernel<2>, grid, block, 0, s, P, ids,
+                         coeffs, k, theta, t.tz, t.wpb, ntx, nty, (int)nt);
+    else
+      hipLaunchKernelGGL(u_sweep3d_kernel<4>, grid, block, 0, s, P, ids,
+                         coeffs, k, theta, t.tz, t.wpb, ntx, nty, (int)nt);
   }
   return hipGetLastError();
 }
