@@ -9,7 +9,8 @@ memory and streams through PyTorch.
 from ._lib import TVPDError, lib  # noqa: F401
 from .batch import BatchedSolver  # noqa: F401
 from .unrolled import (  # noqa: F401
-    UnrolledSolver, UnrolledTV, default_coeffs, unrolled_tv,
+    UnrolledSolver, UnrolledTV, default_coeffs, set_fused_adjoint,
+    unrolled_tv,
 )
 from .solver import (  # noqa: F401
     PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
@@ -19,7 +20,8 @@ from .solver import (  # noqa: F401
 
 __all__ = [
     "BatchedSolver", "PlainSolver", "SolveResult", "TVPDError",
-    "UnrolledSolver", "UnrolledTV", "default_coeffs", "unrolled_tv",
+    "UnrolledSolver", "UnrolledTV", "default_coeffs", "set_fused_adjoint",
+    "unrolled_tv",
     "alloc_workspace", "autotune",
     "tune_load",
     "default_step", "get_tile", "get_tile3d", "lib", "make_shape",

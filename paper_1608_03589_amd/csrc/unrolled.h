@@ -48,5 +48,6 @@ hipError_t launch_u_adjoint(const PlaneSet& P, const AdjIds& ids,
 hipError_t launch_u_final_grad(const PlaneSet& P, int gbar, int a, int b,
                                float* grad_g, hipStream_t s);
 int64_t u_partials_needed(const PlaneSet& P);
+bool fused_adjoint_enabled();  // unrolled_api.hip
 
 }  // namespace tvpd

@@ -24,6 +24,7 @@
 //
 // Per-pixel kernels run one pixel per thread, rows of up to 256 pixels per
 // block; neighbour values are read directly (they are cache hits).
+#include "adj2d.h"
 #include "tile2d.h"
 #include "tile3d.h"
 #include "unrolled.h"
@@ -321,6 +322,62 @@ __global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
   if (threadIdx.x == 0) partials[blockIdx.x] = tb;
 }
 
+// Fused 2D adjoint step (adj2d.h): one pass over wave tiles of th rows; block
+// (bx, image b) writes its (lambar, sigmabar) partials to pa and its taubar
+// partial to pb at index b * gridDim.x + bx.
+__global__ __launch_bounds__(kMaxBlock) void u_adj2d_kernel(
+    PlaneSet P, AdjIds ids, const float* __restrict__ coeffs, int k,
+    float theta, int th_rows, int wpb, int ntx, int nty,
+    double* __restrict__ pa, double* __restrict__ pb) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  const int b = blockIdx.y;
+  const int wave = threadIdx.x / kWave;
+  const int nbx = gridDim.x, bx = blockIdx.x;
+  const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
+  const int wt = bt * wpb + wave;
+  double l = 0.0, sg = 0.0, t = 0.0;
+  if (wt < ntx * nty) {
+    const int ty = wt / ntx, tx = wt - ty * ntx;
+    AdjCtx2D c;
+    c.fk = cplane(P, b, ids.fk);
+    c.fkm = cplane(P, b, ids.fkm);
+    c.px = cplane(P, b, ids.pk);
+    c.py = cplane(P, b, ids.pk + 1);
+    c.g = cplane(P, b, ids.g);
+    c.a = cplane(P, b, ids.a_in);
+    c.b = cplane(P, b, ids.b_in);
+    c.rx = cplane(P, b, ids.r_in);
+    c.ry = cplane(P, b, ids.r_in + 1);
+    c.ao = plane(P, b, ids.a_out);
+    c.bo = plane(P, b, ids.b_out);
+    c.tx = plane(P, b, ids.t_out);
+    c.ty = plane(P, b, ids.t_out + 1);
+    c.gbar = plane(P, b, ids.gbar);
+    c.ny = P.ny;
+    c.nx = P.nx;
+    c.pitch = P.pitch;
+    c.x0 = tx * kStripCols;
+    c.y0 = ty * th_rows;
+    c.y1 = min(c.y0 + th_rows, P.ny);
+    c.lam = coeffs[3 * k];
+    c.tau = coeffs[3 * k + 1];
+    c.sig = coeffs[3 * k + 2];
+    c.th = theta;
+    adj_tile2d(c, l, sg, t);
+  }
+  block_sum2(l, sg, red);
+  __syncthreads();
+  double unused = 0.0;
+  block_sum2(t, unused, red);
+  if (threadIdx.x == 0) {
+    const int64_t i = (int64_t)b * nbx + bx;
+    pa[2 * i] = l;
+    pa[2 * i + 1] = sg;
+    pb[i] = t;
+  }
+}
+
 // grad_coeffs[k] = (lambar, taubar, sigmabar) from the block partials of the
 // two adjoint passes, summed in a fixed order.
 __global__ __launch_bounds__(kMaxBlock) void u_coeff_reduce_kernel(
@@ -489,6 +546,27 @@ hipError_t launch_u_adjoint(const PlaneSet& P, const AdjIds& ids,
   double* pa = partials;
   double* pb = partials + 2 * nblk;
   const dim3 grid((unsigned)nblk);
+  if (P.ndim == 2 && fused_adjoint_enabled()) {
+    // bands for about one block of four waves per CU, and at most nblk
+    // blocks in all
+    const int wpb = 4;
+    const int64_t ntx = (P.nx + kStripCols - 1) / kStripCols;
+    const int64_t cols = ntx * P.ny * P.nb;
+    int64_t th = (cols + 1023) / 1024;
+    const int64_t th_min = (cols + nblk * wpb - 1) / (nblk * wpb);
+    if (th < th_min) th = th_min;
+    if (th < 8) th = 8;
+    const int nty = (int)((P.ny + th - 1) / th);
+    const int nbx = (int)((ntx * nty + wpb - 1) / wpb);
+    const int64_t nb_total = (int64_t)nbx * P.nb;
+    if (nb_total > nblk) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(u_adj2d_kernel, dim3(nbx, P.nb), dim3(wpb * kWave), 0,
+                       s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx,
+                       nty, pa, pb);
+    hipLaunchKernelGGL(u_coeff_reduce_kernel, dim3(1), dim3(kMaxBlock), 0, s,
+                       pa, pb, (int)nb_total, grad_coeffs, k);
+    return hipGetLastError();
+  }
   if (P.ndim == 2) {
     hipLaunchKernelGGL(u_adjA_kernel<2>, grid, dim3(kRowBlock), 0, s, P, ids,
                        coeffs, k, theta, pa);

@@ -16,12 +16,16 @@
 //   p^s          : checkpoint j (segment 0: the zero planes)
 //   p^e          : checkpoint j+1, or a discard slot when e = K
 // so no state is ever copied.
+#include <atomic>
 #include <cmath>
 
 #include "unrolled.h"
 
 namespace tvpd {
 namespace {
+
+// 2D adjoint steps as one fused pass (default) or as the two-pass reference.
+std::atomic<int> g_fused_adjoint{1};
 
 struct UPlan {
   int ndim, K, C, ncp;
@@ -153,6 +157,9 @@ int run_steps(const UPlan& p, const PlaneSet& P, int j, int k_from, int k_to,
 }
 
 }  // namespace
+
+bool fused_adjoint_enabled() { return g_fused_adjoint.load() != 0; }
+
 }  // namespace tvpd
 
 using namespace tvpd;
@@ -235,6 +242,12 @@ int tvpd_unrolled_backward(const tvpd_shape* shape, int32_t batch,
     }
   }
   UHIP(launch_u_final_grad(P, p.GBAR, p.A + ph, p.B + ph, grad_g, s));
+  return TVPD_OK;
+}
+
+int tvpd_set_fused_adjoint(int32_t on) {
+  if (on != 0 && on != 1) return TVPD_ERR_INVALID_ARG;
+  g_fused_adjoint.store(on);
   return TVPD_OK;
 }
 

@@ -22,6 +22,12 @@ def _shape_of(g: torch.Tensor) -> Shape:
     return make_shape(tuple(g.shape[1:]))
 
 
+def set_fused_adjoint(on: bool):
+    """2D adjoint steps as one fused pass (the default) or as the two-pass
+    reference; both give the same dL/dg bit for bit.  Process-wide."""
+    call("tvpd_set_fused_adjoint", 1 if on else 0)
+
+
 def default_coeffs(K: int, ndim: int, lam: float = 0.1, device="cuda"):
     s = default_step(ndim)
     c = torch.tensor([[lam, s, s]], dtype=torch.float32, device=device)

@@ -71,6 +71,31 @@ def test_unrolled_2d_parity(shape, K, ckpt):
     assert rel(gc, gc_ref) <= 1e-4
 
 
+@pytest.mark.parametrize("shape,K,ckpt", [((2, 37, 301), 6, 3),
+                                          ((1, 130, 520), 5, 5),
+                                          ((3, 9, 17), 4, 2),
+                                          ((1, 1, 260), 3, 3)])
+def test_fused_adjoint_equals_two_pass_adjoint(shape, K, ckpt):
+    """The single-pass 2D adjoint and the two-pass reference give the same
+    dL/dg bit for bit; the coefficient gradients differ only in the order of
+    their float64 sums."""
+    print(f"case: fused vs two-pass adjoint {shape} K={K}", flush=True)
+    _, g = batch2d(*shape, seed=900)
+    c = coeffs_for(K, 2, 9)
+    grad_f = np.random.default_rng(10).normal(size=g.shape).astype(np.float32)
+    out = []
+    for fused in (True, False):
+        tv.set_fused_adjoint(fused)
+        try:
+            out.append(run_gpu(g, c, ckpt, grad_f))
+        finally:
+            tv.set_fused_adjoint(True)
+    (f1, gg1, gc1), (f2, gg2, gc2) = out
+    assert np.array_equal(f1, f2)
+    assert np.array_equal(gg1, gg2)
+    assert np.allclose(gc1, gc2, rtol=1e-5, atol=1e-7 * np.abs(gc2).max())
+
+
 def test_unrolled_3d_parity():
     print("case: unrolled 3d", flush=True)
     vols = [scene3d(10, 12, 13, 5, 0.1, 900 + i)[1] for i in range(2)]
