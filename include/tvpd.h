@@ -292,13 +292,13 @@ int tvpd_unrolled_backward(const tvpd_shape* shape, int32_t batch,
                            float* grad_coeffs, void* ws, size_t ws_bytes,
                            void* stream);
 
-/* 2D adjoint steps: with on = 1 (the default) each step is one fused pass
- * over the data (reads f^k, f^{k-1}, p^k, g, a, b, r, gbar; writes a', b',
- * r', gbar: 60 bytes per pixel); with on = 0 it is a forward-difference pass
- * that stores p^{k+1} and t followed by a backward-difference pass (92
- * bytes per pixel).  Both give the same a', b', r' and dL/dg bit for bit;
- * the coefficient gradients differ only in summation order.  3D steps always
- * use the two passes.  Process-wide setting. */
+/* Adjoint steps of the unrolled solver: with on = 1 (the default) each step
+ * is one fused pass over the data (reads f^k, f^{k-1}, p^k, g, a, b, r,
+ * gbar; writes a', b', r', gbar: 60 bytes per pixel in 2D, 72 per voxel in
+ * 3D); with on = 0 it is a forward-difference pass that stores p^{k+1} and t
+ * followed by a backward-difference pass (92 / 116 bytes).  Both give the
+ * same a', b', r' and dL/dg bit for bit; the coefficient gradients differ
+ * only in summation order.  Process-wide setting. */
 int tvpd_set_fused_adjoint(int32_t on);
 
 #ifdef __cplusplus

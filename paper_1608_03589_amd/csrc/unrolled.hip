@@ -25,6 +25,7 @@
 // Per-pixel kernels run one pixel per thread, rows of up to 256 pixels per
 // block; neighbour values are read directly (they are cache hits).
 #include "adj2d.h"
+#include "adj3d.h"
 #include "tile2d.h"
 #include "tile3d.h"
 #include "unrolled.h"
@@ -378,6 +379,65 @@ __global__ __launch_bounds__(kMaxBlock) void u_adj2d_kernel(
   }
 }
 
+// Fused 3D adjoint step (adj3d.h), tiles of 2 rows by tz planes; partials as
+// in u_adj2d_kernel.
+__global__ __launch_bounds__(kMaxBlock) void u_adj3d_kernel(
+    PlaneSet P, AdjIds ids, const float* __restrict__ coeffs, int k,
+    float theta, int tz, int wpb, int ntx, int nty, int ntiles,
+    double* __restrict__ pa, double* __restrict__ pb) {
+  constexpr int TH = 2;
+  __shared__ double red[2][kMaxBlock / kWave];
+  const int b = blockIdx.y;
+  const int wave = threadIdx.x / kWave;
+  const int nbx = gridDim.x, bx = blockIdx.x;
+  const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
+  const int wt = bt * wpb + wave;
+  double l = 0.0, sg = 0.0, t = 0.0;
+  if (wt < ntiles) {
+    const int per_seg = ntx * nty;
+    const int tzi = wt / per_seg;
+    const int rem = wt - tzi * per_seg;
+    const int ty = rem / ntx, tx = rem - ty * ntx;
+    AdjCtx3D c;
+    c.fk = cplane(P, b, ids.fk);
+    c.fkm = cplane(P, b, ids.fkm);
+    c.pk = cplane(P, b, ids.pk);
+    c.g = cplane(P, b, ids.g);
+    c.a = cplane(P, b, ids.a_in);
+    c.b = cplane(P, b, ids.b_in);
+    c.r = cplane(P, b, ids.r_in);
+    c.ao = plane(P, b, ids.a_out);
+    c.bo = plane(P, b, ids.b_out);
+    c.t = plane(P, b, ids.t_out);
+    c.gbar = plane(P, b, ids.gbar);
+    c.cs = P.plane;
+    c.nz = P.nz;
+    c.ny = P.ny;
+    c.nx = P.nx;
+    c.pitch = P.pitch;
+    c.x0 = tx * kStripCols;
+    c.y0 = ty * TH;
+    c.z0 = tzi * tz;
+    c.z1 = min(c.z0 + tz, P.nz);
+    c.lam = coeffs[3 * k];
+    c.tau = coeffs[3 * k + 1];
+    c.sig = coeffs[3 * k + 2];
+    c.th = theta;
+    adj_tile3d<TH>(c, l, sg, t);
+  }
+  block_sum2(l, sg, red);
+  __syncthreads();
+  double unused = 0.0;
+  block_sum2(t, unused, red);
+  if (threadIdx.x == 0) {
+    const int64_t i = (int64_t)b * nbx + bx;
+    pa[2 * i] = l;
+    pa[2 * i + 1] = sg;
+    pb[i] = t;
+  }
+}
+
 // grad_coeffs[k] = (lambar, taubar, sigmabar) from the block partials of the
 // two adjoint passes, summed in a fixed order.
 __global__ __launch_bounds__(kMaxBlock) void u_coeff_reduce_kernel(
@@ -563,6 +623,30 @@ hipError_t launch_u_adjoint(const PlaneSet& P, const AdjIds& ids,
     hipLaunchKernelGGL(u_adj2d_kernel, dim3(nbx, P.nb), dim3(wpb * kWave), 0,
                        s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx,
                        nty, pa, pb);
+    hipLaunchKernelGGL(u_coeff_reduce_kernel, dim3(1), dim3(kMaxBlock), 0, s,
+                       pa, pb, (int)nb_total, grad_coeffs, k);
+    return hipGetLastError();
+  }
+  if (P.ndim == 3 && fused_adjoint_enabled()) {
+    // bands of 2 rows; segments deep enough for about 4 waves per CU (at
+    // most nblk blocks in all)
+    const int wpb = 4, th = 2;
+    const int64_t ntx = (P.nx + kStripCols - 1) / kStripCols;
+    const int64_t nty = (P.ny + th - 1) / th;
+    const int64_t cols = ntx * nty * P.nb;
+    int64_t tz = (cols * P.nz + 1023) / 1024;
+    const int64_t tz_min = (cols * P.nz + nblk * wpb - 1) / (nblk * wpb);
+    if (tz < tz_min) tz = tz_min;
+    if (tz < 4) tz = 4;
+    if (tz > P.nz) tz = P.nz;
+    const int64_t ntz = (P.nz + tz - 1) / tz;
+    const int64_t nt = ntx * nty * ntz;
+    const int nbx = (int)((nt + wpb - 1) / wpb);
+    const int64_t nb_total = (int64_t)nbx * P.nb;
+    if (nb_total > nblk || nt > INT32_MAX / 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(u_adj3d_kernel, dim3(nbx, P.nb), dim3(wpb * kWave), 0,
+                       s, P, ids, coeffs, k, theta, (int)tz, wpb, (int)ntx,
+                       (int)nty, (int)nt, pa, pb);
     hipLaunchKernelGGL(u_coeff_reduce_kernel, dim3(1), dim3(kMaxBlock), 0, s,
                        pa, pb, (int)nb_total, grad_coeffs, k);
     return hipGetLastError();

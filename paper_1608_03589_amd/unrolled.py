@@ -23,7 +23,7 @@ def _shape_of(g: torch.Tensor) -> Shape:
 
 
 def set_fused_adjoint(on: bool):
-    """2D adjoint steps as one fused pass (the default) or as the two-pass
+    """Adjoint steps as one fused pass (the default) or as the two-pass
     reference; both give the same dL/dg bit for bit.  Process-wide."""
     call("tvpd_set_fused_adjoint", 1 if on else 0)
 

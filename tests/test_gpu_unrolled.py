@@ -96,6 +96,28 @@ def test_fused_adjoint_equals_two_pass_adjoint(shape, K, ckpt):
     assert np.allclose(gc1, gc2, rtol=1e-5, atol=1e-7 * np.abs(gc2).max())
 
 
+@pytest.mark.parametrize("shape,K,ckpt", [((1, 9, 14, 300), 4, 2),
+                                          ((2, 13, 7, 20), 5, 5),
+                                          ((1, 40, 6, 9), 3, 3)])
+def test_fused_adjoint_equals_two_pass_adjoint_3d(shape, K, ckpt):
+    print(f"case: fused vs two-pass adjoint 3d {shape} K={K}", flush=True)
+    g = np.stack([scene3d(*shape[1:], 6, 0.1, 950 + i)[1]
+                  for i in range(shape[0])]).astype(np.float32)
+    c = coeffs_for(K, 3, 11)
+    grad_f = np.random.default_rng(12).normal(size=g.shape).astype(np.float32)
+    out = []
+    for fused in (True, False):
+        tv.set_fused_adjoint(fused)
+        try:
+            out.append(run_gpu(g, c, ckpt, grad_f))
+        finally:
+            tv.set_fused_adjoint(True)
+    (f1, gg1, gc1), (f2, gg2, gc2) = out
+    assert np.array_equal(f1, f2)
+    assert np.array_equal(gg1, gg2)
+    assert np.allclose(gc1, gc2, rtol=1e-5, atol=1e-7 * np.abs(gc2).max())
+
+
 def test_unrolled_3d_parity():
     print("case: unrolled 3d", flush=True)
     vols = [scene3d(10, 12, 13, 5, 0.1, 900 + i)[1] for i in range(2)]
