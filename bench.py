@@ -26,10 +26,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 BYTES_PER_PIXEL_ITER = 32      # 20 B read + 12 B written per pixel and sweep
-PASS_BYTES_PER_PIXEL = 36      # a two-iteration pass: 20 B read + 16 B written
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_x2_denoise4096_traffic.txt")
+PASS_BYTES_PER_PIXEL = 36      # a pass of n >= 2 iterations: 20 B read + 16 B written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_xs5_denoise4096_traffic.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1608_03589_amd", "csrc", f)
-               for f in ("kernels2d.hip", "tile2d.h", "tile2d_x2.h", "pointwise.h")]
+               for f in ("kernels2d.hip", "tile2d.h", "tile2d_xs.h", "pointwise.h")]
 
 
 def log(msg):
@@ -60,6 +60,29 @@ def read_traffic(pixels: int):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def pass_schedule(iters, check_every, depth):
+    """Iterations per launch of a solve, as the library schedules them: up
+    to `depth` per pass, a gap check only on a pass's first iteration."""
+    out, k = [], 0
+    while k < iters:
+        n = min(depth, iters - k)
+        if check_every > 0:
+            n = min(n, (k // check_every + 1) * check_every - k)
+        out.append(n)
+        k += n
+    return out
+
+
+def kernel_name(kernels, passes):
+    names = {1: "sweep2d_kernel", 2: "sweep2d_x2_kernel"}
+    parts = []
+    for n in kernels:
+        nm = names.get(n, f"sweep2d_xs_kernel<{n}>")
+        parts.append(f"{nm} ({n} iteration{'s' if n > 1 else ''} per launch, "
+                     f"{passes.count(n)} launches per solve)")
+    return "; ".join(parts) + "; the launch at each 10th iteration also reduces the gap"
 
 
 def cpu_baseline(g64, lam, s, budget_s=15.0, max_iter=30):
@@ -271,6 +294,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blocking", action="store_true",
                     help="one iteration per launch (no temporal blocking)")
+    ap.add_argument("--depth", type=int, default=None,
+                    help="longest pass in iterations per launch (default: the library's)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and unrolled workloads")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -295,6 +320,8 @@ def main():
     g32 = g.astype(np.float32)
     dev = torch.device("cuda:0")
     tv.set_blocking(not args.no_blocking)
+    if args.depth is not None and not args.no_blocking:
+        tv.set_pass_depth(args.depth)
     gt = torch.from_numpy(g32).to(dev)
     out = torch.empty_like(gt)
     solver = tv.PlainSolver((H, W), dev)
@@ -325,20 +352,24 @@ def main():
     ms_step = ms_total / args.steps
     pix = H * W
     mpix_its = pix * iters * args.steps / (ms_total * 1e-3) / 1e6
-    # Dominant kernel: the fused sweep.  With temporal blocking on (the
-    # default) every launch is a two-iteration pass (gap checks fall on even
-    # iterations), so a step is iters/2 launches of 2 pixel-iterations each.
-    its_per_launch = 2 if (iters % 2 == 0 and not args.no_blocking) else 1
-    launches = args.steps * iters // its_per_launch
+    # Dominant kernel: the fused sweep.  The solver runs the iterations as
+    # passes of up to `depth` iterations per launch, a pass ending before the
+    # next gap check (every 10 iterations); replay that schedule to count the
+    # launches (with depth 5: 400 launches of 5 iterations per solve).
+    depth = tv.get_pass_depth()
+    passes = pass_schedule(iters, 10, depth)
+    launches = args.steps * len(passes)
+    its_per_launch = iters / len(passes)
     launch_s = ms_total * 1e-3 / launches
     alg_bytes = BYTES_PER_PIXEL_ITER * pix * its_per_launch
     achieved = alg_bytes / launch_s / 1e9
-    # what the launch itself must move: a two-iteration pass reads f^k,
-    # f^{k-1}, p^k (2), g and writes f^{k+1}, f^{k+2}, p^{k+2} (2)
-    pass_bytes = (PASS_BYTES_PER_PIXEL if its_per_launch == 2
-                  else BYTES_PER_PIXEL_ITER) * pix
+    # what a launch itself must move: reads f^k, f^{k-1}, p^k (2), g, writes
+    # f^{k+n-1}, f^{k+n}, p^{k+n} (2); 32 B for a single iteration
+    pass_bytes = sum((PASS_BYTES_PER_PIXEL if n > 1 else BYTES_PER_PIXEL_ITER) * pix
+                     for n in passes) / len(passes)
     pass_achieved = pass_bytes / launch_s / 1e9
-    traffic = read_traffic(pix) if its_per_launch == 2 else None
+    kernels = sorted(set(passes))
+    traffic = read_traffic(pix) if kernels == [depth] else None
 
     if args.copy_calibration:
         n = 64 * 1024 * 1024  # 256 MiB of float32
@@ -391,6 +422,7 @@ def main():
             "tau_sigma": s,
             "tile": list(tv.get_tile((H, W))),
             "iterations_per_launch": its_per_launch,
+            "pass_depth": depth,
         },
         "roofline": {
             "bound": "hbm",
@@ -399,8 +431,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "basis": ("one-pass algorithmic bytes, 32 B per pixel-iteration; "
-                      "the two-iteration pass keeps f^{k+1}, p^{k+1} on chip, "
-                      "so this figure can exceed the peak"),
+                      "a pass of n iterations keeps the n-1 intermediate iterates "
+                      "on chip, so this figure can exceed the peak"),
             "pass_algorithmic_bytes_per_launch": pass_bytes,
             "pass_achieved_GBs": pass_achieved,
             "pass_frac": pass_achieved / HBM_PEAK_GBS,
@@ -408,9 +440,7 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_vs_algorithmic": (traffic / alg_bytes) if traffic else None,
             "hbm_achieved_GBs": (traffic / launch_s / 1e9) if traffic else None,
-            "kernel": ("sweep2d_x2_kernel (two fused iterations per launch; "
-                       "1 in 5 launches also reduces the gap)") if its_per_launch == 2 else
-                      "sweep2d_kernel (one fused iteration per launch; 1 in 10 also reduces the gap)",
+            "kernel": kernel_name(kernels, passes),
             "pixel_iterations_per_launch": pix * its_per_launch,
             "algorithmic_bytes_per_pixel_iteration": BYTES_PER_PIXEL_ITER,
             "algorithmic_bytes_per_launch": alg_bytes,

@@ -175,13 +175,18 @@ int tvpd_set_tile3d(const tvpd_shape* shape, int32_t th, int32_t tz,
 int tvpd_get_tile3d(const tvpd_shape* shape, int32_t* th, int32_t* tz,
                     int32_t* wpb);
 
-/* Temporal blocking of the plain and batched 2D solvers: with on = 1 (the default) the
- * iterations run as two-iteration passes (f^k, f^{k-1}, p^k, g read once,
- * f^{k+1}, f^{k+2}, p^{k+2} written once: 36 bytes per two pixel-iterations)
- * wherever no gap check falls on a pass's second iteration; with on = 0 every
- * launch is one iteration (32 bytes per pixel-iteration).  The iterates are
- * bit-identical either way.  Process-wide setting. */
+/* Temporal blocking of the 2D solvers.  The plain solver runs its
+ * iterations as passes of up to `depth` iterations per launch (f^k, f^{k-1},
+ * p^k, g read once; f^{k+n-1}, f^{k+n}, p^{k+n} written once: 36 bytes per n
+ * pixel-iterations, against 32 per pixel-iteration unblocked); a gap check
+ * only ever falls on a pass's first iteration, so passes end before the next
+ * check.  depth in 1 .. 6, default 5; the batched solver uses passes of 2
+ * whenever depth >= 2 and check_every is even or 0.  The iterates are
+ * bit-identical for every depth.  Process-wide setting.
+ * tvpd_set_blocking(0) is depth 1, tvpd_set_blocking(1) the default depth. */
 int tvpd_set_blocking(int32_t on);
+int tvpd_set_pass_depth(int32_t depth);
+int tvpd_get_pass_depth(int32_t* depth);
 
 /* Autotuner.  Times every candidate tile of the sweep on `ws`, an
  * initialised workspace of this shape, and keeps the fastest for `shape` in
@@ -211,17 +216,20 @@ int tvpd_tune_load(const char* cache_path, int32_t* count);
  * ------------------------------------------------------------------- */
 
 /* Driver and tiling of a batched solve.  mode 0: one persistent cooperative
- * launch runs every iteration (grid barriers between iterations, per-image
- * stopping on the device); mode 1: one launch per iteration, replayed from
- * HIP graphs of check_every iterations with the host polling a flag; mode 2:
- * plain launches, one per iteration (reference driver).  th: rows per wave
- * band (0 = the autotuned or default value); wpb: waves per block (0 =
- * autotuned or default, else 1, 2 or 4). */
+ * launch runs every iteration (grid barriers between passes, per-image
+ * stopping on the device); mode 1: one launch per pass, replayed from HIP
+ * graphs of whole check intervals with the host polling a flag; mode 2:
+ * plain launches, one per pass (reference driver).  Passes hold up to 4
+ * iterations (tvpd_set_pass_depth).  th: rows per wave band (0 = the
+ * autotuned or default value); wpb: waves per block (0 = autotuned or
+ * default, else 1, 2 or 4); th_short: rows per band of the second tile
+ * table, used once the running images no longer fill the grid (0 = default
+ * 8; at most th). */
 typedef struct tvpd_batch_opts {
   int32_t mode;
   int32_t th;
   int32_t wpb;
-  int32_t reserved;
+  int32_t th_short;
 } tvpd_batch_opts;
 
 /* Workspace bytes for a batch of n shapes (host arrays; ndim must be 2). */

@@ -37,7 +37,7 @@ class Params(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("th", C.c_int32), ("wpb", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("th_short", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -74,6 +74,8 @@ SIGNATURES = {
     "tvpd_get_tile": (C.c_int, [C.POINTER(Shape), C.POINTER(_I32), C.POINTER(_I32),
                                 C.POINTER(_I32)]),
     "tvpd_set_fused_adjoint": (C.c_int, [_I32]),
+    "tvpd_set_pass_depth": (C.c_int, [_I32]),
+    "tvpd_get_pass_depth": (C.c_int, [C.POINTER(_I32)]),
     "tvpd_set_tile3d": (C.c_int, [C.POINTER(Shape), _I32, _I32, _I32]),
     "tvpd_get_tile3d": (C.c_int, [C.POINTER(Shape), C.POINTER(_I32),
                                   C.POINTER(_I32), C.POINTER(_I32)]),

@@ -74,13 +74,13 @@ class BatchedSolver:
 
     def solve(self, images=None, lam=0.1, tau=None, sigma=None, theta=1.0,
               max_iter=20000, check_every=10, gap_tol=1e-4, mode="persistent",
-              th=0, wpb=0):
+              th=0, wpb=0, th_short=0):
         """Solve every image; ``images=None`` reuses the packed arena."""
         if images is not None:
             self.pack(images)
         prm = self._params(lam, tau, sigma, theta, max_iter, check_every, gap_tol)
         opts = BatchOpts(MODES[mode] if isinstance(mode, str) else int(mode),
-                         int(th), int(wpb), 0)
+                         int(th), int(wpb), int(th_short))
         res = (Result * self.n)()
         call("tvpd_solve_batched", self.n, self.cshapes, self.offsets,
              C.c_void_p(self.g_arena.data_ptr()), C.c_void_p(self.f_arena.data_ptr()),

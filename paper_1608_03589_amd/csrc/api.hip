@@ -68,7 +68,8 @@ Layout make_layout(const tvpd_shape& s) {
   L.nplanes = s.ndim == 2 ? kPlainPlanes2D : kPlainPlanes3D;
   // enough reduction slots for one block per (strip, row) and for the
   // one-pixel-per-thread energy kernel
-  const int64_t ntx = (s.nx + kStripCols - 1) / kStripCols;
+  // (the deepest passes own the narrowest strips)
+  const int64_t ntx = (s.nx + kXsOwnedMin - 1) / kXsOwnedMin;
   const int64_t a = ntx * (int64_t)s.ny * s.nz;
   const int64_t b = ((int64_t)s.nz * s.ny * s.nx + kMaxBlock - 1) / kMaxBlock;
   L.max_partials = (a > b ? a : b) + 1;
@@ -145,18 +146,19 @@ int enqueue_sweeps(const Layout& L, const tvpd_coeffs& c, int64_t k_first,
     return TVPD_OK;
   }
   const Tile2D t = tile2d_for(L);
+  const int depth = blocked ? pass_depth() : 1;
   int i = 0;
   while (i < n) {
     const int64_t kk = k_first + i;
     const bool gap = check_every > 0 && (kk % check_every) == 0;
-    const bool gap_next = check_every > 0 && ((kk + 1) % check_every) == 0;
-    if (blocked && n - i >= 2 && !gap_next) {
-      TVPD_HIP(launch_sweep2d(L, t, c, gap, true, ws, s));
-      i += 2;
-    } else {
-      TVPD_HIP(launch_sweep2d(L, t, c, gap, false, ws, s));
-      i += 1;
+    int64_t len = std::min<int64_t>(depth, n - i);
+    if (check_every > 0) {
+      // a check may only fall on the first iteration of a pass
+      const int64_t next = (kk / check_every + 1) * check_every;
+      len = std::min<int64_t>(len, next - kk);
     }
+    TVPD_HIP(launch_sweep2d(L, t, c, gap, (int)len, ws, s));
+    i += (int)len;
   }
   return TVPD_OK;
 }
@@ -178,13 +180,14 @@ hipError_t launch_read(const Layout& L, const void* ws, float* f_out,
                      : launch_read3d(L, ws, f_out, p_out, s);
 }
 
-// Two-iteration passes (temporal blocking) are on unless switched off for
-// this process by tvpd_set_blocking(0).
-std::atomic<int> g_blocking{1};
+// Longest pass of the temporally blocked 2D sweep, process-wide
+// (tvpd_set_pass_depth; tvpd_set_blocking(0) means 1).
+constexpr int kDefaultDepth = 5;
+std::atomic<int> g_depth{kDefaultDepth};
 
 }  // namespace
 
-bool blocking_enabled() { return g_blocking.load() != 0; }
+int pass_depth() { return g_depth.load(); }
 
 namespace {
 
@@ -199,7 +202,7 @@ int solve_plain(const Layout& L, const float* g, float* f_out,
 
   const int ce = prm.check_every;
   const bool can_stop = ce > 0 && prm.gap_tol >= 0.0;
-  const bool blocked = g_blocking.load() != 0;
+  const bool blocked = pass_depth() > 1;
   // chunk of iterations between host polls: a multiple of check_every
   int chunk = 64;
   if (ce > 0) chunk = ce * ((64 + ce - 1) / ce);
@@ -341,7 +344,7 @@ int tvpd_step(const tvpd_shape* shape, const tvpd_coeffs* c, int32_t n_iter,
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
   hipStream_t s = (hipStream_t)stream;
   TVPD_HIP(launch_set_params(ws, INT_MAX, -1.0, s));
-  return enqueue_sweeps(L, *c, 0, n_iter, 0, g_blocking.load() != 0, ws, s);
+  return enqueue_sweeps(L, *c, 0, n_iter, 0, pass_depth() > 1, ws, s);
 }
 
 int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
@@ -495,7 +498,19 @@ int tvpd_tune_load(const char* cache_path, int32_t* count) {
 
 int tvpd_set_blocking(int32_t on) {
   if (on != 0 && on != 1) return TVPD_ERR_INVALID_ARG;
-  g_blocking.store(on);
+  g_depth.store(on ? kDefaultDepth : 1);
+  return TVPD_OK;
+}
+
+int tvpd_set_pass_depth(int32_t depth) {
+  if (depth < 1 || depth > kMaxPass) return TVPD_ERR_INVALID_ARG;
+  g_depth.store(depth);
+  return TVPD_OK;
+}
+
+int tvpd_get_pass_depth(int32_t* depth) {
+  if (!depth) return TVPD_ERR_INVALID_ARG;
+  *depth = g_depth.load();
   return TVPD_OK;
 }
 

@@ -58,14 +58,18 @@ std::string device_arch() {
 }  // namespace
 
 // Default: blocks of 4 side-by-side waves, bands tall enough that the grid
-// is about one block per compute unit.  Few concurrent row streams keep HBM
-// pages open; one block per CU keeps the CUs evenly loaded.
+// is about one and a half blocks per compute unit for the strips of the
+// deepest pass in use.  Few concurrent row streams keep HBM pages open; the
+// deep passes have 2 waves per SIMD resident and need that many to hide
+// their latency.
 Tile2D default_tile2d(const Layout& L) {
   Tile2D t;
   t.wpb = 4;
   t.order = 0;
-  const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
-  const int64_t target_waves = 4LL * device_cus();
+  const int depth = pass_depth();
+  const int strip = depth >= 3 ? xs_owned(depth) : kStripCols;
+  const int64_t ntx = (L.nx + strip - 1) / strip;
+  const int64_t target_waves = (depth >= 3 ? 6LL : 4LL) * device_cus();
   int64_t th = (ntx * L.ny + target_waves - 1) / target_waves;
   if (th < 8) th = 8;
   if (th > 256) th = 256;
@@ -128,34 +132,34 @@ void remember_tile3d(const tvpd_shape& s, const Tile3D& t) {
   g_table3.push_back({s, t});
 }
 
-// Time one tile: warm up, then enough launches for about 2 ms of work.  With
-// `two`, launches are two-iteration passes; the result is per iteration.
-static int time_tile(const Layout& L, const Tile2D& t, bool two, void* ws,
+// Time one tile: warm up, then enough launches for about 2 ms of work, each
+// a pass of n iterations; the result is per iteration.
+static int time_tile(const Layout& L, const Tile2D& t, int n, void* ws,
                      hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* us) {
   tvpd_coeffs c;
   c.lam = 0.1f;
   c.tau = c.sigma = 0.35355339f;
   c.theta = 1.0f;
-  if (sweep2d_blocks(L, t) > L.max_partials) return TVPD_ERR_INVALID_ARG;
+  if (sweep2d_blocks(L, t, n) > L.max_partials) return TVPD_ERR_INVALID_ARG;
   for (int i = 0; i < 2; ++i)
-    if (launch_sweep2d(L, t, c, false, two, ws, s) != hipSuccess) return TVPD_ERR_HIP;
-  int n = 2;
+    if (launch_sweep2d(L, t, c, false, n, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+  int reps = 2;
   float ms = 0.0f;
   for (int round = 0; round < 2; ++round) {
     if (hipEventRecord(e0, s) != hipSuccess) return TVPD_ERR_HIP;
-    for (int i = 0; i < n; ++i)
-      if (launch_sweep2d(L, t, c, false, two, ws, s) != hipSuccess) return TVPD_ERR_HIP;
+    for (int i = 0; i < reps; ++i)
+      if (launch_sweep2d(L, t, c, false, n, ws, s) != hipSuccess) return TVPD_ERR_HIP;
     if (hipEventRecord(e1, s) != hipSuccess) return TVPD_ERR_HIP;
     if (hipEventSynchronize(e1) != hipSuccess) return TVPD_ERR_HIP;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TVPD_ERR_HIP;
     if (round == 0) {
-      const float per = ms / n;
-      n = per > 0.0f ? (int)(2.0f / per) : 50;
-      if (n < 3) n = 3;
-      if (n > 200) n = 200;
+      const float per = ms / reps;
+      reps = per > 0.0f ? (int)(2.0f / per) : 50;
+      if (reps < 3) reps = 3;
+      if (reps > 200) reps = 200;
     }
   }
-  *us = ms * 1000.0f / n / (two ? 2.0f : 1.0f);
+  *us = ms * 1000.0f / reps / (float)n;
   return TVPD_OK;
 }
 
@@ -179,7 +183,7 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
         t.wpb = w;
         t.order = order;
         float us = 0.0f;
-        rc = time_tile(L, t, blocking_enabled(), ws, s, e0, e1, &us);
+        rc = time_tile(L, t, pass_depth(), ws, s, e0, e1, &us);
         if (rc == TVPD_ERR_INVALID_ARG) {
           rc = TVPD_OK;
           continue;

@@ -53,8 +53,31 @@ struct BatchArgs {
   int32_t max_iter, check_every;
   int32_t wpb;
   int32_t switch_tiles;  // use short bands once fewer tall tiles are active
-  int32_t blocked;       // two-iteration passes (check_every even or 0)
+  int32_t depth;         // longest pass (iterations per sweep), 1 .. kBatchMaxPass
 };
+
+// Longest batch pass: deeper passes would raise the register count of the
+// drivers (which contain every pass length) above two waves per SIMD.
+constexpr int kBatchMaxPass = 4;
+
+// Batch tiles: 256-column strips that own their middle kBatchStrip columns
+// (margins of kBatchMargin >= every pass length, tile2d_xs.h).
+constexpr int kBatchMargin = 8;
+constexpr int kBatchStrip = kStripCols - 2 * kBatchMargin;
+static_assert(kBatchMargin >= kMaxPass, "batch strip margin");
+
+// Iterations of the pass that starts at iteration k: at most `depth`, never
+// past max_iter, and ending before the next gap check (a check falls on the
+// first iteration of a pass only).
+__host__ __device__ inline int batch_pass_len(int k, int max_iter, int ce,
+                                              int depth) {
+  int n = max_iter - k < depth ? max_iter - k : depth;
+  if (ce > 0) {
+    const int to_check = (k / ce + 1) * ce - k;
+    if (to_check < n) n = to_check;
+  }
+  return n;
+}
 
 constexpr int kFinalBlocks = 32;  // blocks per image of the final pass
 
@@ -64,7 +87,7 @@ int batch_persistent_grid(int wpb);
 hipError_t launch_batch_persistent(const BatchArgs& a, int grid,
                                    hipStream_t s);
 hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
-                              bool two, hipStream_t s);
+                              int n, hipStream_t s);
 hipError_t launch_batch_final(const BatchArgs& a, float* f_out,
                               const int64_t* offs_dev, hipStream_t s);
 int batch_max_blocks_per_cu(int wpb);

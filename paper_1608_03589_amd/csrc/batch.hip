@@ -19,7 +19,7 @@
 #include "batch.h"
 #include "sync.h"
 #include "tile2d.h"
-#include "tile2d_x2.h"
+#include "tile2d_xs.h"
 
 namespace tvpd {
 namespace {
@@ -70,62 +70,52 @@ __device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
   return s_ok != 0;
 }
 
-// Sweep one tile: one iteration k -> k+1, or with `two` the two-iteration
-// pass k -> k+2 (tile2d_x2.h); on check iterations lane 0 stores the tile's
+// Sweep one tile by a pass of n iterations k -> k+n (tile2d_xs.h, strips of
+// kBatchStrip owned columns); on check iterations lane 0 stores the tile's
 // partials (the gap of (f^k, p^k)).  Plane block of an image: the plain
-// solver's 11-plane layout (f ring of 4, dual ring of 3, g).
-template <bool CHECK>
-__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
-                                        bool two) {
-  const TileDesc T = a.tiles[t];
+// solver's layout (f ring, dual ring, g).
+template <int N, bool CHECK>
+__device__ __forceinline__ void tile_pass(const BatchArgs& a,
+                                          const TileDesc& T, int k,
+                                          double& sg, double& sp) {
   const ImgDesc& D = a.imgs[T.img];
   float* base = a.arena + D.off;
   const int64_t PL = D.plane;
+  TileCtxS c;
+  c.F = base + plain_f(k) * PL;
+  c.M = base + plain_f(k - 1) * PL;
+  c.FL = base + plain_f(k + N - 1) * PL;
+  c.FN = base + plain_f(k + N) * PL;
+  c.PX = base + plain_p(k) * PL;
+  c.PY = c.PX + PL;
+  c.QX = base + plain_p(k + N) * PL;
+  c.QY = c.QX + PL;
+  c.G = base + kPlainG * PL;
+  c.ny = D.ny;
+  c.nx = D.nx;
+  c.pitch = D.pitch;
+  c.x0 = T.x0;
+  c.y0 = T.y0;
+  c.y1 = T.y1;
+  c.lam = D.lam;
+  c.tau = D.tau;
+  c.sig = D.sigma;
+  c.th = D.theta;
+  sweep_tile_xs<N, kBatchMargin, CHECK>(c, sg, sp);
+}
+
+template <bool CHECK>
+__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
+                                        int n) {
+  const TileDesc T = a.tiles[t];
   double sg = 0.0, sp = 0.0;
-  if (two) {
-    TileCtx2 c;
-    c.F = base + plain_f(k) * PL;
-    c.M = base + plain_f(k - 1) * PL;
-    c.FA = base + plain_f(k + 1) * PL;
-    c.FB = base + plain_f(k + 2) * PL;
-    c.PX = base + plain_p(k) * PL;
-    c.PY = c.PX + PL;
-    c.BX = base + plain_p(k + 2) * PL;
-    c.BY = c.BX + PL;
-    c.G = base + kPlainG * PL;
-    c.ny = D.ny;
-    c.nx = D.nx;
-    c.pitch = D.pitch;
-    c.x0 = T.x0;
-    c.y0 = T.y0;
-    c.y1 = T.y1;
-    c.lam = D.lam;
-    c.tau = D.tau;
-    c.sig = D.sigma;
-    c.th = D.theta;
-    sweep_tile_x2<CHECK>(c, sg, sp);
-  } else {
-    TileCtx c;
-    c.fk = base + plain_f(k) * PL;
-    c.fkm = base + plain_f(k - 1) * PL;
-    c.fn = base + plain_f(k + 1) * PL;
-    c.pxk = base + plain_p(k) * PL;
-    c.pyk = c.pxk + PL;
-    c.pxn = base + plain_p(k + 1) * PL;
-    c.pyn = c.pxn + PL;
-    c.g = base + kPlainG * PL;
-    c.ny = D.ny;
-    c.nx = D.nx;
-    c.pitch = D.pitch;
-    c.x0 = T.x0;
-    c.y0 = T.y0;
-    c.y1 = T.y1;
-    c.lam = D.lam;
-    c.tau = D.tau;
-    c.sig = D.sigma;
-    c.th = D.theta;
-    sweep_tile<CHECK>(c, sg, sp);
+  switch (n) {
+    case 1: tile_pass<1, CHECK>(a, T, k, sg, sp); break;
+    case 2: tile_pass<2, CHECK>(a, T, k, sg, sp); break;
+    case 3: tile_pass<3, CHECK>(a, T, k, sg, sp); break;
+    default: tile_pass<4, CHECK>(a, T, k, sg, sp); break;
   }
+  static_assert(kBatchMaxPass == 4, "one case per pass length");
   if (CHECK) {
     sg = wave_sum(sg);
     sp = wave_sum(sp);
@@ -216,15 +206,15 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
   int k = 0;
   while (k < a.max_iter) {
     const bool check = a.check_every > 0 && (k % a.check_every) == 0;
-    const bool two = a.blocked && k + 2 <= a.max_iter;
+    const int n = batch_pass_len(k, a.max_iter, a.check_every, a.depth);
     const int nact = load_i32(&h->n_active);
     if (nact == 0) break;
     if (wave < a.wpb)
       for (int idx = gw; idx < nact; idx += nw) {
         if (check)
-          do_tile<true>(a, a.active[idx], k, two);
+          do_tile<true>(a, a.active[idx], k, n);
         else
-          do_tile<false>(a, a.active[idx], k, two);
+          do_tile<false>(a, a.active[idx], k, n);
       }
     if (!grid_barrier(h, gen)) return;
     if (check) {
@@ -242,21 +232,22 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
         if (!grid_barrier(h, gen)) return;
       }
     }
-    k += two ? 2 : 1;
+    k += n;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) h->k = k;
 }
 
-// One iteration over the active list (graph-block driver).  The last block
-// to finish advances k and, on check iterations, reduces every running
-// image, stops the converged ones and rebuilds the active list.
-template <bool CHECK, bool TWO>
-__global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
+// One pass of n iterations over the active list (graph-block driver).  The
+// last block to finish advances k and, on check iterations, reduces every
+// running image, stops the converged ones and rebuilds the active list.
+template <bool CHECK>
+__global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a,
+                                                                int n) {
   __shared__ double red[2][kMaxBlock / kWave];
   __shared__ int s_last;
   BatchHdr* h = a.hdr;
   const int k = h->k;
-  if (k + (TWO ? 2 : 1) > a.max_iter) return;
+  if (k + n > a.max_iter) return;
   const int nact = h->n_active;
   if (nact == 0) return;
   const int wave = threadIdx.x / kWave;
@@ -264,7 +255,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
   const int gw = blockIdx.x * a.wpb + wave;
   if (wave < a.wpb)
     for (int idx = gw; idx < nact; idx += nw)
-      do_tile<CHECK>(a, a.active[idx], k, TWO);
+      do_tile<CHECK>(a, a.active[idx], k, n);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -282,7 +273,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a) {
       if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
     }
   }
-  if (threadIdx.x == 0) h->k = k + (TWO ? 2 : 1);
+  if (threadIdx.x == 0) h->k = k + n;
 }
 
 __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
@@ -402,19 +393,13 @@ hipError_t launch_batch_persistent(const BatchArgs& a, int grid,
 }
 
 hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
-                              bool two, hipStream_t s) {
+                              int n, hipStream_t s) {
+  if (n < 1 || n > kBatchMaxPass) return hipErrorInvalidValue;
   const dim3 g(grid), blk(a.wpb * kWave);
-  if (two) {
-    if (check)
-      hipLaunchKernelGGL((batch_sweep_kernel<true, true>), g, blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((batch_sweep_kernel<false, true>), g, blk, 0, s, a);
-  } else {
-    if (check)
-      hipLaunchKernelGGL((batch_sweep_kernel<true, false>), g, blk, 0, s, a);
-    else
-      hipLaunchKernelGGL((batch_sweep_kernel<false, false>), g, blk, 0, s, a);
-  }
+  if (check)
+    hipLaunchKernelGGL((batch_sweep_kernel<true>), g, blk, 0, s, a, n);
+  else
+    hipLaunchKernelGGL((batch_sweep_kernel<false>), g, blk, 0, s, a, n);
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
     L.img_off.push_back(arena);
     arena += kPlainPlanes2D * plane;
     // both tile tables together hold at most two tiles per (strip, row)
-    L.tmax += 2 * (int64_t)((s[i].nx + kStripCols - 1) / kStripCols) * s[i].ny;
+    L.tmax += 2 * (int64_t)((s[i].nx + kBatchStrip - 1) / kBatchStrip) * s[i].ny;
   }
   size_t o = kHeaderBytes;
   L.off_imgs = o;
@@ -110,29 +110,31 @@ struct BatchSetup {
   int ntiles;
 };
 
-constexpr int kShortBand = 4;  // rows per band of the short-band table
+// Rows per band of the short-band table (a band walk of a pass of n
+// iterations covers 2n-1 extra rows, so very short bands waste work).
+constexpr int kShortBand = 8;
 
 void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
                  const int64_t* offsets, const tvpd_params* prm, int th,
-                 int wpb, int nwaves, char* ws, BatchSetup& B) {
+                 int th_short, int wpb, int nwaves, char* ws, BatchSetup& B) {
   B.host.assign(L.off_part, 0);
   char* h = B.host.data();
   ImgDesc* imgs = reinterpret_cast<ImgDesc*>(h + L.off_imgs);
   int64_t* offs = reinterpret_cast<int64_t*>(h + L.off_offs);
   TileDesc* tiles = reinterpret_cast<TileDesc*>(h + L.off_tiles);
   int32_t* active = reinterpret_cast<int32_t*>(h + L.off_active);
-  const int ths[2] = {th, std::min(th, kShortBand)};
+  const int ths[2] = {th, std::min(th, th_short > 0 ? th_short : kShortBand)};
   int t = 0;
   for (int tbl = 0; tbl < 2; ++tbl) {
     for (int i = 0; i < n; ++i) {
       ImgDesc& D = imgs[i];
       D.tile_first[tbl] = t;
-      const int ntx = (s[i].nx + kStripCols - 1) / kStripCols;
+      const int ntx = (s[i].nx + kBatchStrip - 1) / kBatchStrip;
       const int nty = (s[i].ny + ths[tbl] - 1) / ths[tbl];
       for (int ty = 0; ty < nty; ++ty)
         for (int tx = 0; tx < ntx; ++tx) {
           tiles[t].img = i;
-          tiles[t].x0 = tx * kStripCols;
+          tiles[t].x0 = tx * kBatchStrip;
           tiles[t].y0 = ty * ths[tbl];
           tiles[t].y1 = std::min((ty + 1) * ths[tbl], s[i].ny);
           ++t;
@@ -181,8 +183,7 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   a.check_every = prm[0].check_every;
   a.wpb = wpb;
   a.switch_tiles = nwaves;
-  a.blocked = blocking_enabled() &&
-              (a.check_every == 0 || a.check_every % 2 == 0) ? 1 : 0;
+  a.depth = pass_depth() < kBatchMaxPass ? pass_depth() : kBatchMaxPass;
 }
 
 struct PinnedHdr {
@@ -216,9 +217,9 @@ int pinned_get(PinnedHdr** out) {
   return TVPD_OK;
 }
 
-// Launches of one block of `chunk` iterations starting at an iteration
-// k0 with k0 % chunk == 0: two-iteration passes when blocked, a check on the
-// first iteration of a pass whenever it is due.
+// Launches of iterations k0 .. k0+n-1: passes as batch_pass_len schedules
+// them (the same schedule as the persistent driver), a check on the first
+// iteration of a pass whenever it is due.
 hipError_t enqueue_batch_iters(const BatchArgs& a, int grid, int k0, int n,
                                hipStream_t s) {
   const int ce = a.check_every;
@@ -226,10 +227,10 @@ hipError_t enqueue_batch_iters(const BatchArgs& a, int grid, int k0, int n,
   while (i < n) {
     const int k = k0 + i;
     const bool check = ce > 0 && (k % ce) == 0;
-    const bool two = a.blocked && n - i >= 2;
-    const hipError_t e = launch_batch_sweep(a, grid, check, two, s);
+    const int len = batch_pass_len(k, k0 + n, ce, a.depth);
+    const hipError_t e = launch_batch_sweep(a, grid, check, len, s);
     if (e != hipSuccess) return e;
-    i += two ? 2 : 1;
+    i += len;
   }
   return hipSuccess;
 }
@@ -291,8 +292,8 @@ int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
 
 int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
                        const float* g, float* f, const tvpd_params* prm,
-                       int mode, int th, int wpb, void* ws, size_t ws_bytes,
-                       tvpd_result* res, hipStream_t s) {
+                       int mode, int th, int th_short, int wpb, void* ws,
+                       size_t ws_bytes, tvpd_result* res, hipStream_t s) {
   const BatchLayout L = make_batch_layout(n, shapes);
   if (!ws) return TVPD_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
@@ -316,7 +317,7 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
     grid = std::min(grid, cap);
   }
   BatchSetup B;
-  build_setup(L, n, shapes, offsets, prm, th, wpb, grid * wpb,
+  build_setup(L, n, shapes, offsets, prm, th, th_short, wpb, grid * wpb,
               static_cast<char*>(ws), B);
   BHIP(hipMemcpyAsync(ws, B.host.data(), B.host.size(), hipMemcpyHostToDevice,
                       s));
@@ -382,14 +383,16 @@ int tvpd_solve_batched(int32_t n, const tvpd_shape* shapes,
                        tvpd_result* res, void* stream) {
   if (int rc = batch_args_ok(n, shapes, offsets, g_arena, f_arena, prm))
     return rc;
-  int mode = 0, th = 0, wpb = 0;
+  int mode = 0, th = 0, wpb = 0, th_short = 0;
   if (opts) {
     mode = opts->mode;
     th = opts->th;
     wpb = opts->wpb;
+    th_short = opts->th_short;
   }
   if (mode < 0 || mode > 2) return TVPD_ERR_INVALID_ARG;
-  if (th < 0 || th > 4096 || !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4))
+  if (th < 0 || th > 4096 || th_short < 0 || th_short > 4096 ||
+      !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4))
     return TVPD_ERR_INVALID_ARG;
   {
     std::lock_guard<std::mutex> gl(g_btile_mu);
@@ -397,7 +400,8 @@ int tvpd_solve_batched(int32_t n, const tvpd_shape* shapes,
     if (wpb == 0) wpb = g_btile_wpb;
   }
   return solve_batched_impl(n, shapes, offsets, g_arena, f_arena, prm, mode,
-                            th, wpb, ws, ws_bytes, res, (hipStream_t)stream);
+                            th, th_short, wpb, ws, ws_bytes, res,
+                            (hipStream_t)stream);
 }
 
 int tvpd_batch_autotune(int32_t n, const tvpd_shape* shapes,
@@ -429,7 +433,8 @@ int tvpd_batch_autotune(int32_t n, const tvpd_shape* shapes,
         if (hipEventRecord(e0, s) != hipSuccess) rc = TVPD_ERR_HIP;
         if (!rc)
           rc = solve_batched_impl(n, shapes, offsets, g_arena, f_arena,
-                                  p.data(), 0, th, w, ws, ws_bytes, nullptr, s);
+                                  p.data(), 0, th, 0, w, ws, ws_bytes,
+                                  nullptr, s);
         if (!rc && (hipEventRecord(e1, s) != hipSuccess ||
                     hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))

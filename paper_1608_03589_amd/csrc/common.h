@@ -48,14 +48,32 @@ struct Layout {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Plane block of the plain 2D solver: f^k in slot k mod 4 (planes 0..3),
-// p^k in slot k mod 3 (planes 4 + 2 (k mod 3), x then y), g in plane 10.  A
-// two-iteration pass reads f^k, f^{k-1}, p^k and writes f^{k+1}, f^{k+2},
-// p^{k+2}: with these ring sizes it never overwrites its own inputs.
-constexpr int kPlainPlanes2D = 11;
-constexpr int kPlainG = 10;
-__host__ __device__ inline int plain_f(int k) { return ((k % 4) + 4) % 4; }
-__host__ __device__ inline int plain_p(int k) { return 4 + 2 * (k % 3); }
+// Longest pass (iterations per launch) of the 2D sweep.  Passes of n >= 3
+// iterations run on overlapping strips: a wave loads 256 columns and owns
+// the middle xs_owned(n) of them (margins of xs_margin(n) >= n columns on
+// each side, a multiple of 4 for aligned float4 access).
+constexpr int kMaxPass = 6;
+__host__ __device__ constexpr int xs_margin(int n) { return n <= 4 ? 4 : 8; }
+__host__ __device__ constexpr int xs_owned(int n) {
+  return kStripCols - 2 * xs_margin(n);
+}
+constexpr int kXsOwnedMin = kStripCols - 2 * xs_margin(kMaxPass);
+
+// Plane block of the plain 2D solver: f^k in slot k mod 6 (planes 0..5),
+// p^k in slot k mod 5 (planes 6 + 2 (k mod 5), x then y), g in plane 16.  A
+// pass of n <= kMaxPass iterations reads f^k, f^{k-1}, p^k and writes
+// f^{k+n-1}, f^{k+n}, p^{k+n}: with rings of kMaxPass + 2 and kMaxPass + 1
+// slots it never overwrites an input that another tile still reads.
+constexpr int kRingF = kMaxPass + 2;
+constexpr int kRingP = kMaxPass + 1;
+constexpr int kPlainPlanes2D = kRingF + 2 * kRingP + 1;
+constexpr int kPlainG = kRingF + 2 * kRingP;
+__host__ __device__ inline int plain_f(int k) {
+  return ((k % kRingF) + kRingF) % kRingF;
+}
+__host__ __device__ inline int plain_p(int k) {
+  return kRingF + 2 * (((k % kRingP) + kRingP) % kRingP);
+}
 
 // Plane block of the plain 3D solver: f^k in slot k mod 3 (planes 0..2),
 // p^k in slot k mod 2 (planes 3 + 3 (k mod 2), x, y, z), g in plane 9.
@@ -113,8 +131,10 @@ struct Sweep3DArgs {
 // Host launchers (kernels2d.hip).
 hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
                          hipStream_t s);
+// One launch of n iterations (n = 1 .. kMaxPass; with n >= 2 the temporally
+// blocked kernels).  Gap check, if any, on the first iteration.
 hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
-                          const tvpd_coeffs& c, bool with_gap, bool two,
+                          const tvpd_coeffs& c, bool with_gap, int n,
                           void* ws, hipStream_t s);
 hipError_t launch_read2d(const Layout& L, const void* ws, float* f_out,
                          float* p_out, hipStream_t s);
@@ -122,7 +142,7 @@ hipError_t launch_energy2d(const Layout& L, float lam, void* ws,
                            bool skip_if_converged, hipStream_t s);
 hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
                              hipStream_t s);
-int sweep2d_blocks(const Layout& L, const Tile2D& t);
+int sweep2d_blocks(const Layout& L, const Tile2D& t, int n);
 hipError_t launch_energy_final(const Layout& L, void* ws, int nparts,
                                bool skip_if_converged, hipStream_t s);
 
@@ -154,6 +174,6 @@ int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t, float us);
 int tune_save3d(const char* path, const tvpd_shape& s, const Tile3D& t,
                 float us);
 int tune_load(const char* path, int* count);
-bool blocking_enabled();  // two-iteration passes in use (api.hip)
+int pass_depth();         // longest pass in use, 1 .. kMaxPass (api.hip)
 
 }  // namespace tvpd

@@ -9,6 +9,7 @@
 #include "finish.h"
 #include "tile2d.h"
 #include "tile2d_x2.h"
+#include "tile2d_xs.h"
 
 namespace tvpd {
 namespace {
@@ -112,6 +113,53 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_x2_kernel(Sweep2DArgs a) {
     sweep_tile_x2<GAP>(c, acc_gap, acc_P);
   }
   finish_sweep<GAP, 2>(st, a.partials, k, acc_gap, acc_P);
+}
+
+// S iterations per launch on overlapping 248-column strips (tile2d_xs.h).
+template <int S, bool GAP>
+__global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
+  DevState* st = a.st;
+  const int k = st->k;
+  if (st->converged || k + S > st->k_end) return;
+  const int wave = threadIdx.x / kWave;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (b >> 3);
+  const int wt = bt * a.wpb + wave;
+  double acc_gap = 0.0, acc_P = 0.0;
+  if (wt < a.ntiles) {
+    TileCtxS c;
+    const int64_t PL = a.plane;
+    c.F = a.base + plain_f(k) * PL;
+    c.M = a.base + plain_f(k - 1) * PL;
+    c.FL = a.base + plain_f(k + S - 1) * PL;
+    c.FN = a.base + plain_f(k + S) * PL;
+    c.PX = a.base + plain_p(k) * PL;
+    c.PY = c.PX + PL;
+    c.QX = a.base + plain_p(k + S) * PL;
+    c.QY = c.QX + PL;
+    c.G = a.base + kPlainG * PL;
+    int tx, ty;
+    if (a.order == 0) {
+      ty = wt / a.ntx;
+      tx = wt - ty * a.ntx;
+    } else {
+      tx = wt / a.nty;
+      ty = wt - tx * a.nty;
+    }
+    c.ny = a.ny;
+    c.nx = a.nx;
+    c.pitch = a.pitch;
+    c.x0 = tx * xs_owned(S);
+    c.y0 = ty * a.th;
+    c.y1 = min(c.y0 + a.th, a.ny);
+    c.lam = a.lam;
+    c.tau = a.tau;
+    c.sig = a.sigma;
+    c.th = a.theta;
+    sweep_tile_xs<S, xs_margin(S), GAP>(c, acc_gap, acc_P);
+  }
+  finish_sweep<GAP, S>(st, a.partials, k, acc_gap, acc_P);
 }
 
 __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
@@ -234,12 +282,6 @@ __global__ __launch_bounds__(kMaxBlock) void energy_final_kernel(
 
 }  // namespace
 
-int sweep2d_blocks(const Layout& L, const Tile2D& t) {
-  const int ntx = (L.nx + kStripCols - 1) / kStripCols;
-  const int nty = (L.ny + t.th - 1) / t.th;
-  const int nt = ntx * nty;
-  return (nt + t.wpb - 1) / t.wpb;
-}
 
 hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
                          hipStream_t s) {
@@ -257,8 +299,9 @@ hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
 }
 
 hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
-                          const tvpd_coeffs& c, bool with_gap, bool two,
+                          const tvpd_coeffs& c, bool with_gap, int n,
                           void* ws, hipStream_t s) {
+  if (n < 1 || n > kMaxPass) return hipErrorInvalidValue;
   Sweep2DArgs a;
   a.base = planes_of(L, ws);
   a.plane = L.plane;
@@ -268,7 +311,9 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   a.th = t.th;
   a.wpb = t.wpb;
   a.order = t.order;
-  a.ntx = (L.nx + kStripCols - 1) / kStripCols;
+  // the blocked kernels of depth >= 3 run on overlapping strips
+  const int strip = n >= 3 ? xs_owned(n) : kStripCols;
+  a.ntx = (L.nx + strip - 1) / strip;
   a.nty = (L.ny + t.th - 1) / t.th;
   a.ntiles = a.ntx * a.nty;
   a.lam = c.lam;
@@ -280,18 +325,34 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   const int nb = (a.ntiles + t.wpb - 1) / t.wpb;
   if (nb > L.max_partials) return hipErrorInvalidValue;
   const dim3 grid(nb), block(t.wpb * kWave);
-  if (two) {
-    if (with_gap)
-      hipLaunchKernelGGL(sweep2d_x2_kernel<true>, grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL(sweep2d_x2_kernel<false>, grid, block, 0, s, a);
+  if (with_gap) {
+    switch (n) {
+      case 1: hipLaunchKernelGGL((sweep2d_kernel<true>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((sweep2d_x2_kernel<true>), grid, block, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((sweep2d_xs_kernel<3, true>), grid, block, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((sweep2d_xs_kernel<4, true>), grid, block, 0, s, a); break;
+      case 5: hipLaunchKernelGGL((sweep2d_xs_kernel<5, true>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((sweep2d_xs_kernel<6, true>), grid, block, 0, s, a); break;
+    }
   } else {
-    if (with_gap)
-      hipLaunchKernelGGL(sweep2d_kernel<true>, grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL(sweep2d_kernel<false>, grid, block, 0, s, a);
+    switch (n) {
+      case 1: hipLaunchKernelGGL((sweep2d_kernel<false>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((sweep2d_x2_kernel<false>), grid, block, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((sweep2d_xs_kernel<3, false>), grid, block, 0, s, a); break;
+      case 4: hipLaunchKernelGGL((sweep2d_xs_kernel<4, false>), grid, block, 0, s, a); break;
+      case 5: hipLaunchKernelGGL((sweep2d_xs_kernel<5, false>), grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL((sweep2d_xs_kernel<6, false>), grid, block, 0, s, a); break;
+    }
   }
   return hipGetLastError();
+}
+
+int sweep2d_blocks(const Layout& L, const Tile2D& t, int n) {
+  const int strip = n >= 3 ? xs_owned(n) : kStripCols;
+  const int ntx = (L.nx + strip - 1) / strip;
+  const int nty = (L.ny + t.th - 1) / t.th;
+  const int nt = ntx * nty;
+  return (nt + t.wpb - 1) / t.wpb;
 }
 
 hipError_t launch_read2d(const Layout& L, const void* ws, float* f_out,

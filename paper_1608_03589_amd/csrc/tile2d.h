@@ -88,11 +88,18 @@ __device__ __forceinline__ void project2(float qx, float qy, float lam,
   py = qy * c;
 }
 
+// Value of the next (from_right) or previous (from_left) lane of the wave,
+// by a DPP wavefront shift (wave_shl:1 / wave_shr:1): a VALU operation with
+// no LDS round trip, unlike a bpermute shuffle.  The edge lane keeps its own
+// value, as a shuffle past the wave's end does; callers replace it.  All
+// lanes of the wave must be active.
 __device__ __forceinline__ float from_right(float v) {
-  return __shfl_down(v, 1, kWave);
+  const int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x130, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float from_left(float v) {
-  return __shfl_up(v, 1, kWave);
+  const int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x138, 0xF, 0xF, false));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

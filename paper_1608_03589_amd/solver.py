@@ -183,6 +183,18 @@ def get_tile3d(shape):
     return th.value, tz.value, wpb.value
 
 
+def set_pass_depth(depth: int):
+    """Longest pass (iterations per launch) of the plain 2D solver, 1 .. 6;
+    the iterates are the same for every depth.  Process-wide."""
+    call("tvpd_set_pass_depth", int(depth))
+
+
+def get_pass_depth() -> int:
+    d = C.c_int32()
+    call("tvpd_get_pass_depth", C.byref(d))
+    return d.value
+
+
 def set_blocking(on: bool):
     """Two-iteration passes (temporal blocking) for the plain and batched 2D
     solvers on or off, process-wide; the iterates are the same either way."""

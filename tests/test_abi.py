@@ -59,13 +59,16 @@ def _ws(shape):
 
 
 def test_workspace_size_grows_and_validates():
-    # 11 planes: f ring of 4, dual ring of 3 x 2, g
+    # 23 planes: f ring of 8, dual ring of 7 x 2, g (passes of up to 6)
     st, a = _ws(Shape(2, 1, 256, 256))
-    assert st == 0 and a >= 11 * 256 * 256 * 4
+    assert st == 0 and a >= 23 * 256 * 256 * 4
     st, b = _ws(Shape(2, 1, 4096, 4096))
-    assert st == 0 and b >= 11 * 4096 * 4096 * 4 and b < 11.2 * 4096 * 4096 * 4
+    assert st == 0 and b >= 23 * 4096 * 4096 * 4 and b < 23.2 * 4096 * 4096 * 4
     st, c = _ws(Shape(2, 1, 7, 5))   # ragged: pitch rounds 5 up to 8
-    assert st == 0 and c >= 11 * 7 * 8 * 4
+    assert st == 0 and c >= 23 * 7 * 8 * 4
+    # 3D: 10 planes (f ring of 3, dual ring of 2 x 3, g)
+    st, d = _ws(Shape(3, 32, 32, 32))
+    assert st == 0 and d >= 10 * 32 ** 3 * 4 and d < 10.5 * 32 ** 3 * 4
     for bad in [Shape(2, 2, 4, 4), Shape(4, 1, 4, 4), Shape(2, 1, 0, 4),
                 Shape(2, 1, 4, -1), Shape(3, 0, 4, 4)]:
         assert _ws(bad)[0] == -2

@@ -75,30 +75,31 @@ def test_batch_tile_shapes_do_not_change_iterates():
 
 
 @pytest.mark.parametrize("mode", ["persistent", "graph", "launches"])
-def test_batch_two_iteration_passes_match_single(mode):
-    """Two-iteration passes (on whenever check_every is even or 0) give the
-    same iterates, stopping iterations and gaps as one-iteration passes, also
-    with an odd iteration budget (the last pass is a single iteration)."""
+def test_batch_blocked_passes_match_single(mode):
+    """Passes of several iterations (up to the pass depth, ending before each
+    gap check) give the same iterates, stopping iterations and gaps as
+    one-iteration passes, also with odd iteration budgets and check
+    intervals."""
     imgs = small_batch(700)
     b = tv.BatchedSolver([g.shape for g in imgs], DEV)
     gts = [torch.from_numpy(g).to(DEV) for g in imgs]
     for kw in [dict(max_iter=121, check_every=0, gap_tol=-1.0),
                dict(max_iter=333, check_every=12, gap_tol=3e-3),
                dict(max_iter=95, check_every=7, gap_tol=3e-3)]:
-        out = []
-        for blocked in (True, False):
-            print(f"case: batch {mode} blocked={blocked} {kw}", flush=True)
-            tv.set_blocking(blocked)
+        out = {}
+        for depth in (1, 2, 3, 4):
+            print(f"case: batch {mode} depth={depth} {kw}", flush=True)
+            tv.set_pass_depth(depth)
             try:
                 fs, rs = b.solve(gts, lam=0.1, mode=mode, **kw)
-                out.append(([f.cpu().numpy().copy() for f in fs],
-                            [(r.iters, r.converged, r.gap, r.primal) for r in rs]))
+                out[depth] = ([f.cpu().numpy().copy() for f in fs],
+                              [(r.iters, r.converged, r.gap, r.primal) for r in rs])
             finally:
                 tv.set_blocking(True)
-        (fa, ra), (fb, rb) = out
-        assert ra == rb
-        for a, c in zip(fa, fb):
-            assert np.array_equal(a, c)
+        for depth in (2, 3, 4):
+            assert out[depth][1] == out[1][1], depth
+            for a, c in zip(out[depth][0], out[1][0]):
+                assert np.array_equal(a, c), depth
 
 
 def test_batch_against_oracle():

@@ -257,28 +257,36 @@ def test_autotune_choice_and_cache_roundtrip(tmp_path):
     ((300, 517), (1, 1, 1)), ((300, 517), (2, 2, 0)), ((300, 517), (3, 4, 0)),
     ((300, 517), (64, 4, 0)), ((37, 1030), (5, 2, 1)), ((1, 9), (1, 1, 0)),
     ((2, 300), (1, 4, 0)), ((3, 3), (2, 1, 1)), ((513, 257), (300, 1, 0)),
+    ((20, 248), (4, 4, 0)), ((21, 249), (7, 2, 1)), ((9, 744), (2, 4, 0)),
+    ((70, 497), (16, 1, 0)), ((6, 4), (1, 1, 0)), ((11, 240), (3, 4, 0)),
+    ((12, 241), (2, 2, 1)), ((31, 480), (9, 4, 0)),
 ])
-def test_two_iteration_passes_are_bitwise_equal(shape, tile):
-    """Temporal blocking (two iterations per pass) reproduces one-iteration
-    passes bit for bit, for even and odd iteration counts and with a
-    stopping solve."""
+def test_blocked_passes_are_bitwise_equal(shape, tile):
+    """Temporal blocking of every depth (1 to 6 iterations per launch)
+    reproduces one-iteration passes bit for bit, for iteration counts that do
+    and do not divide into whole passes and for stopping solves whose checks
+    cut passes short."""
     g32 = scene32(*shape, 10, 0.1, 90 + shape[0])
     tv.set_tile(shape, *tile)
     out = {}
     try:
-        for blocked in (False, True):
-            tv.set_blocking(blocked)
+        for depth in (1, 2, 3, 4, 5, 6):
+            print(f"case: depth {depth} shape {shape} tile {tile}", flush=True)
+            tv.set_pass_depth(depth)
             for n in (7, 20):
                 f, p, _ = gpu_fixed(g32, n, 0.1)
-                out[(blocked, n)] = (f, p)
+                out[(depth, n)] = (f, p)
             s = tv.PlainSolver(shape, DEV)
-            fs, rs = s.solve(torch.from_numpy(g32).to(DEV), 0.1, max_iter=400,
-                             check_every=10, gap_tol=2e-3)
-            out[(blocked, "solve")] = (fs.cpu().numpy(), rs.iters, rs.gap)
+            for ce in (10, 7, 3):
+                fs, rs = s.solve(torch.from_numpy(g32).to(DEV), 0.1,
+                                 max_iter=400, check_every=ce, gap_tol=2e-3)
+                out[(depth, "solve", ce)] = (fs.cpu().numpy(), rs.iters)
     finally:
         tv.set_blocking(True)
-    for n in (7, 20):
-        assert np.array_equal(out[(True, n)][0], out[(False, n)][0])
-        assert np.array_equal(out[(True, n)][1], out[(False, n)][1])
-    a, b = out[(True, "solve")], out[(False, "solve")]
-    assert a[1] == b[1] and np.array_equal(a[0], b[0])
+    for depth in (2, 3, 4, 5, 6):
+        for n in (7, 20):
+            assert np.array_equal(out[(depth, n)][0], out[(1, n)][0]), (depth, n)
+            assert np.array_equal(out[(depth, n)][1], out[(1, n)][1]), (depth, n)
+        for ce in (10, 7, 3):
+            a, b = out[(depth, "solve", ce)], out[(1, "solve", ce)]
+            assert a[1] == b[1] and np.array_equal(a[0], b[0]), (depth, ce)
