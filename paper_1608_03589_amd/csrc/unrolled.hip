@@ -524,9 +524,14 @@ int64_t u_partials_needed(const PlaneSet& P) { return 3 * adj_blocks(P) + 1; }
 
 hipError_t launch_u_init(const PlaneSet& P, const float* g, int id_g,
                          int id_zero, int nzero, hipStream_t s) {
-  // zero every plane first so that padding columns hold zeros
-  hipLaunchKernelGGL(u_zero_pitch_kernel, dim3(4096), dim3(256), 0, s, P, 0,
-                     (int)(P.istride / P.plane));
+  // Only g and p^0 are read before a kernel has written them: zero those
+  // planes (padding included; g's padding stays zero), then copy g in.
+  // Every other plane is written whole (all rows, all pitch columns) by the
+  // sweep that produces it before anything reads it.
+  const int first = id_g < id_zero ? id_g : id_zero;
+  const int last = id_g > id_zero + nzero - 1 ? id_g : id_zero + nzero - 1;
+  hipLaunchKernelGGL(u_zero_pitch_kernel, dim3(4096), dim3(256), 0, s, P,
+                     first, last - first + 1);
   hipLaunchKernelGGL(u_init_kernel, dim3((unsigned)nrow_blocks(P)),
                      dim3(kRowBlock), 0, s, P, g, id_g, id_zero, nzero);
   return hipGetLastError();

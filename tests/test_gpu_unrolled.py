@@ -118,6 +118,40 @@ def test_fused_adjoint_equals_two_pass_adjoint_3d(shape, K, ckpt):
     assert np.allclose(gc1, gc2, rtol=1e-5, atol=1e-7 * np.abs(gc2).max())
 
 
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("shape,K,ckpt", [((2, 21, 301), 6, 3),
+                                          ((1, 7, 9, 266), 5, 2)])
+def test_workspace_contents_do_not_matter(shape, K, ckpt, fused):
+    """The forward initialises only g and p^0; every other plane is written
+    whole before it is read.  A workspace full of NaN gives the same results
+    bit for bit as a zeroed one."""
+    print(f"case: NaN workspace {shape} fused={fused}", flush=True)
+    ndim = len(shape) - 1
+    if ndim == 2:
+        _, g = batch2d(*shape, seed=960)
+    else:
+        g = np.stack([scene3d(*shape[1:], 6, 0.1, 970 + i)[1]
+                      for i in range(shape[0])]).astype(np.float32)
+    c = coeffs_for(K, ndim, 13)
+    grad_f = np.random.default_rng(14).normal(size=g.shape).astype(np.float32)
+    tv.set_fused_adjoint(fused)
+    try:
+        out = []
+        for fill in (0x00, 0xFF):
+            solver = tv.UnrolledSolver(g.shape, K, ckpt, 1.0, DEV)
+            solver.ws.fill_(fill)
+            gt = torch.from_numpy(g).to(DEV)
+            ct = torch.from_numpy(c).to(DEV)
+            f = solver.forward(gt, ct)
+            gg, gc = solver.backward(ct, torch.from_numpy(grad_f).to(DEV))
+            torch.cuda.synchronize()
+            out.append((f.cpu().numpy(), gg.cpu().numpy(), gc.cpu().numpy()))
+    finally:
+        tv.set_fused_adjoint(True)
+    for a, b in zip(out[0], out[1]):
+        assert np.isfinite(a).all() and np.array_equal(a, b)
+
+
 def test_unrolled_3d_parity():
     print("case: unrolled 3d", flush=True)
     vols = [scene3d(10, 12, 13, 5, 0.1, 900 + i)[1] for i in range(2)]
