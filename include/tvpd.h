@@ -180,9 +180,9 @@ int tvpd_get_tile3d(const tvpd_shape* shape, int32_t* th, int32_t* tz,
  * p^k, g read once; f^{k+n-1}, f^{k+n}, p^{k+n} written once: 36 bytes per n
  * pixel-iterations, against 32 per pixel-iteration unblocked); a gap check
  * only ever falls on a pass's first iteration, so passes end before the next
- * check.  depth in 1 .. 6, default 5; the batched solver uses passes of 2
- * whenever depth >= 2 and check_every is even or 0.  The iterates are
- * bit-identical for every depth.  Process-wide setting.
+ * check.  depth in 1 .. 6, default 5; the batched solver uses passes of 1,
+ * 2 and (with depth >= 5) 5 iterations.  The iterates are bit-identical for
+ * every depth.  Process-wide setting.
  * tvpd_set_blocking(0) is depth 1, tvpd_set_blocking(1) the default depth. */
 int tvpd_set_blocking(int32_t on);
 int tvpd_set_pass_depth(int32_t depth);
@@ -219,7 +219,7 @@ int tvpd_tune_load(const char* cache_path, int32_t* count);
  * launch runs every iteration (grid barriers between passes, per-image
  * stopping on the device); mode 1: one launch per pass, replayed from HIP
  * graphs of whole check intervals with the host polling a flag; mode 2:
- * plain launches, one per pass (reference driver).  Passes hold up to 4
+ * plain launches, one per pass (reference driver).  Passes hold 1, 2 or 5
  * iterations (tvpd_set_pass_depth).  th: rows per wave band (0 = the
  * autotuned or default value); wpb: waves per block (0 = autotuned or
  * default, else 1, 2 or 4); th_short: rows per band of the second tile

@@ -56,9 +56,11 @@ struct BatchArgs {
   int32_t depth;         // longest pass (iterations per sweep), 1 .. kBatchMaxPass
 };
 
-// Longest batch pass: deeper passes would raise the register count of the
-// drivers (which contain every pass length) above two waves per SIMD.
-constexpr int kBatchMaxPass = 4;
+// Batch passes are 1, 2 or 5 iterations long: the drivers contain every
+// pass length they can launch, and their register count is that of the
+// longest; with lengths 3 and 4 as well it would exceed two waves per SIMD.
+// Passes of 5 fit the usual check interval of 10 exactly.
+constexpr int kBatchMaxPass = 5;
 
 // Batch tiles: 256-column strips that own their middle kBatchStrip columns
 // (margins of kBatchMargin >= every pass length, tile2d_xs.h).
@@ -76,7 +78,7 @@ __host__ __device__ inline int batch_pass_len(int k, int max_iter, int ce,
     const int to_check = (k / ce + 1) * ce - k;
     if (to_check < n) n = to_check;
   }
-  return n;
+  return (n == 3 || n == 4) ? 2 : n;  // lengths 1, 2 and 5 only
 }
 
 constexpr int kFinalBlocks = 32;  // blocks per image of the final pass

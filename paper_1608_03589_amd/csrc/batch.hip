@@ -112,10 +112,9 @@ __device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
   switch (n) {
     case 1: tile_pass<1, CHECK>(a, T, k, sg, sp); break;
     case 2: tile_pass<2, CHECK>(a, T, k, sg, sp); break;
-    case 3: tile_pass<3, CHECK>(a, T, k, sg, sp); break;
-    default: tile_pass<4, CHECK>(a, T, k, sg, sp); break;
+    default: tile_pass<5, CHECK>(a, T, k, sg, sp); break;
   }
-  static_assert(kBatchMaxPass == 4, "one case per pass length");
+  static_assert(kBatchMaxPass == 5, "one case per pass length");
   if (CHECK) {
     sg = wave_sum(sg);
     sp = wave_sum(sp);
@@ -394,7 +393,7 @@ hipError_t launch_batch_persistent(const BatchArgs& a, int grid,
 
 hipError_t launch_batch_sweep(const BatchArgs& a, int grid, bool check,
                               int n, hipStream_t s) {
-  if (n < 1 || n > kBatchMaxPass) return hipErrorInvalidValue;
+  if (n != 1 && n != 2 && n != kBatchMaxPass) return hipErrorInvalidValue;
   const dim3 g(grid), blk(a.wpb * kWave);
   if (check)
     hipLaunchKernelGGL((batch_sweep_kernel<true>), g, blk, 0, s, a, n);
