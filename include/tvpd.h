@@ -190,8 +190,8 @@ int tvpd_get_pass_depth(int32_t* depth);
 
 /* Autotuner.  Times every candidate tile of the sweep on `ws`, an
  * initialised workspace of this shape, and keeps the fastest for `shape` in
- * this process.  2D: th from 4 to 256, wpb 1/2/4, both orders, timing the
- * two-iteration pass when blocking is on.  3D: th 2/4, tz from 2 to 128,
+ * this process.  2D: th from 4 to 256, wpb 1/2/4, both orders, timing
+ * passes of the pass depth in use.  3D: th 2/4, tz from 2 to 128,
  * wpb 1/2/4; the chosen tz is returned in *order.  The workspace state is
  * advanced by the timing runs: call tvpd_init before solving with it.  If
  * cache_path is not NULL the choice is appended to that text file (one line

@@ -57,22 +57,33 @@ std::string device_arch() {
 
 }  // namespace
 
-// Default: blocks of 4 side-by-side waves, bands tall enough that the grid
-// is about one and a half blocks per compute unit for the strips of the
-// deepest pass in use.  Few concurrent row streams keep HBM pages open; the
-// deep passes have 2 waves per SIMD resident and need that many to hide
-// their latency.
+// Default: blocks of 4 side-by-side waves.  One-iteration and two-iteration
+// passes: bands tall enough for about one block per compute unit (few
+// concurrent row streams keep HBM pages open).  Deeper passes are bound by
+// latency and issue rather than by HBM: the shortest bands whose blocks all
+// fit on the GPU at once (two per CU at two waves per SIMD, one for passes of
+// 6), so that every CU holds as many waves as it can.
 Tile2D default_tile2d(const Layout& L) {
   Tile2D t;
   t.wpb = 4;
   t.order = 0;
   const int depth = pass_depth();
-  const int strip = depth >= 3 ? xs_owned(depth) : kStripCols;
-  const int64_t ntx = (L.nx + strip - 1) / strip;
-  const int64_t target_waves = (depth >= 3 ? 6LL : 4LL) * device_cus();
-  int64_t th = (ntx * L.ny + target_waves - 1) / target_waves;
-  if (th < 8) th = 8;
-  if (th > 256) th = 256;
+  const int cus = device_cus();
+  int64_t th;
+  if (depth >= 3) {
+    const int64_t ntx = (L.nx + xs_owned(depth) - 1) / xs_owned(depth);
+    const int64_t max_blocks = (depth >= 6 ? 1LL : 2LL) * cus;
+    th = 8;
+    while (th < 256 &&
+           (ntx * ((L.ny + th - 1) / th) + t.wpb - 1) / t.wpb > max_blocks)
+      ++th;
+  } else {
+    const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
+    const int64_t target_waves = 4LL * cus;
+    th = (ntx * L.ny + target_waves - 1) / target_waves;
+    if (th < 8) th = 8;
+    if (th > 256) th = 256;
+  }
   t.th = (int)th;
   return t;
 }
@@ -169,7 +180,8 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return TVPD_ERR_HIP;
-  static const int ths[] = {4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+  static const int ths[] = {4, 8, 12, 16, 24, 32, 36, 40, 44, 48, 64, 96, 128,
+                            192, 256};
   static const int wpbs[] = {1, 2, 4};
   float bu = 1e30f;
   Tile2D bt = default_tile2d(L);
