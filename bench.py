@@ -44,9 +44,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(pixels: int):
+def read_traffic(pixels: int, tile):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel source or the tile changed since it was
+    taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -55,6 +56,8 @@ def read_traffic(pixels: int):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    if kv.get("tile_th_wpb_order") != " ".join(str(v) for v in tile):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -369,7 +372,7 @@ def main():
                      for n in passes) / len(passes)
     pass_achieved = pass_bytes / launch_s / 1e9
     kernels = sorted(set(passes))
-    traffic = read_traffic(pix) if kernels == [depth] else None
+    traffic = read_traffic(pix, tv.get_tile((H, W))) if kernels == [depth] else None
 
     if args.copy_calibration:
         n = 64 * 1024 * 1024  # 256 MiB of float32
