@@ -189,7 +189,7 @@ def test_full_size_4096_sampled_windows():
     rng = np.random.default_rng(7)
     centres = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, 255),
                (H // 2, 256), (th - 1, 1000), (th, 1000), (5 * th, 511),
-               (H - 1, 2047), (17, W - 1)]
+               (H - 1, 2047), (17, W - 1), (100, 239), (100, 240), (3 * th, 480)]
     centres += [tuple(rng.integers(0, [H, W])) for _ in range(6)]
     m = N + 2
     for (cy, cx) in centres:

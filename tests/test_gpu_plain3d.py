@@ -138,3 +138,60 @@ def test_resume_and_graph_replay_are_bitwise():
     fb, _ = b.solve(gt, lam=0.1, max_iter=20, check_every=0, gap_tol=-1.0,
                     use_graph=1)
     assert np.array_equal(fa, fb.cpu().numpy())
+
+
+def _crop_bounds(c, r, n):
+    return max(c - r, 0), min(c + r + 1, n)
+
+
+def test_full_size_256cube_sampled_windows():
+    """256^3 in the default launch configuration: after N iterations a voxel
+    depends only on data within N + 1 voxels, so the oracle on a crop with
+    a margin of N + 2 (or the true volume edge) reproduces sampled windows
+    of the full-size run."""
+    from scenes import WORKLOADS
+    w = WORKLOADS["unrolled_256cube"]
+    _, g = scene3d(w["D"], w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    g32 = g.astype(np.float32)
+    del g
+    N = 10
+    th, tz, wpb = tv.get_tile3d(g32.shape)
+    print(f"case: 256^3 sampled windows, tile {(th, tz, wpb)}", flush=True)
+    f, p, _ = gpu_fixed(g32, N)
+    D, H, W = g32.shape
+    rng = np.random.default_rng(8)
+    centres = [(0, 0, 0), (D - 1, H - 1, W - 1), (0, H - 1, 0), (tz - 1, th - 1, 100),
+               (tz, th, 100), (2 * tz, 3 * th - 1, W - 1), (D // 2, H // 2, 0)]
+    centres += [tuple(rng.integers(0, [D, H, W])) for _ in range(4)]
+    m = N + 2
+    for c in centres:
+        b = [_crop_bounds(ci, m + 2, n) for ci, n in zip(c, (D, H, W))]
+        crop = g32[b[0][0]:b[0][1], b[1][0]:b[1][1], b[2][0]:b[2][1]].astype(np.float64)
+        fr, _, pr = oracle.run_fixed(crop, 0.1, S3, S3, N)
+        sl_g, sl_c = [], []
+        for (lo, hi), n in zip(b, (D, H, W)):
+            i0 = 0 if lo == 0 else m
+            i1 = (hi - lo) if hi == n else (hi - lo) - m
+            sl_g.append(slice(lo + i0, lo + i1))
+            sl_c.append(slice(i0, i1))
+        got = f[tuple(sl_g)]
+        exp = fr[tuple(sl_c)]
+        assert got.size > 0
+        assert rel(got, exp) <= RTOL, c
+        gp = p[(slice(None),) + tuple(sl_g)]
+        ep = pr[(slice(None),) + tuple(sl_c)]
+        assert np.max(np.abs(gp - ep)) <= 1e-5 * 0.1, c
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 1, 1), (1, 1, 300), (1, 3, 1),
+                                   (3, 2, 5), (70, 1, 1)])
+def test_degenerate_3d_shapes(shape):
+    """Volumes with unit axes (the forward difference along them vanishes)
+    and a single voxel (the iterate stays g) match the oracle."""
+    g32 = vol32(*shape, seed=3 + sum(shape), n_shapes=3) if min(shape) > 4 else \
+        np.random.default_rng(sum(shape)).uniform(0, 1, shape).astype(np.float32)
+    print(f"case: degenerate 3D {shape}", flush=True)
+    f, p, _ = gpu_fixed(g32, 17)
+    fr, _, pr = oracle.run_fixed(g32.astype(np.float64), 0.1, S3, S3, 17)
+    assert rel(f, fr) <= RTOL
+    assert np.max(np.abs(p - pr)) <= 1e-6
