@@ -202,8 +202,10 @@ def bench_unrolled_2d(dev, plain_mpix):
         "fwd_ms": ms_f, "fwd_bwd_ms": ms_fb,
         "mpix_its_fwd": work / (ms_f * 1e-3) / 1e6,
         "mpix_its_fwd_bwd": work / (ms_fb * 1e-3) / 1e6,
-        "fwd_vs_plain_4096": work / (ms_f * 1e-3) / 1e6 / plain_mpix,
-        "fwd_bwd_vs_plain_4096": work / (ms_fb * 1e-3) / 1e6 / plain_mpix,
+        "fwd_vs_plain_4096": (work / (ms_f * 1e-3) / 1e6 / plain_mpix
+                              if plain_mpix else None),
+        "fwd_bwd_vs_plain_4096": (work / (ms_fb * 1e-3) / 1e6 / plain_mpix
+                                  if plain_mpix else None),
     }
 
 
@@ -287,6 +289,27 @@ def bench_plain_3d(dev):
     }
 
 
+def copy_calibration(dev):
+    """Five device copies of 256 MiB: a transfer of known size against which
+    the HBM byte counters are scaled."""
+    import torch
+    n = 64 * 1024 * 1024  # 256 MiB of float32
+    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: 5 copies of 256 MiB done")
+
+
+EXTRA_WORKLOADS = {
+    "batch64_uneven": lambda dev: bench_batched(dev),
+    "unrolled_32x512": lambda dev, ref: bench_unrolled_2d(dev, ref),
+    "unrolled_256cube": lambda dev: bench_unrolled_3d(dev),
+    "plain_256cube": lambda dev: bench_plain_3d(dev),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +327,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size "
                          "(for scaling HBM counters)")
+    ap.add_argument("--only", default=None,
+                    choices=sorted(EXTRA_WORKLOADS),
+                    help="run only this secondary workload and print its record "
+                         "(for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -314,6 +341,15 @@ def main():
 
     import paper_1608_03589_amd as tv
     from scenes import WORKLOADS, scene2d
+
+    if args.only:
+        dev = torch.device("cuda:0")
+        fn = EXTRA_WORKLOADS[args.only]
+        rec = fn(dev, None) if args.only == "unrolled_32x512" else fn(dev)
+        if args.copy_calibration:
+            copy_calibration(dev)
+        print(json.dumps(rec), flush=True)
+        return
 
     w = WORKLOADS["denoise_4096"]
     iters = args.iters or w["iters"]
@@ -375,13 +411,7 @@ def main():
     traffic = read_traffic(pix, tv.get_tile((H, W))) if kernels == [depth] else None
 
     if args.copy_calibration:
-        n = 64 * 1024 * 1024  # 256 MiB of float32
-        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("copy calibration: 5 copies of 256 MiB done")
+        copy_calibration(dev)
 
     extra = {}
     if not args.no_extra:
