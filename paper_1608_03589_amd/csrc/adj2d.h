@@ -69,7 +69,7 @@ __device__ __forceinline__ void adj_project2(float qx, float qy, float sx,
                                              float sy, float lam, float lam2,
                                              float& tx, float& ty,
                                              float& ns_out, bool& outside) {
-  const float n2 = qx * qx + qy * qy;
+  const float n2 = sq2(qx, qy);
   outside = n2 > lam2;
   const float rn = inv_norm(n2);
   const float nx = qx * rn, ny = qy * rn;
@@ -136,12 +136,12 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
     F4 cb, nb, ta, tan;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      cb.v[j] = cur.f.v[j] + th * (cur.f.v[j] - cur.m.v[j]);
-      nb.v[j] = nxt.f.v[j] + th * (nxt.f.v[j] - nxt.m.v[j]);
+      cb.v[j] = extrap(cur.f.v[j], cur.m.v[j], th);
+      nb.v[j] = extrap(nxt.f.v[j], nxt.m.v[j], th);
       ta.v[j] = tau * (cur.a.v[j] * iopt);
       tan.v[j] = tau * (nxt.a.v[j] * iopt);
     }
-    const float rb = cur.rf + th * (cur.rf - cur.rm);
+    const float rb = extrap(cur.rf, cur.rm, th);
     const float rta = tau * (cur.ra * iopt);
     const float nbr = from_right(cb.v[0]);
     const float ntr = from_right(ta.v[0]);
@@ -156,8 +156,8 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
           (j < 3) ? ta.v[(j + 1) & 3] : (lane == kWave - 1 ? rta : ntr);
       const float gx = xf ? rgt - cb.v[j] : 0.0f;
       const float gy = dn ? nb.v[j] - cb.v[j] : 0.0f;
-      const float qx = pc.px.v[j] + sig * gx;
-      const float qy = pc.py.v[j] + sig * gy;
+      const float qx = dual_arg(pc.px.v[j], sig, gx);
+      const float qy = dual_arg(pc.py.v[j], sig, gy);
       project2(qx, qy, lam, lam2, pnx.v[j], pny.v[j]);
       const float sx = pc.rx.v[j] - (xf ? rgta - ta.v[j] : 0.0f);
       const float sy = pc.ry.v[j] - (dn ? tan.v[j] - ta.v[j] : 0.0f);
@@ -177,14 +177,14 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
       l_pn = 0.0f;
       l_t = 0.0f;
       if (hl) {
-        const float lb = cur.lf + th * (cur.lf - cur.lm);
-        const float lnb = nxt.lf + th * (nxt.lf - nxt.lm);
+        const float lb = extrap(cur.lf, cur.lm, th);
+        const float lnb = extrap(nxt.lf, nxt.lm, th);
         const float lta = tau * (cur.la * iopt);
         const float ltan = tau * (nxt.la * iopt);
         const float gx = cb.v[0] - lb;
         const float gy = dn ? lnb - lb : 0.0f;
-        const float qx = pc.lpx + sig * gx;
-        const float qy = pc.lpy + sig * gy;
+        const float qx = dual_arg(pc.lpx, sig, gx);
+        const float qy = dual_arg(pc.lpy, sig, gy);
         float hx, hy;
         project2(qx, qy, lam, lam2, hx, hy);
         const float sx = pc.lrx - (ta.v[0] - lta);
@@ -206,8 +206,8 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
         const float lt = (j == 0) ? l_t : tx.v[(j + 3) & 3];
         float d = pnx.v[j] - lpn;
         d = d + (pny.v[j] - up_pn.v[j]);
-        const float v = cur.f.v[j] + tau * d;
-        const float fnew = (v + tau * pc.g.v[j]) * iopt;
+        const float v = fmaf(tau, d, cur.f.v[j]);
+        const float fnew = fmaf(tau, pc.g.v[j], v) * iopt;
         const float alpha = cur.a.v[j] * iopt;
         gbo.v[j] = pc.gb.v[j] + tau * alpha;
         if (xc + j < nx)

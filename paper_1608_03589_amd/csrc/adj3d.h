@@ -59,8 +59,7 @@ __device__ __forceinline__ void adj_project3(float qx, float qy, float qz,
                                              float lam, float lam2, float& tx,
                                              float& ty, float& tz,
                                              float& ns_out, bool& outside) {
-  float n2 = qx * qx + qy * qy;
-  n2 = n2 + qz * qz;
+  const float n2 = sq3(qx, qy, qz);
   outside = n2 > lam2;
   const float rn = inv_norm(n2);
   const float ux = qx * rn, uy = qy * rn, uz = qz * rn;
@@ -164,15 +163,14 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
         F4 cb, db, zb, ta, tad, taz;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          cb.v[j] = cur.f[r].v[j] + th * (cur.f[r].v[j] - cur.m[r].v[j]);
-          db.v[j] = cur.f[r + 1].v[j] +
-                    th * (cur.f[r + 1].v[j] - cur.m[r + 1].v[j]);
-          zb.v[j] = nxt.f[r].v[j] + th * (nxt.f[r].v[j] - nxt.m[r].v[j]);
+          cb.v[j] = extrap(cur.f[r].v[j], cur.m[r].v[j], th);
+          db.v[j] = extrap(cur.f[r + 1].v[j], cur.m[r + 1].v[j], th);
+          zb.v[j] = extrap(nxt.f[r].v[j], nxt.m[r].v[j], th);
           ta.v[j] = tau * (cur.a[r].v[j] * iopt);
           tad.v[j] = tau * (cur.a[r + 1].v[j] * iopt);
           taz.v[j] = tau * (nxt.a[r].v[j] * iopt);
         }
-        const float rb = cur.rf[r] + th * (cur.rf[r] - cur.rm[r]);
+        const float rb = extrap(cur.rf[r], cur.rm[r], th);
         const float rta = tau * (cur.ra[r] * iopt);
         const float nbr = from_right(cb.v[0]);
         const float ntr = from_right(ta.v[0]);
@@ -188,9 +186,9 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
           const float gx = xf ? rgt - cb.v[j] : 0.0f;
           const float gy = dn ? db.v[j] - cb.v[j] : 0.0f;
           const float gz = zf ? zb.v[j] - cb.v[j] : 0.0f;
-          const float qx = pc.px[r].v[j] + sig * gx;
-          const float qy = pc.py[r].v[j] + sig * gy;
-          const float qz = pc.pz[r].v[j] + sig * gz;
+          const float qx = dual_arg(pc.px[r].v[j], sig, gx);
+          const float qy = dual_arg(pc.py[r].v[j], sig, gy);
+          const float qz = dual_arg(pc.pz[r].v[j], sig, gz);
           project3(qx, qy, qz, lam, lam2, pnx.v[j], pny.v[j], pnz.v[j]);
           const float sx = pc.rx[r].v[j] - (xf ? rgta - ta.v[j] : 0.0f);
           const float sy = pc.ry[r].v[j] - (dn ? tad.v[j] - ta.v[j] : 0.0f);
@@ -213,19 +211,19 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
             float l_pn = from_left(pnx.v[3]);
             float l_t = from_left(tx.v[3]);
             if (hl) {
-              const float lb = cur.lf[r] + th * (cur.lf[r] - cur.lm[r]);
+              const float lb = extrap(cur.lf[r], cur.lm[r], th);
               const float ldb =
-                  cur.lf[r + 1] + th * (cur.lf[r + 1] - cur.lm[r + 1]);
-              const float lzb = nxt.lf[r] + th * (nxt.lf[r] - nxt.lm[r]);
+                  extrap(cur.lf[r + 1], cur.lm[r + 1], th);
+              const float lzb = extrap(nxt.lf[r], nxt.lm[r], th);
               const float lta = tau * (cur.la[r] * iopt);
               const float ltad = tau * (cur.la[r + 1] * iopt);
               const float ltaz = tau * (nxt.la[r] * iopt);
               const float gx = cb.v[0] - lb;
               const float gy = dn ? ldb - lb : 0.0f;
               const float gz = zf ? lzb - lb : 0.0f;
-              const float qx = pc.lpx[ri] + sig * gx;
-              const float qy = pc.lpy[ri] + sig * gy;
-              const float qz = pc.lpz[ri] + sig * gz;
+              const float qx = dual_arg(pc.lpx[ri], sig, gx);
+              const float qy = dual_arg(pc.lpy[ri], sig, gy);
+              const float qz = dual_arg(pc.lpz[ri], sig, gz);
               float hx, hy, hz;
               project3(qx, qy, qz, lam, lam2, hx, hy, hz);
               const float sx = pc.lrx[ri] - (ta.v[0] - lta);
@@ -252,8 +250,8 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
               float d = pnx.v[j] - lpn;
               d = d + (pny.v[j] - up_pn.v[j]);
               d = d + (pnz.v[j] - pzn[ri].v[j]);
-              const float v = cur.f[r].v[j] + tau * d;
-              const float fnew = (v + tau * pc.g[ri].v[j]) * iopt;
+              const float v = fmaf(tau, d, cur.f[r].v[j]);
+              const float fnew = fmaf(tau, pc.g[ri].v[j], v) * iopt;
               const float alpha = cur.a[r].v[j] * iopt;
               gbo.v[j] = pc.gb[ri].v[j] + tau * alpha;
               if (xc + j < nx)

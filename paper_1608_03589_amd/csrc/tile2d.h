@@ -83,7 +83,7 @@ __device__ __forceinline__ RowP zeroP() {
 // Projection of q onto the disc of radius lam (lam2 = lam * lam).
 __device__ __forceinline__ void project2(float qx, float qy, float lam,
                                          float lam2, float& px, float& py) {
-  const float c = ball_scale(qx * qx + qy * qy, lam, lam2);
+  const float c = ball_scale(sq2(qx, qy), lam, lam2);
   px = qx * c;
   py = qy * c;
 }
@@ -237,12 +237,12 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
     F4 cb, nb4;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      cb.v[j] = cur.f.v[j] + th * (cur.f.v[j] - cur.m.v[j]);
-      nb4.v[j] = nxt.f.v[j] + th * (nxt.f.v[j] - nxt.m.v[j]);
+      cb.v[j] = extrap(cur.f.v[j], cur.m.v[j], th);
+      nb4.v[j] = extrap(nxt.f.v[j], nxt.m.v[j], th);
     }
-    const float lb = cur.lf + th * (cur.lf - cur.lm);
-    const float rb = cur.rf + th * (cur.rf - cur.rm);
-    const float lnb = nxt.lf + th * (nxt.lf - nxt.lm);
+    const float lb = extrap(cur.lf, cur.lm, th);
+    const float rb = extrap(cur.rf, cur.rm, th);
+    const float lnb = extrap(nxt.lf, nxt.lm, th);
     const float rf = cur.rf;
 
     // dual ascent on the extrapolated gradient, then the projection
@@ -255,7 +255,7 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
             (j < 3) ? cb.v[(j + 1) & 3] : (lane == kWave - 1 ? rb : nbr);
         const float gx = (xc + j < nx - 1) ? right - cb.v[j] : 0.0f;
         const float gy = dn ? nb4.v[j] - cb.v[j] : 0.0f;
-        project2(opx.v[j] + sig * gx, opy.v[j] + sig * gy, lam, lam2, npx.v[j],
+        project2(dual_arg(opx.v[j], sig, gx), dual_arg(opy.v[j], sig, gy), lam, lam2, npx.v[j],
                  npy.v[j]);
       }
     }
@@ -267,7 +267,7 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
         const float gx = cb.v[0] - lb;
         const float gy = dn ? lnb - lb : 0.0f;
         float hx, hy;
-        project2(pc.lpx + sig * gx, pc.lpy + sig * gy, lam, lam2, hx, hy);
+        project2(dual_arg(pc.lpx, sig, gx), dual_arg(pc.lpy, sig, gy), lam, lam2, hx, hy);
         left_n = hx;
         left_o = pc.lpx;
       } else {
@@ -282,8 +282,8 @@ __device__ __forceinline__ void sweep_tile(const TileCtx& c, double& acc_gap,
       for (int j = 0; j < 4; ++j) {
         const float lp = (j == 0) ? left_n : npx.v[(j + 3) & 3];
         const float d = (npx.v[j] - lp) + (npy.v[j] - up_pyn.v[j]);
-        const float v = cf.v[j] + tau * d;
-        fnew.v[j] = (v + tau * gg.v[j]) * iopt;
+        const float v = fmaf(tau, d, cf.v[j]);
+        fnew.v[j] = fmaf(tau, gg.v[j], v) * iopt;
       }
       if (lin) {
         st4(fn + o, fnew);

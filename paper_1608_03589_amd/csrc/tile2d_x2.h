@@ -110,7 +110,7 @@ __device__ __forceinline__ void sweep_tile_x2(const TileCtx2& c,
     r.r1y = c.PY[ro + cr1];
     r.r1g = c.G[ro + cr1];
   };
-  auto xb = [&](float f, float m) { return f + th * (f - m); };
+  auto xb = [&](float f, float m) { return extrap(f, m, th); };
 
   // ---- state carried from row to row (values of row r-1, or of row r
   // for the extrapolation of the current row)
@@ -156,20 +156,20 @@ __device__ __forceinline__ void sweep_tile_x2(const TileCtx2& c,
             (j < 3) ? ab.v[(j + 1) & 3] : (last_lane ? abR1 : abr);
         const float gx = (xc + j < nx - 1) ? right - ab.v[j] : 0.0f;
         const float gy = dnA ? abn.v[j] - ab.v[j] : 0.0f;
-        project2(pc.px.v[j] + sig * gx, pc.py.v[j] + sig * gy, lam, lam2, ax.v[j],
+        project2(dual_arg(pc.px.v[j], sig, gx), dual_arg(pc.py.v[j], sig, gy), lam, lam2, ax.v[j],
                  ay.v[j]);
       }
       {  // halo x0-2 (p_x only), x0-1 and x0+256
         float dummy;
         const float gx2 = abL1 - abL2;
         const float gy2 = dnA ? abnL2 - abL2 : 0.0f;
-        project2(pc.l2x + sig * gx2, pc.l2y + sig * gy2, lam, lam2, axL2, dummy);
+        project2(dual_arg(pc.l2x, sig, gx2), dual_arg(pc.l2y, sig, gy2), lam, lam2, axL2, dummy);
         const float gx1 = ab.v[0] - abL1;
         const float gy1 = dnA ? abnL1 - abL1 : 0.0f;
-        project2(pc.l1x + sig * gx1, pc.l1y + sig * gy1, lam, lam2, axL1, ayL1);
+        project2(dual_arg(pc.l1x, sig, gx1), dual_arg(pc.l1y, sig, gy1), lam, lam2, axL1, ayL1);
         const float gxr = (xR1 < nx - 1) ? abR2 - abR1 : 0.0f;
         const float gyr = dnA ? abnR1 - abR1 : 0.0f;
-        project2(pc.r1x + sig * gxr, pc.r1y + sig * gyr, lam, lam2, axR1, ayR1);
+        project2(dual_arg(pc.r1x, sig, gxr), dual_arg(pc.r1y, sig, gyr), lam, lam2, axR1, ayR1);
       }
       if (doFA) {
         float lft = from_left(ax.v[3]);
@@ -178,15 +178,15 @@ __device__ __forceinline__ void sweep_tile_x2(const TileCtx2& c,
         for (int j = 0; j < 4; ++j) {
           const float lp = (j == 0) ? lft : ax.v[(j + 3) & 3];
           const float d = (ax.v[j] - lp) + (ay.v[j] - AYm1.v[j]);
-          const float v = F0.v[j] + tau * d;
-          fa.v[j] = (v + tau * pc.g.v[j]) * iopt;
+          const float v = fmaf(tau, d, F0.v[j]);
+          fa.v[j] = fmaf(tau, pc.g.v[j], v) * iopt;
         }
         // x0-1 (its left neighbour x0-2 always exists when x0 > 0)
         const float dL = (axL1 - axL2) + (ayL1 - AYm1L1);
-        faL1 = ((F0L1 + tau * dL) + tau * pc.l1g) * iopt;
+        faL1 = fmaf(tau, pc.l1g, fmaf(tau, dL, F0L1)) * iopt;
         // x0+256: its left neighbour is this lane's last column
         const float dR = (axR1 - ax.v[3]) + (ayR1 - AYm1R1);
-        faR1 = ((F0R1 + tau * dR) + tau * pc.r1g) * iopt;
+        faR1 = fmaf(tau, pc.r1g, fmaf(tau, dR, F0R1)) * iopt;
         if (r >= y0 && r < y1 && lin) st4(c.FA + (int64_t)r * P + xc, fa);
       }
       if constexpr (GAP) {
@@ -238,14 +238,14 @@ __device__ __forceinline__ void sweep_tile_x2(const TileCtx2& c,
             (j < 3) ? bb0.v[(j + 1) & 3] : (last_lane ? bbR1a : bbr);
         const float gx = (xc + j < nx - 1) ? right - bb0.v[j] : 0.0f;
         const float gy = dnB ? bb1.v[j] - bb0.v[j] : 0.0f;
-        project2(AXm1.v[j] + sig * gx, AYm1.v[j] + sig * gy, lam, lam2, bx.v[j],
+        project2(dual_arg(AXm1.v[j], sig, gx), dual_arg(AYm1.v[j], sig, gy), lam, lam2, bx.v[j],
                  by.v[j]);
       }
       float bxL1, dummy;
       {
         const float gx = bb0.v[0] - bbL1a;
         const float gy = dnB ? bbL1b - bbL1a : 0.0f;
-        project2(AXm1L1 + sig * gx, AYm1L1 + sig * gy, lam, lam2, bxL1, dummy);
+        project2(dual_arg(AXm1L1, sig, gx), dual_arg(AYm1L1, sig, gy), lam, lam2, bxL1, dummy);
       }
       if (rb >= y0) {
         float lft = from_left(bx.v[3]);
@@ -255,8 +255,8 @@ __device__ __forceinline__ void sweep_tile_x2(const TileCtx2& c,
         for (int j = 0; j < 4; ++j) {
           const float lp = (j == 0) ? lft : bx.v[(j + 3) & 3];
           const float d = (bx.v[j] - lp) + (by.v[j] - BYm2.v[j]);
-          const float v = FAm1.v[j] + tau * d;
-          fb.v[j] = (v + tau * Gm1.v[j]) * iopt;
+          const float v = fmaf(tau, d, FAm1.v[j]);
+          fb.v[j] = fmaf(tau, Gm1.v[j], v) * iopt;
         }
         if (lin) {
           const int64_t o = (int64_t)rb * P + xc;

@@ -113,8 +113,8 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       F4 cb, nb;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        cb.v[j] = B.v[j] + th * (B.v[j] - D.v[j]);
-        nb.v[j] = A.v[j] + th * (A.v[j] - C.v[j]);
+        cb.v[j] = extrap(B.v[j], D.v[j], th);
+        nb.v[j] = extrap(A.v[j], C.v[j], th);
       }
       const float nbr = from_right(cb.v[0]);
       F4 npx, npy;
@@ -123,7 +123,7 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
         const float right = (j < 3) ? cb.v[j + 1] : nbr;
         const float gx = (xg + j < nx - 1) ? right - cb.v[j] : 0.0f;
         const float gy = dn ? nb.v[j] - cb.v[j] : 0.0f;
-        project2(EX.v[j] + sig * gx, EY.v[j] + sig * gy, lam, lam2, npx.v[j],
+        project2(dual_arg(EX.v[j], sig, gx), dual_arg(EY.v[j], sig, gy), lam, lam2, npx.v[j],
                  npy.v[j]);
       }
       const float left = from_left(npx.v[3]);
@@ -133,8 +133,8 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       for (int j = 0; j < 4; ++j) {
         const float lp = (j == 0) ? (xg > 0 ? left : 0.0f) : npx.v[j - 1];
         const float d = (npx.v[j] - lp) + (npy.v[j] - (up ? cy[s].v[j] : 0.0f));
-        const float v = B.v[j] + tau * d;
-        fnew.v[j] = (v + tau * Gv.v[j]) * iopt;
+        const float v = fmaf(tau, d, B.v[j]);
+        fnew.v[j] = fmaf(tau, Gv.v[j], v) * iopt;
       }
       fo[s] = fnew;
       pox[s] = npx;

@@ -48,9 +48,7 @@ struct Tile3DCtx {
 __device__ __forceinline__ void project3(float qx, float qy, float qz,
                                          float lam, float lam2, float& px,
                                          float& py, float& pz) {
-  float n2 = qx * qx + qy * qy;
-  n2 = n2 + qz * qz;
-  const float c = ball_scale(n2, lam, lam2);
+  const float c = ball_scale(sq3(qx, qy, qz), lam, lam2);
   px = qx * c;
   py = qy * c;
   pz = qz * c;
@@ -166,12 +164,11 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
         F4 cb, db, zb;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          cb.v[j] = cur.f[r].v[j] + th * (cur.f[r].v[j] - cur.m[r].v[j]);
-          db.v[j] = cur.f[r + 1].v[j] +
-                    th * (cur.f[r + 1].v[j] - cur.m[r + 1].v[j]);
-          zb.v[j] = nxt.f[r].v[j] + th * (nxt.f[r].v[j] - nxt.m[r].v[j]);
+          cb.v[j] = extrap(cur.f[r].v[j], cur.m[r].v[j], th);
+          db.v[j] = extrap(cur.f[r + 1].v[j], cur.m[r + 1].v[j], th);
+          zb.v[j] = extrap(nxt.f[r].v[j], nxt.m[r].v[j], th);
         }
-        const float rb = cur.rf[r] + th * (cur.rf[r] - cur.rm[r]);
+        const float rb = extrap(cur.rf[r], cur.rm[r], th);
         const float nbr = from_right(cb.v[0]);
         F4 npx, npy, npz;
 #pragma unroll
@@ -181,8 +178,8 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
           const float gx = (xc + j < nx - 1) ? right - cb.v[j] : 0.0f;
           const float gy = dn ? db.v[j] - cb.v[j] : 0.0f;
           const float gz = zf ? zb.v[j] - cb.v[j] : 0.0f;
-          project3(pc.px[r].v[j] + sig * gx, pc.py[r].v[j] + sig * gy,
-                   pc.pz[r].v[j] + sig * gz, lam, lam2, npx.v[j], npy.v[j],
+          project3(dual_arg(pc.px[r].v[j], sig, gx), dual_arg(pc.py[r].v[j], sig, gy),
+                   dual_arg(pc.pz[r].v[j], sig, gz), lam, lam2, npx.v[j], npy.v[j],
                    npz.v[j]);
         }
         if (r > 0) {
@@ -193,16 +190,16 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
             // uses it; hl is the same for the whole wave
             float left_n = from_left(npx.v[3]);
             if (hl) {
-              const float lb = cur.lf[r] + th * (cur.lf[r] - cur.lm[r]);
+              const float lb = extrap(cur.lf[r], cur.lm[r], th);
               const float ldb =
-                  cur.lf[r + 1] + th * (cur.lf[r + 1] - cur.lm[r + 1]);
-              const float lzb = nxt.lf[r] + th * (nxt.lf[r] - nxt.lm[r]);
+                  extrap(cur.lf[r + 1], cur.lm[r + 1], th);
+              const float lzb = extrap(nxt.lf[r], nxt.lm[r], th);
               const float gx = cb.v[0] - lb;
               const float gy = dn ? ldb - lb : 0.0f;
               const float gz = zf ? lzb - lb : 0.0f;
               float hx, hy, hz;
-              project3(pc.lx[ri] + sig * gx, pc.ly[ri] + sig * gy,
-                       pc.lz[ri] + sig * gz, lam, lam2, hx, hy, hz);
+              project3(dual_arg(pc.lx[ri], sig, gx), dual_arg(pc.ly[ri], sig, gy),
+                       dual_arg(pc.lz[ri], sig, gz), lam, lam2, hx, hy, hz);
               if (lane == 0) left_n = hx;
             } else if (lane == 0) {
               left_n = 0.0f;
@@ -213,8 +210,8 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
               const float lp = (j == 0) ? left_n : npx.v[(j + 3) & 3];
               float d = (npx.v[j] - lp) + (npy.v[j] - up.v[j]);
               d = d + (npz.v[j] - pzn[ri].v[j]);
-              const float v = cur.f[r].v[j] + tau * d;
-              fnew.v[j] = (v + tau * pc.g[ri].v[j]) * iopt;
+              const float v = fmaf(tau, d, cur.f[r].v[j]);
+              fnew.v[j] = fmaf(tau, pc.g[ri].v[j], v) * iopt;
             }
             if (lin) {
               const int64_t o = zo + (int64_t)y * P + xc;

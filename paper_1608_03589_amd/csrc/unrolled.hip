@@ -77,8 +77,7 @@ __device__ __forceinline__ float* plane(const PlaneSet& P, int b, int id) {
 
 template <int ND>
 __device__ __forceinline__ void project(const float* q, float lam, float* p) {
-  float n2 = q[0] * q[0] + q[1] * q[1];
-  if (ND == 3) n2 = n2 + q[2] * q[2];
+  const float n2 = ND == 3 ? sq3(q[0], q[1], q[2]) : sq2(q[0], q[1]);
   const float c = ball_scale(n2, lam, lam * lam);
 #pragma unroll
   for (int i = 0; i < ND; ++i) p[i] = q[i] * c;
@@ -110,17 +109,17 @@ __device__ __forceinline__ void dual_point(const float* fk, const float* fkm,
                                            const bool* fwd, float sig,
                                            float th, float* q, float* gfb) {
   const float f0 = fk[o];
-  const float fb = f0 + th * (f0 - fkm[o]);
+  const float fb = extrap(f0, fkm[o], th);
 #pragma unroll
   for (int c = 0; c < ND; ++c) {
     float gc = 0.0f;
     if (fwd[c]) {
       const float f1 = fk[o + st[c]];
-      const float fb1 = f1 + th * (f1 - fkm[o + st[c]]);
+      const float fb1 = extrap(f1, fkm[o + st[c]], th);
       gc = fb1 - fb;
     }
     gfb[c] = gc;
-    q[c] = pk[c * PL + o] + sig * gc;
+    q[c] = dual_arg(pk[c * PL + o], sig, gc);
   }
 }
 
@@ -251,8 +250,7 @@ __global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
                    cplane(P, q.b, ids.pk), P.plane, q.o, st, fwd, sig, theta,
                    qq, gfb);
     project<ND>(qq, lam, pn);
-    float n2 = qq[0] * qq[0] + qq[1] * qq[1];
-    if (ND == 3) n2 = n2 + qq[2] * qq[2];
+    const float n2 = ND == 3 ? sq3(qq[0], qq[1], qq[2]) : sq2(qq[0], qq[1]);
     float t[ND];
     if (n2 > lam * lam) {  // the forward's branch (ball_scale)
       const float rn = inv_norm(n2);
@@ -306,8 +304,8 @@ __global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
         div_point<ND>(cplane(P, q.b, ids.pn), P.plane, q.o, st, bwd);
     const float f = cplane(P, q.b, ids.fk)[q.o];
     const float g = cplane(P, q.b, ids.g)[q.o];
-    const float v = f + tau * d;
-    const float fn = (v + tau * g) * iopt;
+    const float v = fmaf(tau, d, f);
+    const float fn = fmaf(tau, g, v) * iopt;
     const float alpha = cplane(P, q.b, ids.a_in)[q.o] * iopt;
     float* gbar = plane(P, q.b, ids.gbar);
     gbar[q.o] = gbar[q.o] + tau * alpha;
