@@ -19,10 +19,15 @@ Contents
             variant, plain and batched solves
   unrolled  K unrolled iterations with per-iteration (lam, tau, sigma) and the
             reverse-mode adjoint of that unrolled map
+  tomo      the tomographic data term: discrete Radon transform and its
+            adjoint backprojection, the primal-dual iteration for
+            1/2 ||A f - g||^2 + TV or Tikhonov regulariser, energies, ||A||^2
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, exact finite algorithms or brute force (see the test
-files); the centre plateau of a single disc is pinned only approximately.
+files); the centre plateau of a single disc is pinned only approximately, and so are
+the tomographic operators' agreement with continuous line integrals and with
+the point-source backprojection (their exact pins are the geometric ones).
 """
 from .pdhg import (  # noqa: F401
     grad, div, project_ball, pdhg_iteration, primal_energy, dual_energy,

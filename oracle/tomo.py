@@ -1,0 +1,188 @@
+"""FP64 oracle for the tomographic data term (test infrastructure only).
+
+Problem: the paper's regularised reconstruction (Section 6, eq. opt) with its
+Radon transform as forward operator,
+
+    minimise_f  1/2 ||A f - g||^2 + lam * TV(f)          (reg = "tv")
+    minimise_f  1/2 ||A f - g||^2 + lam/2 * ||f||^2      (reg = "tikhonov")
+
+where the Tikhonov case is half of eq. opt, so that its optimality condition is
+the paper's normal equation (Section 6, eq. neq2) (A^T A + lam I) f = A^T g.
+
+Discretisation (pixel units, detector spacing 1):
+  * image f of shape (H, W); pixel (a, b) has centre
+        X_ab = (b + 1/2 - W/2,  a + 1/2 - H/2)
+    relative to the rotation centre (x along columns, y along rows);
+  * angles theta_k = k pi / n_angles, k = 0 .. n_angles-1 (the angle mesh of
+    the paper's table of symbols, Section 4), xi_k = (cos theta_k, sin theta_k)
+    as in Section 1 eq. L;
+  * detector bins t_i = i + 1/2 - n_det / 2, i = 0 .. n_det-1.
+
+Projection, the discrete Radon transform (Section 1 eq. P_theta, with the
+line's delta function replaced by the unit hat Lambda(s) = max(0, 1 - |s|)):
+    (A f)[k, i] = sum_ab f[a, b] Lambda(X_ab . xi_k - t_i).
+Backprojection, its exact transpose: linear interpolation of each projection
+at X_ab . xi_k, summed over the angles (Section 2 eq. bp_app without the factor
+dtheta; the sinogram counts as zero beyond the detector's ends):
+    (A^T s)[a, b] = sum_k interp(s[k, :], X_ab . xi_k).
+The pair satisfies the discrete form of Section 1 eq. adjoint,
+<A f, s> = <f, A^T s>.
+
+Sinograms are arrays of shape (n_angles, n_det): angle-major, t fastest.
+
+Iteration (Chambolle & Pock 2011, Algorithm 1, theta = 1, with the operator
+(A, grad) and one dual step size per block, sigma_r for the sinogram dual r and
+sigma_p for the gradient dual p):
+    fbar    = f^k + theta (f^k - f^{k-1})
+    r^{k+1} = (r^k + sigma_r (A fbar - g)) / (1 + sigma_r)
+    p^{k+1} = P_lam(p^k + sigma_p grad fbar)                       (tv)
+    f^{k+1} = f^k - tau A^T r^{k+1} + tau div p^{k+1}               (tv)
+    f^{k+1} = (f^k - tau A^T r^{k+1}) / (1 + tau lam)               (tikhonov)
+from f^0 = f^{-1} = 0 (or a given f^0), r^0 = 0, p^0 = 0.  Convergence needs
+tau (sigma_r ||A||^2 + sigma_p ||grad||^2) <= 1 (tv) or tau sigma_r ||A||^2
+<= 1 (tikhonov); ||A||^2 comes from :func:`opnorm_sq`.
+
+Plain NumPy in float64; nothing is blocked, fused or reordered.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .pdhg import div, grad, project_ball
+
+REGS = ("tv", "tikhonov")
+
+
+# --------------------------------------------------------------------------
+# Geometry.
+# --------------------------------------------------------------------------
+
+def angles(n_angles: int) -> np.ndarray:
+    """theta_k = k pi / n_angles (Section 4, table of symbols)."""
+    return np.arange(n_angles, dtype=np.float64) * (math.pi / n_angles)
+
+
+def pixel_centres(H: int, W: int):
+    """(x, y) of every pixel centre, each of shape (H, W)."""
+    x = np.arange(W, dtype=np.float64) + 0.5 - W / 2.0
+    y = np.arange(H, dtype=np.float64) + 0.5 - H / 2.0
+    return np.broadcast_to(x[None, :], (H, W)), np.broadcast_to(y[:, None], (H, W))
+
+
+def detector(n_det: int) -> np.ndarray:
+    """t_i = i + 1/2 - n_det / 2."""
+    return np.arange(n_det, dtype=np.float64) + 0.5 - n_det / 2.0
+
+
+# --------------------------------------------------------------------------
+# The operator pair.  project() scatters every pixel onto the two bins its
+# hat overlaps; backproject() gathers by linear interpolation.  They are
+# written independently, so their adjointness is a check, not a tautology.
+# --------------------------------------------------------------------------
+
+def project(f: np.ndarray, n_angles: int, n_det: int) -> np.ndarray:
+    """A f: shape (n_angles, n_det)."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    x, y = pixel_centres(H, W)
+    t0 = 0.5 - n_det / 2.0
+    out = np.zeros((n_angles, n_det), dtype=np.float64)
+    fv = f.ravel()
+    for k, th in enumerate(angles(n_angles)):
+        u = (x * math.cos(th) + y * math.sin(th)).ravel()
+        v = u - t0                      # position in bin units: bin i at v = i
+        i0 = np.floor(v).astype(np.int64)
+        w = v - i0                      # weight of bin i0 + 1
+        for idx, wt in ((i0, 1.0 - w), (i0 + 1, w)):
+            ok = (idx >= 0) & (idx < n_det)
+            np.add.at(out[k], idx[ok], fv[ok] * wt[ok])
+    return out
+
+
+def backproject(s: np.ndarray, H: int, W: int) -> np.ndarray:
+    """A^T s: shape (H, W)."""
+    s = np.asarray(s, dtype=np.float64)
+    n_angles, n_det = s.shape
+    x, y = pixel_centres(H, W)
+    t0 = 0.5 - n_det / 2.0
+    out = np.zeros((H, W), dtype=np.float64)
+    for k, th in enumerate(angles(n_angles)):
+        ext = np.concatenate(([0.0], s[k], [0.0]))   # ext[i + 1] = s[k, i]
+        v = x * math.cos(th) + y * math.sin(th) - t0
+        i0 = np.floor(v).astype(np.int64)
+        w = v - i0
+        lo = np.clip(i0, -1, n_det) + 1
+        hi = np.clip(i0 + 1, -1, n_det) + 1
+        out += (1.0 - w) * ext[lo] + w * ext[hi]
+    return out
+
+
+def opnorm_sq(H: int, W: int, n_angles: int, n_det: int, iters: int = 50):
+    """Power iteration for ||A||^2 = largest eigenvalue of A^T A, from the
+    all-ones image.  Returns the Rayleigh quotient after ``iters`` steps."""
+    v = np.ones((H, W), dtype=np.float64)
+    v /= np.linalg.norm(v)
+    est = 0.0
+    for _ in range(iters):
+        w = backproject(project(v, n_angles, n_det), H, W)
+        est = float(np.sum(v * w))
+        nrm = np.linalg.norm(w)
+        if nrm == 0.0:
+            return 0.0
+        v = w / nrm
+    return est
+
+
+# --------------------------------------------------------------------------
+# Energy and iteration.
+# --------------------------------------------------------------------------
+
+def energy(f: np.ndarray, g: np.ndarray, lam: float, reg: str = "tv"):
+    """(data term, regulariser term, total) of the problem above."""
+    f = np.asarray(f, dtype=np.float64)
+    res = project(f, *np.shape(g)) - np.asarray(g, dtype=np.float64)
+    data = 0.5 * float(np.sum(res * res))
+    if reg == "tv":
+        gr = grad(f)
+        regv = lam * float(np.sum(np.sqrt(np.sum(gr * gr, axis=0))))
+    elif reg == "tikhonov":
+        regv = 0.5 * lam * float(np.sum(f * f))
+    else:
+        raise ValueError(reg)
+    return data, regv, data + regv
+
+
+def init_state(H: int, W: int, n_angles: int, n_det: int, f0=None):
+    f = np.zeros((H, W)) if f0 is None else np.array(f0, dtype=np.float64)
+    return dict(f=f, f_prev=f.copy(), r=np.zeros((n_angles, n_det)),
+                p=np.zeros((2, H, W)))
+
+
+def iteration(state, g, lam, tau, sigma_r, sigma_p, reg="tv", theta=1.0):
+    """One iteration; returns the new state (the input is not modified)."""
+    f, fp, r, p = state["f"], state["f_prev"], state["r"], state["p"]
+    H, W = f.shape
+    fbar = f + theta * (f - fp)
+    r_new = (r + sigma_r * (project(fbar, *r.shape) - g)) / (1.0 + sigma_r)
+    bp = backproject(r_new, H, W)
+    if reg == "tv":
+        p_new = project_ball(p + sigma_p * grad(fbar), lam)
+        f_new = f - tau * bp + tau * div(p_new)
+    elif reg == "tikhonov":
+        p_new = p
+        f_new = (f - tau * bp) / (1.0 + tau * lam)
+    else:
+        raise ValueError(reg)
+    return dict(f=f_new, f_prev=f, r=r_new, p=p_new)
+
+
+def run(g, H, W, lam, tau, sigma_r, sigma_p, n_iter, reg="tv", f0=None,
+        theta=1.0):
+    """``n_iter`` iterations from the initial state; returns the state."""
+    g = np.asarray(g, dtype=np.float64)
+    st = init_state(H, W, g.shape[0], g.shape[1], f0)
+    for _ in range(n_iter):
+        st = iteration(st, g, lam, tau, sigma_r, sigma_p, reg, theta)
+    return st

@@ -23,6 +23,9 @@ __all__ = [
     "scene3d",
     "batch_sides",
     "batch_scenes",
+    "phantom2d",
+    "phantom_sinogram",
+    "tomo_scene",
     "WORKLOADS",
 ]
 
@@ -151,7 +154,75 @@ def batch_scenes(n: int = 64, seed: int = 3000, n_shapes: int = 20,
     return out
 
 
-# The five workloads, by what they are.
+def phantom2d(H: int, W: int, n_ellipses: int = 32, seed: int = 0):
+    """Random ellipse phantom inside the disc inscribed in the image.
+
+    Returns ``(image, ellipses)``.  Each ellipse is a tuple
+    ``(cx, cy, a, b, phi, rho)``: centre relative to the image centre (x along
+    columns, y along rows, pixel units), semi-axes a, b of U[0.02, 0.15] * m
+    (m = min(H, W)), rotation phi of its a-axis from the x-axis, U[0, pi), and
+    intensity rho of U[0.1, 1].  Centres lie within 0.3 m of the image centre,
+    so every ellipse stays inside radius 0.45 m.  Intensities add where
+    ellipses overlap; the image samples the phantom at pixel centres
+    (b + 1/2 - W/2, a + 1/2 - H/2).
+    """
+    rng = np.random.default_rng(seed)
+    m = float(min(H, W))
+    ell = []
+    for _ in range(n_ellipses):
+        rc = 0.3 * m * math.sqrt(rng.uniform(0.0, 1.0))
+        ac = rng.uniform(0.0, 2.0 * math.pi)
+        a, b = rng.uniform(0.02, 0.15, size=2) * m
+        phi = rng.uniform(0.0, math.pi)
+        rho = rng.uniform(0.1, 1.0)
+        ell.append((rc * math.cos(ac), rc * math.sin(ac), float(a), float(b),
+                    float(phi), float(rho)))
+    x = (np.arange(W) + 0.5 - W / 2.0)[None, :]
+    y = (np.arange(H) + 0.5 - H / 2.0)[:, None]
+    img = np.zeros((H, W), dtype=np.float64)
+    for cx, cy, a, b, phi, rho in ell:
+        c, s = math.cos(phi), math.sin(phi)
+        u = (x - cx) * c + (y - cy) * s
+        v = -(x - cx) * s + (y - cy) * c
+        img += rho * ((u / a) ** 2 + (v / b) ** 2 <= 1.0)
+    return img, ell
+
+
+def phantom_sinogram(ellipses, n_angles: int, n_det: int, noise: float = 0.0,
+                     seed: int = 0):
+    """Synthetic measurements of a :func:`phantom2d` phantom.
+
+    Exact line integrals of the continuous phantom (sum over ellipses of
+    rho times the chord length) along the lines {X . (cos theta, sin theta) =
+    t}, theta_k = k pi / n_angles, t_i = i + 1/2 - n_det / 2, plus Gaussian
+    noise of standard deviation ``noise`` times the largest clean value.
+    Returns ``(clean, noisy)`` of shape (n_angles, n_det).
+    """
+    th = (np.arange(n_angles) * (math.pi / n_angles))[:, None]
+    t = (np.arange(n_det) + 0.5 - n_det / 2.0)[None, :]
+    out = np.zeros((n_angles, n_det), dtype=np.float64)
+    for cx, cy, a, b, phi, rho in ellipses:
+        ct = cx * np.cos(th) + cy * np.sin(th)          # centre's offset
+        h2 = (a * np.cos(th - phi)) ** 2 + (b * np.sin(th - phi)) ** 2
+        d2 = h2 - (t - ct) ** 2
+        out += np.where(d2 > 0.0,
+                        rho * 2.0 * a * b * np.sqrt(np.maximum(d2, 0.0)) / h2,
+                        0.0)
+    rng = np.random.default_rng(seed + 1)
+    noisy = out + rng.normal(0.0, noise * float(out.max(initial=0.0)),
+                             size=out.shape)
+    return out, noisy
+
+
+def tomo_scene(H: int, W: int, n_angles: int, n_det: int,
+               n_ellipses: int = 32, noise: float = 0.01, seed: int = 0):
+    """``(image, clean sinogram, noisy sinogram)`` of one phantom."""
+    img, ell = phantom2d(H, W, n_ellipses, seed)
+    clean, noisy = phantom_sinogram(ell, n_angles, n_det, noise, seed)
+    return img, clean, noisy
+
+
+# The six workloads, by what they are.
 WORKLOADS = {
     "denoise_256": dict(kind="2d", H=256, W=256, n_shapes=20, noise=0.1,
                         seed=1000, lam=0.1, iters=1000),
@@ -165,4 +236,9 @@ WORKLOADS = {
     "unrolled_256cube": dict(kind="unrolled3d", D=256, H=256, W=256,
                              n_shapes=32, noise=0.1, seed=5000, K=100,
                              ckpt_every=10),
+    # a 2048^2 slice from 1000 projections of 2048 rays: the size of the
+    # paper's measured sinograms (Section 7)
+    "tomo_2048x1000": dict(kind="tomo", H=2048, W=2048, n_angles=1000,
+                           n_det=2048, n_ellipses=32, noise=0.01, seed=6000,
+                           iters=20),
 }

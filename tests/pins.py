@@ -152,3 +152,29 @@ def tv2d_bruteforce(g, lam):
                    options=dict(ftol=1e-16, maxiter=2000))
     f = (gv - G.T @ res.x).reshape(shape)
     return f, res
+
+
+# --------------------------------------------------------------------------
+# Reference solver of the tomographic TV problem
+#   min_f 1/2 ||A f - g||^2 + lam sum_i |(G f)_i|_2
+# by ADMM on the split z = G f with exact dense f-solves (Boyd et al. 2011,
+# Section 6.4.1): a different algorithm from the primal-dual iteration, with
+# A given as a dense matrix and G the explicit gradient matrix above.
+# --------------------------------------------------------------------------
+
+def tomo_tv_admm(A, g, lam, shape, rho=10.0, iters=20000):
+    N = int(np.prod(shape))
+    G = grad_matrix(shape).toarray()
+    Minv = np.linalg.inv(A.T @ A + rho * G.T @ G)
+    Atg = A.T @ np.asarray(g, dtype=np.float64).ravel()
+    z = np.zeros(2 * N)
+    u = np.zeros(2 * N)
+    f = np.zeros(N)
+    for _ in range(iters):
+        f = Minv @ (Atg + rho * G.T @ (z - u))
+        v = (G @ f + u).reshape(2, N)
+        nv = np.sqrt(np.sum(v * v, axis=0))
+        shrink = np.maximum(0.0, 1.0 - (lam / rho) / np.maximum(nv, 1e-300))
+        z = (v * shrink).ravel()
+        u = u + G @ f - z
+    return f.reshape(shape)

@@ -1,0 +1,192 @@
+"""Pins of the FP64 tomography oracle (no GPU).
+
+The projection and the backprojection are pinned by what the geometry fixes
+exactly (adjointness, mass and first moment of every projection, line sums at
+0 and 90 degrees, the half-turn and transpose symmetries), against the
+independent line integrals of an ellipse phantom (Section 1 eq. P_theta), and
+against the backprojection of a point source (Section 5, Example I: 1/|x - a|
+once the printed form's sine and cosine are put back in place).  The
+iteration is pinned by its first step in closed form, by the normal equation
+of the Tikhonov problem (Section 6, eq. neq2), by the constant solution for a
+large TV weight and by the TV solution of an independent solver (ADMM).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import tomo
+from pins import tomo_tv_admm
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def dense_A(H, W, na, nd):
+    cols = []
+    for j in range(H * W):
+        e = np.zeros(H * W)
+        e[j] = 1.0
+        cols.append(tomo.project(e.reshape(H, W), na, nd).ravel())
+    return np.stack(cols, axis=1)
+
+
+@pytest.mark.parametrize("H,W,na,nd", [(37, 53, 30, 41), (16, 16, 7, 40),
+                                       (5, 9, 1, 3), (20, 11, 64, 80)])
+def test_adjoint_pair(H, W, na, nd):
+    f = rng(1).normal(size=(H, W))
+    s = rng(2).normal(size=(na, nd))
+    lhs = float(np.sum(tomo.project(f, na, nd) * s))
+    rhs = float(np.sum(f * tomo.backproject(s, H, W)))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + np.abs(f).sum() * np.abs(s).sum() * 1e-3)
+
+
+@pytest.mark.parametrize("H,W,na", [(37, 53, 30), (64, 64, 48), (9, 4, 13)])
+def test_mass_and_first_moment_of_every_projection(H, W, na):
+    nd = int(math.ceil(math.hypot(H, W))) + 3
+    f = rng(3).uniform(-1, 2, size=(H, W))
+    s = tomo.project(f, na, nd)
+    t = tomo.detector(nd)
+    x, y = tomo.pixel_centres(H, W)
+    for k, th in enumerate(tomo.angles(na)):
+        assert s[k].sum() == pytest.approx(f.sum(), rel=1e-12, abs=1e-12)
+        mom = float(np.sum(f * (x * math.cos(th) + y * math.sin(th))))
+        assert float(np.sum(t * s[k])) == pytest.approx(mom, rel=1e-11, abs=1e-10)
+
+
+def test_line_sums_at_0_and_90_degrees():
+    H, W, na = 14, 22, 8
+    nd = 30                       # nd - W and nd - H even: bins on pixel centres
+    f = rng(4).normal(size=(H, W))
+    s = tomo.project(f, na, nd)
+    ox, oy = (nd - W) // 2, (nd - H) // 2
+    np.testing.assert_allclose(s[0, ox:ox + W], f.sum(axis=0), rtol=0, atol=1e-12)
+    assert np.all(s[0, :ox] == 0) and np.all(s[0, ox + W:] == 0)
+    np.testing.assert_allclose(s[na // 2, oy:oy + H], f.sum(axis=1), rtol=0, atol=1e-12)
+
+
+def test_half_turn_and_transpose_symmetries():
+    N, na, nd = 24, 12, 37
+    f = rng(5).normal(size=(N, N))
+    s = tomo.project(f, na, nd)
+    np.testing.assert_allclose(tomo.project(f[::-1, ::-1], na, nd), s[:, ::-1],
+                               rtol=0, atol=1e-12)
+    sT = tomo.project(f.T, na, nd)
+    for k in range(na):
+        ref = s[na // 2 - k] if k <= na // 2 else s[3 * na // 2 - k, ::-1]
+        np.testing.assert_allclose(sT[k], ref, rtol=0, atol=1e-12)
+
+
+def test_projection_of_ellipse_phantom_matches_line_integrals():
+    # pixel sampling of the phantom costs a few percent; a wrong scale, axis
+    # or sign costs far more
+    img, clean, _ = scenes.tomo_scene(128, 128, 60, 184, n_ellipses=12, seed=7)
+    s = tomo.project(img, 60, 184)
+    err = np.linalg.norm(s - clean) / np.linalg.norm(clean)
+    assert err < 0.03
+    wrong = tomo.project(img[::-1, :], 60, 184)   # y axis flipped
+    assert np.linalg.norm(wrong - clean) / np.linalg.norm(clean) > 0.3
+
+
+def test_point_source_backprojection():
+    # dtheta * A^T A e_a approximates the backprojection of a point source's
+    # sinogram, 1/|x - a| (unit-integral hat kernels in t).  Pixel by pixel
+    # the discrete kernel aliases (about +-30 %), so the check is on annulus
+    # means and on 7 x 7 local means.
+    from scipy.ndimage import uniform_filter
+    N, na = 96, 1440
+    nd = 140
+    f = np.zeros((N, N))
+    a, b = 40, 51
+    f[a, b] = 1.0
+    bimg = (math.pi / na) * tomo.backproject(tomo.project(f, na, nd), N, N)
+    x, y = tomo.pixel_centres(N, N)
+    r = np.hypot(x - x[a, b], y - y[a, b])
+    for lo, hi in ((15, 25), (25, 35)):
+        ring = (r >= lo) & (r <= hi)
+        assert abs(float(np.mean(bimg[ring] * r[ring])) - 1.0) < 0.003
+    ring = (r >= 15) & (r <= 35)
+    local = uniform_filter(bimg, 7) / uniform_filter(1.0 / np.maximum(r, 1e-9), 7)
+    assert float(np.max(np.abs(local[ring] - 1.0))) < 0.05
+
+
+def test_opnorm_is_largest_eigenvalue():
+    H, W, na, nd = 10, 12, 16, 20
+    A = dense_A(H, W, na, nd)
+    lmax = float(np.linalg.eigvalsh(A.T @ A)[-1])
+    assert tomo.opnorm_sq(H, W, na, nd, 400) == pytest.approx(lmax, rel=1e-9)
+
+
+def test_first_iteration_closed_form():
+    H, W, na, nd = 12, 15, 9, 21
+    g = rng(6).normal(size=(na, nd))
+    tau, sr, sp = 0.02, 0.03, 0.5
+    for reg, lam in (("tv", 0.7), ("tikhonov", 0.7)):
+        st = tomo.iteration(tomo.init_state(H, W, na, nd), g, lam, tau, sr, sp, reg)
+        r1 = -sr * g / (1 + sr)
+        np.testing.assert_allclose(st["r"], r1, rtol=1e-14, atol=1e-15)
+        f1 = -tau * tomo.backproject(r1, H, W)
+        if reg == "tikhonov":
+            f1 = f1 / (1 + tau * lam)
+        np.testing.assert_allclose(st["f"], f1, rtol=1e-13, atol=1e-15)
+        assert np.all(st["p"] == 0)
+
+
+def test_tikhonov_limit_solves_the_normal_equation():
+    H, W, na, nd = 10, 8, 12, 16
+    img, _, g = scenes.tomo_scene(H, W, na, nd, n_ellipses=4, noise=0.05, seed=8)
+    lam = 3.0
+    L2 = tomo.opnorm_sq(H, W, na, nd, 200)
+    tau = sr = 0.99 / math.sqrt(L2)
+    st = tomo.run(g, H, W, lam, tau, sr, 0.0, 3000, reg="tikhonov")
+    A = dense_A(H, W, na, nd)
+    ref = np.linalg.solve(A.T @ A + lam * np.eye(H * W), A.T @ g.ravel())
+    err = np.linalg.norm(st["f"].ravel() - ref) / np.linalg.norm(ref)
+    assert err < 1e-9
+
+
+def test_tv_large_weight_gives_the_best_constant():
+    H, W, na, nd = 8, 9, 10, 16
+    _, _, g = scenes.tomo_scene(H, W, na, nd, n_ellipses=3, noise=0.05, seed=9)
+    L2 = tomo.opnorm_sq(H, W, na, nd, 200)
+    tau = 1.0 / math.sqrt(L2)
+    sr, sp = 0.5 / math.sqrt(L2), math.sqrt(L2) / 16
+    st = tomo.run(g, H, W, 1e4, tau, sr, sp, 7000, reg="tv")
+    a1 = tomo.project(np.ones((H, W)), na, nd)
+    c = float(np.sum(a1 * g) / np.sum(a1 * a1))
+    np.testing.assert_allclose(st["f"], c, rtol=1e-6, atol=0)
+
+
+def test_tv_limit_matches_an_independent_solver():
+    H, W, na, nd = 8, 7, 12, 14
+    _, _, g = scenes.tomo_scene(H, W, na, nd, n_ellipses=4, noise=0.05, seed=10)
+    lam = 2.0
+    L2 = tomo.opnorm_sq(H, W, na, nd, 200)
+    tau = 1.0 / math.sqrt(L2)
+    sr, sp = 0.5 / math.sqrt(L2), math.sqrt(L2) / 16
+    st = tomo.run(g, H, W, lam, tau, sr, sp, 10000, reg="tv")
+    ref = tomo_tv_admm(dense_A(H, W, na, nd), g, lam, (H, W), rho=10.0, iters=3000)
+    assert np.linalg.norm(st["f"] - ref) / np.linalg.norm(ref) < 1e-6
+    # the data term's dual variable converges to the residual A f - g
+    res = tomo.project(st["f"], na, nd) - g
+    assert np.linalg.norm(st["r"] - res) / np.linalg.norm(res) < 1e-6
+
+
+def test_energy_terms():
+    H, W, na, nd = 11, 13, 9, 19
+    f = rng(11).normal(size=(H, W))
+    g = rng(12).normal(size=(na, nd))
+    lam = 0.3
+    A = dense_A(H, W, na, nd)
+    res = A @ f.ravel() - g.ravel()
+    from pins import grad_matrix
+    Gf = (grad_matrix((H, W)) @ f.ravel()).reshape(2, -1)
+    d, r, tot = tomo.energy(f, g, lam, "tv")
+    assert d == pytest.approx(0.5 * res @ res, rel=1e-13)
+    assert r == pytest.approx(lam * np.sum(np.hypot(Gf[0], Gf[1])), rel=1e-13)
+    assert tot == pytest.approx(d + r, rel=1e-15)
+    d2, r2, _ = tomo.energy(f, g, lam, "tikhonov")
+    assert d2 == pytest.approx(d, rel=1e-15)
+    assert r2 == pytest.approx(0.5 * lam * np.sum(f * f), rel=1e-13)
