@@ -309,6 +309,113 @@ int tvpd_unrolled_backward(const tvpd_shape* shape, int32_t batch,
  * only in summation order.  Process-wide setting. */
 int tvpd_set_fused_adjoint(int32_t on);
 
+/* ---------------------------------------------------------------------
+ * Tomographic data term.  The paper's reconstruction problem (Section 6,
+ * eq. opt) with its Radon transform as forward operator:
+ *
+ *     minimise_f  1/2 ||A f - g||^2 + lam TV(f)             (TVPD_REG_TV)
+ *     minimise_f  1/2 ||A f - g||^2 + lam/2 ||f||^2         (TVPD_REG_TIKHONOV)
+ *
+ * (the Tikhonov form is half of eq. opt; its optimality condition is the
+ * normal equation (A^T A + lam I) f = A^T g of Section 6, eq. neq2).
+ *
+ * Geometry, in pixel units with detector spacing 1: image f is [ny][nx]
+ * (dense, row-major), pixel (a, b) centred at x = b + 1/2 - nx/2 (along
+ * columns), y = a + 1/2 - ny/2 (along rows); angles theta_k = k pi / n_angles
+ * (k < n_angles, the angle mesh of Section 4); bins t_i = i + 1/2 - n_det/2;
+ * a sinogram is [n_angles][n_det] (dense, t fastest).
+ *
+ *   A f    [k][i] = sum_ab f[a][b] max(0, 1 - |x cos theta_k + y sin theta_k - t_i|)
+ *              (the Radon transform, Section 1 eq. P_theta, with the line's
+ *               delta replaced by the unit hat: pixel-driven, linear weights)
+ *   A^T s  [a][b] = sum_k (linear interpolation of s[k][.] at x cos + y sin,
+ *              zero beyond the detector's ends)
+ *              (its exact transpose: the backprojection of Section 2,
+ *               eq. bp_app, without the factor pi / n_angles)
+ *
+ * Iteration (Chambolle & Pock 2011, Algorithm 1, with the operator
+ * (A, grad) and dual steps sigma_r for the sinogram dual r, sigma_p for the
+ * gradient dual p):
+ *     fbar    = f^k + theta (f^k - f^{k-1})
+ *     r^{k+1} = (r^k + sigma_r (A fbar - g)) / (1 + sigma_r)
+ *     p^{k+1} = projection of p^k + sigma_p grad fbar onto {|p_i|_2 <= lam}   (TV)
+ *     f^{k+1} = f^k - tau A^T r^{k+1} + tau div p^{k+1}                       (TV)
+ *     f^{k+1} = (f^k - tau A^T r^{k+1}) / (1 + tau lam)                        (Tikhonov)
+ * from f^0 = f^{-1} = f0 (or 0), r^0 = 0, p^0 = 0; grad, div as above.
+ * Convergence needs tau (sigma_r ||A||^2 + sigma_p ||grad||^2) <= 1 (TV) or
+ * tau sigma_r ||A||^2 <= 1 (Tikhonov); tvpd_tomo_opnorm estimates ||A||^2.
+ * The library does not check this condition.
+ *
+ * All tomography calls share one workspace type, sized by
+ * tvpd_tomo_workspace_size for the geometry; it holds the iteration state
+ * (k, f ring, r, p ring), padded copies of the extrapolated image and its
+ * transpose, an angle table and reduction partials.
+ * ------------------------------------------------------------------- */
+
+typedef struct tvpd_tomo_geom {
+  int32_t ny, nx;      /* image rows and columns, >= 1 */
+  int32_t n_angles;    /* >= 1 */
+  int32_t n_det;       /* >= 1 */
+} tvpd_tomo_geom;
+
+enum { TVPD_REG_TV = 0, TVPD_REG_TIKHONOV = 1 };
+
+/* lam >= 0; tau, sigma_r > 0; sigma_p > 0 for TV (unused for Tikhonov);
+ * theta in [0, 1]; reg one of TVPD_REG_*. */
+typedef struct tvpd_tomo_params {
+  float lam, tau, sigma_r, sigma_p, theta;
+  int32_t reg;
+} tvpd_tomo_params;
+
+/* Workspace bytes for `geom` (host out).  Sizes are limited so that every
+ * index fits in int32: ny, nx, n_det <= 32768, n_angles <= 65535. */
+int tvpd_tomo_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes);
+
+/* sino = A f.  f: device [ny][nx]; sino: device [n_angles][n_det].  Uses the
+ * workspace's scratch planes only (the iteration state is left alone). */
+int tvpd_radon_forward(const tvpd_tomo_geom* geom, const float* f, float* sino,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* img = A^T sino.  sino: device [n_angles][n_det]; img: device [ny][nx].
+ * Uses no workspace state except the angle table (rebuilt by the call). */
+int tvpd_radon_backward(const tvpd_tomo_geom* geom, const float* sino,
+                        float* img, void* ws, size_t ws_bytes, void* stream);
+
+/* Start an iteration: f^0 = f^{-1} = f0 (device [ny][nx], or NULL for 0),
+ * r^0 = 0, p^0 = 0, k = 0. */
+int tvpd_tomo_init(const tvpd_tomo_geom* geom, const float* f0, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* n_iter >= 0 iterations from the workspace's state.  g: device
+ * [n_angles][n_det], the measured sinogram. */
+int tvpd_tomo_step(const tvpd_tomo_geom* geom, const float* g,
+                   const tvpd_tomo_params* prm, int32_t n_iter, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Copy the current state out (device buffers, each may be NULL): f = f^k
+ * [ny][nx], r = r^k [n_angles][n_det], p = p^k [2][ny][nx] (x component
+ * first).  k (host, may be NULL) receives the iteration count and
+ * synchronises the stream. */
+int tvpd_tomo_read(const tvpd_tomo_geom* geom, const void* ws, size_t ws_bytes,
+                   float* f, float* r, float* p, int32_t* k, void* stream);
+
+/* Energies of the current f^k (host out[3]: data term 1/2 ||A f - g||^2,
+ * regulariser term, their sum), accumulated in float64.  Synchronises. */
+int tvpd_tomo_energy(const tvpd_tomo_geom* geom, const float* g, float lam,
+                     int32_t reg, void* ws, size_t ws_bytes, double* out,
+                     void* stream);
+
+/* ||A||^2 by `iters` >= 1 steps of the power iteration on A^T A from the
+ * constant image (host out: the last Rayleigh quotient).  Uses scratch
+ * planes only.  Synchronises. */
+int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
+                     size_t ws_bytes, double* out, void* stream);
+
+/* tvpd_tomo_init(f0 = NULL) + tvpd_tomo_step(n_iter) + f_out = f^n_iter. */
+int tvpd_tomo_solve(const tvpd_tomo_geom* geom, const float* g,
+                    const tvpd_tomo_params* prm, int32_t n_iter, float* f_out,
+                    void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

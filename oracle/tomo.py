@@ -186,3 +186,38 @@ def run(g, H, W, lam, tau, sigma_r, sigma_p, n_iter, reg="tv", f0=None,
     for _ in range(n_iter):
         st = iteration(st, g, lam, tau, sigma_r, sigma_p, reg, theta)
     return st
+
+
+# --------------------------------------------------------------------------
+# Single entries, for sampled checks of large problems: the definitions of
+# the two operators evaluated at chosen outputs only.
+# --------------------------------------------------------------------------
+
+def project_at(f: np.ndarray, n_angles: int, n_det: int, ks, iis) -> np.ndarray:
+    """(A f)[k, i] for the pairs (ks[j], iis[j])."""
+    f = np.asarray(f, dtype=np.float64)
+    H, W = f.shape
+    x, y = pixel_centres(H, W)
+    th = angles(n_angles)
+    t = detector(n_det)
+    out = np.empty(len(ks), dtype=np.float64)
+    for j, (k, i) in enumerate(zip(ks, iis)):
+        u = x * math.cos(th[k]) + y * math.sin(th[k])
+        out[j] = float(np.sum(f * np.maximum(0.0, 1.0 - np.abs(u - t[i]))))
+    return out
+
+
+def backproject_at(s: np.ndarray, H: int, W: int, rows, cols) -> np.ndarray:
+    """(A^T s)[a, b] for the pixels (rows[j], cols[j])."""
+    s = np.asarray(s, dtype=np.float64)
+    n_angles, n_det = s.shape
+    th = angles(n_angles)
+    t = detector(n_det)
+    out = np.empty(len(rows), dtype=np.float64)
+    for j, (a, b) in enumerate(zip(rows, cols)):
+        x = b + 0.5 - W / 2.0
+        y = a + 0.5 - H / 2.0
+        u = x * np.cos(th) + y * np.sin(th)                 # one per angle
+        w = np.maximum(0.0, 1.0 - np.abs(u[:, None] - t[None, :]))
+        out[j] = float(np.sum(w * s))
+    return out

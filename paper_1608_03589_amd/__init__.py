@@ -1,6 +1,6 @@
 """MI355X-native primal-dual image sweep (total-variation regularised
-denoising), after the regularised inverse problem of arXiv 1608.03589,
-Section 6.
+denoising, and reconstruction from a Radon-transform sinogram), after the
+regularised inverse problem of arXiv 1608.03589, Section 6.
 
 The compute path is ``libtvpd.so`` (HIP, gfx950) behind the C ABI in
 ``include/tvpd.h``; this package only marshals arguments and supplies device
@@ -8,6 +8,7 @@ memory and streams through PyTorch.
 """
 from ._lib import TVPDError, lib  # noqa: F401
 from .batch import BatchedSolver  # noqa: F401
+from .tomo import TomoSolver, default_steps, tomo_workspace_size  # noqa: F401
 from .unrolled import (  # noqa: F401
     UnrolledSolver, UnrolledTV, default_coeffs, set_fused_adjoint,
     unrolled_tv,
@@ -19,7 +20,8 @@ from .solver import (  # noqa: F401
 )
 
 __all__ = [
-    "BatchedSolver", "PlainSolver", "SolveResult", "TVPDError",
+    "BatchedSolver", "PlainSolver", "SolveResult", "TVPDError", "TomoSolver",
+    "default_steps", "tomo_workspace_size",
     "UnrolledSolver", "UnrolledTV", "default_coeffs", "set_fused_adjoint",
     "unrolled_tv",
     "alloc_workspace", "autotune",

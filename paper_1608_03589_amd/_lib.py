@@ -46,6 +46,20 @@ class Result(C.Structure):
                 ("gap", C.c_double)]
 
 
+class TomoGeom(C.Structure):
+    _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("n_angles", C.c_int32),
+                ("n_det", C.c_int32)]
+
+
+class TomoParams(C.Structure):
+    _fields_ = [("lam", C.c_float), ("tau", C.c_float), ("sigma_r", C.c_float),
+                ("sigma_p", C.c_float), ("theta", C.c_float), ("reg", C.c_int32)]
+
+
+REG_TV = 0
+REG_TIKHONOV = 1
+
+
 class TVPDError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} failed: {STATUS.get(status, status)} ({msg})")
@@ -98,6 +112,20 @@ SIGNATURES = {
                                       _P, _P, C.POINTER(Params), _P, _SZ,
                                       C.POINTER(_I32), C.POINTER(_I32),
                                       C.POINTER(C.c_float), _P]),
+    "tvpd_tomo_workspace_size": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_SZ)]),
+    "tvpd_radon_forward": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
+    "tvpd_radon_backward": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
+    "tvpd_tomo_init": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _SZ, _P]),
+    "tvpd_tomo_step": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,
+                                 _P, _SZ, _P]),
+    "tvpd_tomo_read": (C.c_int, [C.POINTER(TomoGeom), _P, _SZ, _P, _P, _P,
+                                 C.POINTER(_I32), _P]),
+    "tvpd_tomo_energy": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _I32, _P, _SZ,
+                                   C.POINTER(C.c_double), _P]),
+    "tvpd_tomo_opnorm": (C.c_int, [C.POINTER(TomoGeom), _I32, _P, _SZ,
+                                   C.POINTER(C.c_double), _P]),
+    "tvpd_tomo_solve": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,
+                                  _P, _P, _SZ, _P]),
 }
 
 _lib = None

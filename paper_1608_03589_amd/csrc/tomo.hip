@@ -1,0 +1,472 @@
+// HIP kernels of the tomographic data term (see tomo.h for the operators'
+// layout in memory and the iteration they serve).
+#include <cmath>
+
+#include "tile2d.h"
+#include "tomo.h"
+
+namespace tvpd {
+namespace {
+
+using dev::block_sum2;
+using dev::dual_arg;
+using dev::extrap;
+using dev::project2;
+using dev::prox_factor;
+
+// Angle table in float64: theta_k = k pi / n_angles.
+__global__ void tomo_trig_kernel(double* trig, int na) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= na) return;
+  const double a = (double)k / (double)na;
+  trig[2 * k] = cospi(a);
+  trig[2 * k + 1] = sinpi(a);
+}
+
+// Ring slots of the iteration: with kptr set, slot (k & 1) holds the
+// current iterate; without it both pointers of a pair are the same buffer.
+__device__ __forceinline__ int ring_parity(const int32_t* kptr) {
+  return kptr ? (*kptr & 1) : 0;
+}
+
+struct PrepArgs {
+  const float* x0;       // slot 0 / slot 1 of the image ring
+  const float* x1;
+  const int32_t* kptr;   // current iterate in slot (k & 1); null: x0 == x1
+  float theta;
+  float* fb;
+  float* fbt;
+  float* px0;            // dual ring (null: no dual update)
+  float* py0;
+  float* px1;
+  float* py1;
+  float sigma, lam;
+  int ny, nx, pitch_b, pitch_t;
+};
+
+// fbar = x + theta (x - x_prev) of a 32 x 32 tile: written to the padded
+// copy, transposed through LDS into the padded transposed copy, and (TV)
+// the dual update p^{k+1} = P_lam(p^k + sigma grad fbar) of the tile's
+// pixels.  Blocks at the image's edges also write the zero pad columns.
+__global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
+  __shared__ float tile[kTomoPrepTile][kTomoPrepTile + 1];
+  const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+  const int b0 = blockIdx.x * kTomoPrepTile, a0 = blockIdx.y * kTomoPrepTile;
+  const int ny = a.ny, nx = a.nx;
+  const int par = ring_parity(a.kptr);
+  const float* x = par ? a.x1 : a.x0;
+  const float* xp = par ? a.x0 : a.x1;
+  const float th = a.theta;
+  auto fbar = [&](int r, int c) {
+    const int64_t o = (int64_t)r * nx + c;
+    return extrap(x[o], xp[o], th);
+  };
+  const bool dual = a.px0 != nullptr;
+  const float* pxi = par ? a.px1 : a.px0;
+  const float* pyi = par ? a.py1 : a.py0;
+  float* pxo = par ? a.px0 : a.px1;
+  float* pyo = par ? a.py0 : a.py1;
+  const float lam2 = a.lam * a.lam;
+#pragma unroll
+  for (int rr = 0; rr < kTomoPrepTile; rr += 8) {
+    const int r = a0 + ty + rr, c = b0 + tx;
+    if (r < ny && c < nx) {
+      const float v = fbar(r, c);
+      a.fb[(int64_t)r * a.pitch_b + kTomoPad + c] = v;
+      tile[ty + rr][tx] = v;
+      if (dual) {
+        const int64_t o = (int64_t)r * nx + c;
+        const float gx = c + 1 < nx ? fbar(r, c + 1) - v : 0.0f;
+        const float gy = r + 1 < ny ? fbar(r + 1, c) - v : 0.0f;
+        float qx, qy;
+        project2(dual_arg(pxi[o], a.sigma, gx), dual_arg(pyi[o], a.sigma, gy),
+                 a.lam, lam2, qx, qy);
+        pxo[o] = qx;
+        pyo[o] = qy;
+      }
+    }
+    if (tx < kTomoPad && r < ny) {
+      if (blockIdx.x == 0) a.fb[(int64_t)r * a.pitch_b + tx] = 0.0f;
+      if (blockIdx.x == gridDim.x - 1)
+        a.fb[(int64_t)r * a.pitch_b + kTomoPad + nx + tx] = 0.0f;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < kTomoPrepTile; rr += 8) {
+    const int c = b0 + ty + rr, r = a0 + tx;   // row c of the transpose
+    if (c < nx && r < ny) a.fbt[(int64_t)c * a.pitch_t + kTomoPad + r] = tile[tx][ty + rr];
+    if (tx < kTomoPad && c < nx) {
+      if (blockIdx.y == 0) a.fbt[(int64_t)c * a.pitch_t + tx] = 0.0f;
+      if (blockIdx.y == gridDim.y - 1)
+        a.fbt[(int64_t)c * a.pitch_t + kTomoPad + ny + tx] = 0.0f;
+    }
+  }
+}
+
+// max(0, 1 - aa |d|): a multiply-add whose median with 0 and 1 becomes the
+// instruction's clamp modifier.
+__device__ __forceinline__ float hat_weight(float d, float aa) {
+  return __builtin_amdgcn_fmed3f(fmaf(-aa, fabsf(d), 1.0f), 0.0f, 1.0f);
+}
+
+// Projection: one lane per bin of one angle (see tomo.h).
+template <int MODE>
+__global__ __launch_bounds__(kProjBlock) void tomo_project_kernel(ProjArgs a) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  const int k = blockIdx.y;
+  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+  const double c = a.trig[2 * k], s = a.trig[2 * k + 1];
+  const bool xmaj = fabs(c) >= fabs(s);
+  const double al = xmaj ? c : s, be = xmaj ? s : c;
+  const int nq = xmaj ? a.ny : a.nx, nj = xmaj ? a.nx : a.ny;
+  const float* src = xmaj ? a.fb : a.fbt;
+  const int64_t pitch = xmaj ? a.pitch_b : a.pitch_t;
+  const double rr = 1.0 / fabs(al);          // half-width of the hat in columns
+  // e(q) = j*(q) - rr with j*(q) = (t_i - c_q be) / al + (nj - 1) / 2 and
+  // c_q = q + 1/2 - nq/2 the row's coordinate; 32.32 fixed point
+  const double ti = (double)i + 0.5 - 0.5 * (double)a.nd;
+  const double c0 = 0.5 - 0.5 * (double)nq;
+  const double e0 = (ti - c0 * be) / al + 0.5 * (double)(nj - 1) - rr;
+  constexpr double kFx = 4294967296.0;
+  int64_t E = llrint(e0 * kFx);
+  const int64_t dE = llrint(-be / al * kFx);
+  const float aa = (float)fabs(al);
+  // distance (in columns) of candidate column floor(e) + 1 + m from j* is
+  // (1 + m - rr) - frac(e)
+  const float k1 = (float)(1.0 - rr), k2 = (float)(2.0 - rr), k3 = (float)(3.0 - rr);
+  constexpr float kInvFx = 2.3283064365386963e-10f;   // 2^-32
+  float acc = 0.0f;
+#pragma unroll 8
+  for (int q = 0; q < nq; ++q) {
+    const uint64_t U = (uint64_t)E;
+    // first candidate column floor(e) + 1, as an offset into the padded row
+    // (clamped into the zero pad when the hat misses the image)
+    const int o = min(max((int)(uint32_t)(U >> 32) + kTomoPad + 1, 1), nj + kTomoPad + 1);
+    const float ph = (float)(uint32_t)U;      // frac(e) * 2^32
+    const float* p = src + (int64_t)q * pitch + (uint32_t)o;
+    acc = fmaf(hat_weight(fmaf(ph, -kInvFx, k1), aa), p[0], acc);
+    acc = fmaf(hat_weight(fmaf(ph, -kInvFx, k2), aa), p[1], acc);
+    acc = fmaf(hat_weight(fmaf(ph, -kInvFx, k3), aa), p[2], acc);
+    E += dE;
+  }
+  double v = 0.0, unused = 0.0;
+  if (i < a.nd) {
+    const int64_t o = (int64_t)k * a.nd + i;
+    if constexpr (MODE == kProjWrite) {
+      a.out[o] = acc;
+    } else if constexpr (MODE == kProjDual) {
+      a.out[o] = fmaf(a.sigma, acc - a.g[o], a.out[o]) * prox_factor(a.sigma);
+    } else {
+      const double res = (double)acc - (double)a.g[o];
+      v = res * res;
+    }
+  }
+  if constexpr (MODE == kProjResid) {
+    block_sum2(v, unused, red);
+    if (threadIdx.x == 0) {
+      const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+      a.part[2 * slot] = v;
+      a.part[2 * slot + 1] = 0.0;
+    }
+  }
+}
+
+struct BpKernelArgs {
+  BpArgs b;
+  const int32_t* kptr;   // ring mode (null: pointers used as given)
+  const float* f1;       // slot 1 of the image ring (f in b is slot 0)
+  float* out1;           // slot 1 of the output ring
+  const float* px1;      // slot 1 of the dual ring
+  const float* py1;
+};
+
+// Backprojection of a 32 x 64 tile (see tomo.h), with the primal update in
+// the epilogue for the iteration's modes.
+template <int MODE>
+__global__ __launch_bounds__(kMaxBlock) void tomo_backproject_kernel(BpKernelArgs ka) {
+  __shared__ float2 win[kBpChunk][kBpWin];
+  __shared__ float4 tab[kBpChunk];
+  const BpArgs& a = ka.b;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int b0 = blockIdx.x * kBpCols, a0 = blockIdx.y * kBpRows;
+  // centre of the tile's corner pixel (a0, b0)
+  const double xr = b0 + 0.5 - 0.5 * (double)a.nx;
+  const double yr = a0 + 0.5 - 0.5 * (double)a.ny;
+  const double t0 = 0.5 - 0.5 * (double)a.nd;
+  const float dx = (float)lane;
+  const float dy = (float)(wave * kBpPerLane);
+  float acc[kBpPerLane];
+#pragma unroll
+  for (int m = 0; m < kBpPerLane; ++m) acc[m] = 0.0f;
+  for (int kc = 0; kc < a.na; kc += kBpChunk) {
+    const int nk = min(kBpChunk, a.na - kc);
+    if (threadIdx.x < nk) {
+      const int k = kc + threadIdx.x;
+      const double c = a.trig[2 * k], s = a.trig[2 * k + 1];
+      const double ur = xr * c + yr * s;
+      const double umin = ur + fmin(0.0, (kBpCols - 1) * c) + fmin(0.0, (kBpRows - 1) * s);
+      // window of bins [ws, ws + kBpWin); the tile's positions u - t0 - ws lie
+      // in [2, 74) (the tile spans at most 71 bins)
+      const double ws = floor(umin - t0) - 2.0;
+      tab[threadIdx.x] = make_float4((float)c, (float)s, (float)(ur - t0 - ws),
+                                     __int_as_float((int)ws));
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nk * kBpWin; e += kMaxBlock) {
+      const int kk = e / kBpWin, j = e - kk * kBpWin;
+      const int bin = __float_as_int(tab[kk].w) + j;
+      const float* row = a.sino + (int64_t)(kc + kk) * a.nd;
+      const float s0 = (bin >= 0 && bin < a.nd) ? row[bin] : 0.0f;
+      const float s1 = (bin + 1 >= 0 && bin + 1 < a.nd) ? row[bin + 1] : 0.0f;
+      win[kk][j] = make_float2(s0, s1 - s0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) {
+      const float4 T = tab[kk];
+      const float vx = fmaf(dx, T.x, fmaf(dy, T.y, T.z));
+#pragma unroll
+      for (int m = 0; m < kBpPerLane; ++m) {
+        const float v = fmaf((float)m, T.y, vx);   // > 0: truncation is floor
+        const int idx = (int)v;
+        const float w = __builtin_amdgcn_fractf(v);
+        const float2 S = win[kk][idx];
+        acc[m] += fmaf(w, S.y, S.x);
+      }
+    }
+    __syncthreads();
+  }
+  const int b = b0 + lane;
+  if (b >= a.nx) return;
+  const int par = ring_parity(ka.kptr);
+  const float* f = par ? ka.f1 : a.f;
+  float* out = par ? a.out : ka.out1;     // slot of k + 1
+  if (MODE == kBpWrite) out = a.out;
+  const float* px = par ? a.px : ka.px1;  // p^{k+1} sits in slot of k + 1
+  const float* py = par ? a.py : ka.py1;
+  const float itl = MODE == kBpTikhonov ? 1.0f / (1.0f + a.tau * a.lam) : 1.0f;
+#pragma unroll
+  for (int m = 0; m < kBpPerLane; ++m) {
+    const int r = a0 + wave * kBpPerLane + m;
+    if (r >= a.ny) break;
+    const int64_t o = (int64_t)r * a.nx + b;
+    if constexpr (MODE == kBpWrite) {
+      out[o] = acc[m];
+    } else if constexpr (MODE == kBpTikhonov) {
+      out[o] = fmaf(-a.tau, acc[m], f[o]) * itl;
+    } else {
+      float d = px[o] - (b > 0 ? px[o - 1] : 0.0f);
+      d = d + (py[o] - (r > 0 ? py[o - a.nx] : 0.0f));
+      out[o] = fmaf(a.tau, d, fmaf(-a.tau, acc[m], f[o]));
+    }
+  }
+}
+
+__global__ void tomo_fill_kernel(float* p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void tomo_advance_kernel(TomoState* st) { st->k += 1; }
+__global__ void tomo_set_k_kernel(TomoState* st, int k) { st->k = k; }
+
+constexpr int kRedBlocks = 1024;
+
+// Regulariser partials: reg 0 -> sum |grad x| (float64 differences), 1 ->
+// sum x^2.
+__global__ __launch_bounds__(kMaxBlock) void tomo_regsum_kernel(const float* x, int ny,
+                                                                int nx, int reg,
+                                                                double* part) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  const int64_t n = (int64_t)ny * nx;
+  double acc = 0.0, unused = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    if (reg == 0) {
+      const int r = (int)(i / nx), c = (int)(i - (int64_t)r * nx);
+      const double gx = c + 1 < nx ? (double)x[i + 1] - v : 0.0;
+      const double gy = r + 1 < ny ? (double)x[i + nx] - v : 0.0;
+      acc += sqrt(gx * gx + gy * gy);
+    } else {
+      acc += v * v;
+    }
+  }
+  block_sum2(acc, unused, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = acc;
+    part[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kMaxBlock) void tomo_dot_kernel(const float* v,
+                                                             const float* w,
+                                                             int64_t n, double* part) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  double vw = 0.0, ww = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = v[i], b = w[i];
+    vw += a * b;
+    ww += b * b;
+  }
+  block_sum2(vw, ww, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = vw;
+    part[2 * blockIdx.x + 1] = ww;
+  }
+}
+
+// One block: fixed-order sums of a range of partials.
+__global__ __launch_bounds__(kMaxBlock) void tomo_reduce_kernel(const double* part,
+                                                                int64_t first, int64_t n,
+                                                                double* red0, double* red1) {
+  __shared__ double red[2][kMaxBlock / kWave];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    a += part[2 * (first + i)];
+    b += part[2 * (first + i) + 1];
+  }
+  block_sum2(a, b, red);
+  if (threadIdx.x == 0) {
+    *red0 = a;
+    if (red1) *red1 = b;
+  }
+}
+
+__global__ void tomo_scale_kernel(float* v, const float* w, int64_t n,
+                                  const double* nrm2) {
+  const double q = *nrm2;
+  const float sc = q > 0.0 ? (float)(1.0 / sqrt(q)) : 0.0f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] * sc;
+}
+
+int grid_1d(int64_t n) {
+  const int64_t b = (n + kMaxBlock - 1) / kMaxBlock;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+#define TOMO_LAUNCHED() (hipGetLastError() == hipSuccess ? TVPD_OK : TVPD_ERR_HIP)
+
+}  // namespace
+
+int launch_tomo_trig(double* trig, int na, hipStream_t s) {
+  tomo_trig_kernel<<<(na + 255) / 256, 256, 0, s>>>(trig, na);
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_prep(const TomoLayout& L, const float* x0, const float* x1,
+                     const int32_t* kptr, float theta, float* fb, float* fbt,
+                     float* px0, float* py0, float* px1, float* py1, float sigma,
+                     float lam, hipStream_t s) {
+  PrepArgs a;
+  a.x0 = x0;
+  a.x1 = x1;
+  a.kptr = kptr;
+  a.theta = theta;
+  a.fb = fb;
+  a.fbt = fbt;
+  a.px0 = px0;
+  a.py0 = py0;
+  a.px1 = px1;
+  a.py1 = py1;
+  a.sigma = sigma;
+  a.lam = lam;
+  a.ny = L.ny;
+  a.nx = L.nx;
+  a.pitch_b = L.pitch_b;
+  a.pitch_t = L.pitch_t;
+  const dim3 grid((L.nx + kTomoPrepTile - 1) / kTomoPrepTile,
+                  (L.ny + kTomoPrepTile - 1) / kTomoPrepTile);
+  tomo_prep_kernel<<<grid, dim3(kTomoPrepTile, 8), 0, s>>>(a);
+  return TOMO_LAUNCHED();
+}
+
+int tomo_project_blocks(int na, int nd) {
+  return ((nd + kProjBlock - 1) / kProjBlock) * na;
+}
+
+int launch_tomo_project(const ProjArgs& a, int mode, hipStream_t s) {
+  const dim3 grid((a.nd + kProjBlock - 1) / kProjBlock, a.na);
+  switch (mode) {
+    case kProjWrite: tomo_project_kernel<kProjWrite><<<grid, kProjBlock, 0, s>>>(a); break;
+    case kProjDual: tomo_project_kernel<kProjDual><<<grid, kProjBlock, 0, s>>>(a); break;
+    case kProjResid: tomo_project_kernel<kProjResid><<<grid, kProjBlock, 0, s>>>(a); break;
+    default: return TVPD_ERR_INVALID_ARG;
+  }
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_backproject(const BpArgs& a, int mode, const int32_t* kptr,
+                            const float* f1, float* out1, const float* px1,
+                            const float* py1, hipStream_t s) {
+  BpKernelArgs ka;
+  ka.b = a;
+  ka.kptr = kptr;
+  ka.f1 = f1;
+  ka.out1 = out1;
+  ka.px1 = px1;
+  ka.py1 = py1;
+  const dim3 grid((a.nx + kBpCols - 1) / kBpCols, (a.ny + kBpRows - 1) / kBpRows);
+  switch (mode) {
+    case kBpWrite: tomo_backproject_kernel<kBpWrite><<<grid, kMaxBlock, 0, s>>>(ka); break;
+    case kBpTikhonov: tomo_backproject_kernel<kBpTikhonov><<<grid, kMaxBlock, 0, s>>>(ka); break;
+    case kBpTV: tomo_backproject_kernel<kBpTV><<<grid, kMaxBlock, 0, s>>>(ka); break;
+    default: return TVPD_ERR_INVALID_ARG;
+  }
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_fill(float* p, int64_t n, float v, hipStream_t s) {
+  tomo_fill_kernel<<<grid_1d(n), kMaxBlock, 0, s>>>(p, n, v);
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_advance(TomoState* st, hipStream_t s) {
+  tomo_advance_kernel<<<1, 1, 0, s>>>(st);
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_set_k(TomoState* st, int k, hipStream_t s) {
+  tomo_set_k_kernel<<<1, 1, 0, s>>>(st, k);
+  return TOMO_LAUNCHED();
+}
+
+int tomo_regsum_blocks(int ny, int nx) {
+  const int64_t b = ((int64_t)ny * nx + kMaxBlock - 1) / kMaxBlock;
+  return (int)(b < 1 ? 1 : (b > kRedBlocks ? kRedBlocks : b));
+}
+
+int launch_tomo_regsum(const float* x, int ny, int nx, int reg, double* part,
+                       hipStream_t s) {
+  tomo_regsum_kernel<<<tomo_regsum_blocks(ny, nx), kMaxBlock, 0, s>>>(x, ny, nx, reg, part);
+  return TOMO_LAUNCHED();
+}
+
+int tomo_dot_blocks(int64_t n) {
+  const int64_t b = (n + kMaxBlock - 1) / kMaxBlock;
+  return (int)(b < 1 ? 1 : (b > kRedBlocks ? kRedBlocks : b));
+}
+
+int launch_tomo_dot(const float* v, const float* w, int64_t n, double* part,
+                    hipStream_t s) {
+  tomo_dot_kernel<<<tomo_dot_blocks(n), kMaxBlock, 0, s>>>(v, w, n, part);
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_reduce(const double* part, int64_t first, int64_t n, double* red0,
+                       double* red1, hipStream_t s) {
+  tomo_reduce_kernel<<<1, kMaxBlock, 0, s>>>(part, first, n, red0, red1);
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_scale(float* v, const float* w, int64_t n, const double* nrm2,
+                      hipStream_t s) {
+  tomo_scale_kernel<<<grid_1d(n), kMaxBlock, 0, s>>>(v, w, n, nrm2);
+  return TOMO_LAUNCHED();
+}
+
+}  // namespace tvpd

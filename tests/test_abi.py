@@ -124,3 +124,43 @@ def test_loud_failure_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_tomo_validation_without_gpu(L):
+    from paper_1608_03589_amd._lib import TomoGeom, TomoParams
+    assert C.sizeof(TomoGeom) == 16 and C.sizeof(TomoParams) == 24
+    n = C.c_size_t()
+    good = TomoGeom(64, 48, 30, 90)
+    assert L.tvpd_tomo_workspace_size(C.byref(good), C.byref(n)) == 0
+    assert n.value > 4 * 64 * 48 * 8
+    for bad in (TomoGeom(0, 4, 4, 4), TomoGeom(4, 4, 0, 4), TomoGeom(4, 4, 4, 0),
+                TomoGeom(40000, 4, 4, 4), TomoGeom(4, 4, 70000, 4)):
+        assert L.tvpd_tomo_workspace_size(C.byref(bad), C.byref(n)) == -2
+    assert L.tvpd_tomo_workspace_size(None, C.byref(n)) == -2
+    dummy = C.c_void_p(256)
+    ok = TomoParams(0.1, 0.01, 0.01, 1.0, 1.0, 0)
+    # parameters are checked before the workspace (and before any HIP call)
+    for prm, code in ((TomoParams(0.1, 0.0, 0.01, 1.0, 1.0, 0), -7),
+                      (TomoParams(0.1, 0.01, -1.0, 1.0, 1.0, 0), -7),
+                      (TomoParams(0.1, 0.01, 0.01, 0.0, 1.0, 0), -7),
+                      (TomoParams(-0.1, 0.01, 0.01, 1.0, 1.0, 0), -1),
+                      (TomoParams(0.1, 0.01, 0.01, 1.0, 1.5, 0), -1),
+                      (TomoParams(0.1, 0.01, 0.01, 1.0, 1.0, 7), -1)):
+        assert L.tvpd_tomo_step(C.byref(good), dummy, C.byref(prm), 1, None, 0,
+                                None) == code
+    # Tikhonov ignores sigma_p
+    tik = TomoParams(0.1, 0.01, 0.01, 0.0, 1.0, 1)
+    assert L.tvpd_tomo_step(C.byref(good), dummy, C.byref(tik), 1, None, 0, None) == -1
+    assert L.tvpd_tomo_step(C.byref(good), dummy, C.byref(ok), -1, None, 0, None) == -1
+    assert L.tvpd_tomo_step(C.byref(good), None, C.byref(ok), 1, None, 0, None) == -1
+    assert L.tvpd_tomo_step(C.byref(good), dummy, C.byref(ok), 1, C.c_void_p(256 + 8),
+                            1 << 40, None) == -3
+    assert L.tvpd_tomo_step(C.byref(good), dummy, C.byref(ok), 1, dummy, 16,
+                            None) == -4
+    assert L.tvpd_radon_forward(C.byref(good), None, dummy, dummy, 1 << 40, None) == -1
+    assert L.tvpd_radon_backward(C.byref(good), dummy, None, dummy, 1 << 40, None) == -1
+    out = C.c_double()
+    assert L.tvpd_tomo_opnorm(C.byref(good), 0, dummy, 1 << 40, C.byref(out), None) == -1
+    res = (C.c_double * 3)()
+    assert L.tvpd_tomo_energy(C.byref(good), dummy, 0.1, 5, dummy, 1 << 40, res,
+                              None) == -1

@@ -190,3 +190,17 @@ def test_energy_terms():
     d2, r2, _ = tomo.energy(f, g, lam, "tikhonov")
     assert d2 == pytest.approx(d, rel=1e-15)
     assert r2 == pytest.approx(0.5 * lam * np.sum(f * f), rel=1e-13)
+
+
+def test_single_entries_match_the_full_operators():
+    H, W, na, nd = 23, 31, 17, 29          # detector narrower than the image
+    f = rng(13).normal(size=(H, W))
+    s = rng(14).normal(size=(na, nd))
+    A = tomo.project(f, na, nd)
+    B = tomo.backproject(s, H, W)
+    ks, iis = np.meshgrid(np.arange(na), np.arange(nd), indexing="ij")
+    np.testing.assert_allclose(tomo.project_at(f, na, nd, ks.ravel(), iis.ravel()),
+                               A.ravel(), rtol=1e-12, atol=1e-12)
+    rr, cc = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    np.testing.assert_allclose(tomo.backproject_at(s, H, W, rr.ravel(), cc.ravel()),
+                               B.ravel(), rtol=1e-12, atol=1e-12)
