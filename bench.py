@@ -289,6 +289,81 @@ def bench_plain_3d(dev):
     }
 
 
+# Algorithmic fp32 operations per (pixel, angle) pair: the backprojection
+# interpolates once (fraction, one multiply-add) and accumulates, with the
+# position advanced by one add; the projection (as the transpose) forms the
+# position, the fraction and two hat-weighted multiply-adds.
+TOMO_FLOPS_BP = 5
+TOMO_FLOPS_PROJ = 6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def bench_tomo(dev):
+    """Reconstruction of a 2048^2 slice from 1000 projections of 2048 rays
+    (TV regulariser): 20 iterations of the primal-dual method, and the two
+    operators on their own."""
+    import torch
+    import paper_1608_03589_amd as tv
+    from scenes import WORKLOADS, tomo_scene
+    w = WORKLOADS["tomo_2048x1000"]
+    H, W, na, nd = w["H"], w["W"], w["n_angles"], w["n_det"]
+    img, _, g = tomo_scene(H, W, na, nd, w["n_ellipses"], w["noise"], w["seed"])
+    gt = torch.from_numpy(g.astype(np.float32)).to(dev)
+    ft = torch.from_numpy(img.astype(np.float32)).to(dev)
+    solver = tv.TomoSolver(H, W, na, nd, dev)
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    L2 = solver.opnorm_sq(20)
+    opnorm_s = time.perf_counter() - t0
+    tau, sr, sp = tv.default_steps(L2, "tv")
+    lam = w["lam"]
+    iters = w["iters"]
+    sino = torch.empty_like(gt)
+    back = torch.empty_like(ft)
+    solver.radon(ft, sino)
+    solver.backproject(gt, back)
+    ms_radon, _ = timed(lambda: solver.radon(ft, sino), stream, 5)
+    ms_bp, _ = timed(lambda: solver.backproject(gt, back), stream, 5)
+
+    def run():
+        solver.init()
+        solver.step(gt, iters, lam, tau, sr, sp, reg="tv")
+    run()
+    ms, _ = timed(run, stream, 2)
+    pairs = H * W * na
+    e = solver.energy(gt, lam, "tv")
+    log(f"tomo: {ms / iters:.3f} ms per iteration, A {ms_radon:.3f} ms, "
+        f"A^T {ms_bp:.3f} ms")
+    tf_bp = pairs * TOMO_FLOPS_BP / (ms_bp * 1e-3) / 1e12
+    tf_proj = pairs * TOMO_FLOPS_PROJ / (ms_radon * 1e-3) / 1e12
+    return {
+        "workload": "tomo_2048x1000",
+        "image": [H, W], "n_angles": na, "n_det": nd, "reg": "tv", "lam": lam,
+        "iterations": iters,
+        "ms_per_iteration": ms / iters,
+        "opnorm_sq": L2, "opnorm_20_steps_s": opnorm_s,
+        "steps_tau_sigma_r_sigma_p": [tau, sr, sp],
+        "energy_after": list(e),
+        "radon_ms": ms_radon,
+        "backproject_ms": ms_bp,
+        "gpairs_per_s_radon": pairs / (ms_radon * 1e-3) / 1e9,
+        "gpairs_per_s_backproject": pairs / (ms_bp * 1e-3) / 1e9,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "tomo_project_kernel (A, with the padded-copy kernel in the timing)",
+            "achieved": tf_proj,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": tf_proj / FP32_VECTOR_PEAK_TFLOPS,
+            "flops_per_pixel_angle": TOMO_FLOPS_PROJ,
+            "backprojection_achieved": tf_bp,
+            "backprojection_frac": tf_bp / FP32_VECTOR_PEAK_TFLOPS,
+            "backprojection_flops_per_pixel_angle": TOMO_FLOPS_BP,
+            "traffic": None,
+        },
+    }
+
+
 def copy_calibration(dev):
     """Five device copies of 256 MiB: a transfer of known size against which
     the HBM byte counters are scaled."""
@@ -307,6 +382,7 @@ EXTRA_WORKLOADS = {
     "unrolled_32x512": lambda dev, ref: bench_unrolled_2d(dev, ref),
     "unrolled_256cube": lambda dev: bench_unrolled_3d(dev),
     "plain_256cube": lambda dev: bench_plain_3d(dev),
+    "tomo_2048x1000": lambda dev: bench_tomo(dev),
 }
 
 
@@ -424,6 +500,7 @@ def main():
         extra["unrolled_2d"] = bench_unrolled_2d(dev, mpix_its)
         extra["unrolled_3d"] = bench_unrolled_3d(dev)
         extra["plain_3d"] = bench_plain_3d(dev)
+        extra["tomo"] = bench_tomo(dev)
 
     cpu = None
     if not args.no_cpu_baseline:

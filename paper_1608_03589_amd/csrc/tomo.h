@@ -16,8 +16,10 @@
 //    constant -sin/cos per row and is carried in 32.32 fixed point (exact
 //    steps; the start is rounded once from float64), so the column index and
 //    the weights do not lose bits to the size of j*.  Rows are read from
-//    padded copies (kTomoPad zero columns on each side), so a hat partly or
-//    wholly outside the image reads zeros instead of branching.
+//    padded copies (kTomoPad zero columns on each side): a wave walks only
+//    the rows its bins' hats meet, and in those rows every candidate column
+//    of its 64 bins lies inside the padded row, so hats partly outside the
+//    image read zeros instead of branching.
 //
 //  * backprojection (one lane per pixel, eight pixels per lane down a
 //    column): a block owns a 32 x 64 pixel tile; for each angle the tile's
@@ -32,7 +34,7 @@
 
 namespace tvpd {
 
-constexpr int kTomoPad = 4;          // zero columns on each side of a padded row
+constexpr int kTomoPad = 104;        // zero columns on each side of a padded row
 constexpr int kTomoMaxSide = 32768;  // ny, nx, n_det limit
 constexpr int kTomoMaxAngles = 65535;
 constexpr int kProjBlock = 256;      // bins per projection block (4 waves)

@@ -23,6 +23,9 @@ __global__ void tomo_trig_kernel(double* trig, int na) {
   trig[2 * k + 1] = sinpi(a);
 }
 
+// Word 3 of a raw buffer descriptor for 32-bit loads on CDNA.
+constexpr int kBufferWord3 = 0x00020000;
+
 // Ring slots of the iteration: with kptr set, slot (k & 1) holds the
 // current iterate; without it both pointers of a pair are the same buffer.
 __device__ __forceinline__ int ring_parity(const int32_t* kptr) {
@@ -85,10 +88,12 @@ __global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
         pyo[o] = qy;
       }
     }
-    if (tx < kTomoPad && r < ny) {
-      if (blockIdx.x == 0) a.fb[(int64_t)r * a.pitch_b + tx] = 0.0f;
-      if (blockIdx.x == gridDim.x - 1)
-        a.fb[(int64_t)r * a.pitch_b + kTomoPad + nx + tx] = 0.0f;
+    if (r < ny) {
+      for (int j = tx; j < kTomoPad; j += kTomoPrepTile) {
+        if (blockIdx.x == 0) a.fb[(int64_t)r * a.pitch_b + j] = 0.0f;
+        if (blockIdx.x == gridDim.x - 1)
+          a.fb[(int64_t)r * a.pitch_b + kTomoPad + nx + j] = 0.0f;
+      }
     }
   }
   __syncthreads();
@@ -96,21 +101,33 @@ __global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
   for (int rr = 0; rr < kTomoPrepTile; rr += 8) {
     const int c = b0 + ty + rr, r = a0 + tx;   // row c of the transpose
     if (c < nx && r < ny) a.fbt[(int64_t)c * a.pitch_t + kTomoPad + r] = tile[tx][ty + rr];
-    if (tx < kTomoPad && c < nx) {
-      if (blockIdx.y == 0) a.fbt[(int64_t)c * a.pitch_t + tx] = 0.0f;
-      if (blockIdx.y == gridDim.y - 1)
-        a.fbt[(int64_t)c * a.pitch_t + kTomoPad + ny + tx] = 0.0f;
+    if (c < nx) {
+      for (int j = tx; j < kTomoPad; j += kTomoPrepTile) {
+        if (blockIdx.y == 0) a.fbt[(int64_t)c * a.pitch_t + j] = 0.0f;
+        if (blockIdx.y == gridDim.y - 1)
+          a.fbt[(int64_t)c * a.pitch_t + kTomoPad + ny + j] = 0.0f;
+      }
     }
   }
 }
 
-// max(0, 1 - aa |d|): a multiply-add whose median with 0 and 1 becomes the
-// instruction's clamp modifier.
-__device__ __forceinline__ float hat_weight(float d, float aa) {
-  return __builtin_amdgcn_fmed3f(fmaf(-aa, fabsf(d), 1.0f), 0.0f, 1.0f);
-}
-
 // Projection: one lane per bin of one angle (see tomo.h).
+//
+// Weights.  With e = j* - rr = jl + phi (jl integer, 0 <= phi < 1) and
+// aa = |cos| (rows) or |sin| (columns), aa rr = 1, the hat weights
+// 1 - aa |column - j*| of the three candidate columns jl + 1, jl + 2, jl + 3
+// reduce to
+//     w1 = aa (1 - phi),
+//     w2 = 1 - |2 aa - 1 - aa phi|        (in [0, 1] for aa >= 1/sqrt(2)),
+//     w3 = max(0, 2 - 3 aa + aa phi).
+//
+// Rows.  A wave's 64 bins lie within 63 / aa <= 89.1 columns of each other in
+// every row; the wave walks only the rows in which at least one of its
+// bins' hats meets the image (plus one row on each side), and there every
+// candidate column lies inside the padded row (kTomoPad >= 94 zeros; 10
+// spare), so no per-row clamp is needed.  Each row costs one 12-byte load
+// per lane; staging the wave's row segment through LDS (two coalesced
+// dword loads, a store and the three reads) measured slower.
 template <int MODE>
 __global__ __launch_bounds__(kProjBlock) void tomo_project_kernel(ProjArgs a) {
   __shared__ double red[2][kMaxBlock / kWave];
@@ -123,32 +140,68 @@ __global__ __launch_bounds__(kProjBlock) void tomo_project_kernel(ProjArgs a) {
   const float* src = xmaj ? a.fb : a.fbt;
   const int64_t pitch = xmaj ? a.pitch_b : a.pitch_t;
   const double rr = 1.0 / fabs(al);          // half-width of the hat in columns
-  // e(q) = j*(q) - rr with j*(q) = (t_i - c_q be) / al + (nj - 1) / 2 and
-  // c_q = q + 1/2 - nq/2 the row's coordinate; 32.32 fixed point
-  const double ti = (double)i + 0.5 - 0.5 * (double)a.nd;
-  const double c0 = 0.5 - 0.5 * (double)nq;
-  const double e0 = (ti - c0 * be) / al + 0.5 * (double)(nj - 1) - rr;
+  // j*(q) = A_i + m c_q, c_q = q + 1/2 - nq/2 the row's coordinate
+  const double m = -be / al;
+  const double half = 0.5 * (double)(nj - 1);
+  auto A_of = [&](int bin) {
+    return ((double)bin + 0.5 - 0.5 * (double)a.nd) / al + half;
+  };
+  // rows met by the wave (uniform over the wave)
+  const int i0w = __builtin_amdgcn_readfirstlane(i);
+  const double Af = A_of(i0w), Al = A_of(i0w + kWave - 1);
+  const double Alo = fmin(Af, Al), Ahi = fmax(Af, Al);
+  const double lo_j = -rr, hi_j = (double)(nj - 1) + rr;   // j* range that meets
+  const double cq0 = 0.5 - 0.5 * (double)nq;
+  int q_lo = 0, q_hi = nq - 1;
+  if (m == 0.0) {
+    if (!(Ahi > lo_j && Alo < hi_j)) q_hi = -1;
+  } else {
+    // Ahi + m c > lo_j  and  Alo + m c < hi_j
+    double c1 = (lo_j - Ahi) / m, c2 = (hi_j - Alo) / m;
+    const double cmin = fmin(c1, c2), cmax = fmax(c1, c2);
+    const double qa = floor(cmin - cq0) - 1.0, qb = ceil(cmax - cq0) + 1.0;
+    q_lo = (int)fmax(qa, 0.0);
+    q_hi = (int)fmin(qb, (double)(nq - 1));
+  }
+  // e(q) = j*(q) - rr in 32.32 fixed point, from row q_lo
   constexpr double kFx = 4294967296.0;
-  int64_t E = llrint(e0 * kFx);
-  const int64_t dE = llrint(-be / al * kFx);
+  const int qlo = __builtin_amdgcn_readfirstlane(q_lo);
+  const int qhi = __builtin_amdgcn_readfirstlane(q_hi);
+  const double e0 = A_of(i) + m * cq0 - rr;
+  const int64_t dE = llrint(m * kFx);
+  const int64_t E0 = llrint(e0 * kFx) + (int64_t)qlo * dE;
+  // the 32.32 value as an integer part and a fraction word, stepped with an
+  // explicit carry (two 32-bit adds)
+  int32_t hi = (int32_t)(E0 >> 32);
+  uint32_t lo = (uint32_t)E0;
+  const int32_t dhi = (int32_t)(dE >> 32);
+  const uint32_t dlo = (uint32_t)dE;
   const float aa = (float)fabs(al);
-  // distance (in columns) of candidate column floor(e) + 1 + m from j* is
-  // (1 + m - rr) - frac(e)
-  const float k1 = (float)(1.0 - rr), k2 = (float)(2.0 - rr), k3 = (float)(3.0 - rr);
-  constexpr float kInvFx = 2.3283064365386963e-10f;   // 2^-32
+  const float aaf = aa * 2.3283064365386963e-10f;   // aa 2^-32 (phi carried x 2^32)
+  const float c2w = 2.0f * aa - 1.0f, c3w = 2.0f - 3.0f * aa;
   float acc = 0.0f;
+  // one buffer descriptor per row (scalar work): reads past the row's end
+  // return 0 instead of touching the next row
+  const char* rowb = reinterpret_cast<const char*>(src + (int64_t)qlo * pitch);
+  const int row_bytes = (int)(pitch * sizeof(float));
+  constexpr uint32_t kOff0 = (kTomoPad + 1) * sizeof(float);
 #pragma unroll 8
-  for (int q = 0; q < nq; ++q) {
-    const uint64_t U = (uint64_t)E;
-    // first candidate column floor(e) + 1, as an offset into the padded row
-    // (clamped into the zero pad when the hat misses the image)
-    const int o = min(max((int)(uint32_t)(U >> 32) + kTomoPad + 1, 1), nj + kTomoPad + 1);
-    const float ph = (float)(uint32_t)U;      // frac(e) * 2^32
-    const float* p = src + (int64_t)q * pitch + (uint32_t)o;
-    acc = fmaf(hat_weight(fmaf(ph, -kInvFx, k1), aa), p[0], acc);
-    acc = fmaf(hat_weight(fmaf(ph, -kInvFx, k2), aa), p[1], acc);
-    acc = fmaf(hat_weight(fmaf(ph, -kInvFx, k3), aa), p[2], acc);
-    E += dE;
+  for (int q = qlo; q <= qhi; ++q) {
+    const float ph = (float)lo;                       // phi * 2^32
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(rowb), (short)0, row_bytes, kBufferWord3);
+    const auto v3 =
+        __builtin_amdgcn_raw_buffer_load_b96(rs, ((uint32_t)hi << 2) + kOff0, 0, 0);
+    const float w1 = fmaf(-aaf, ph, aa);
+    const float w2 = 1.0f - fabsf(fmaf(-aaf, ph, c2w));
+    const float w3 = __builtin_amdgcn_fmed3f(fmaf(aaf, ph, c3w), 0.0f, 1.0f);
+    acc = fmaf(w1, __uint_as_float(v3[0]), acc);
+    acc = fmaf(w2, __uint_as_float(v3[1]), acc);
+    acc = fmaf(w3, __uint_as_float(v3[2]), acc);
+    unsigned carry;
+    lo = __builtin_addc(lo, dlo, 0u, &carry);
+    hi = (int32_t)__builtin_addc((unsigned)hi, (unsigned)dhi, carry, &carry);
+    rowb += row_bytes;
   }
   double v = 0.0, unused = 0.0;
   if (i < a.nd) {

@@ -240,5 +240,5 @@ WORKLOADS = {
     # paper's measured sinograms (Section 7)
     "tomo_2048x1000": dict(kind="tomo", H=2048, W=2048, n_angles=1000,
                            n_det=2048, n_ellipses=32, noise=0.01, seed=6000,
-                           iters=20),
+                           lam=10.0, iters=20),
 }
