@@ -221,3 +221,42 @@ def backproject_at(s: np.ndarray, H: int, W: int, rows, cols) -> np.ndarray:
         w = np.maximum(0.0, 1.0 - np.abs(u[:, None] - t[None, :]))
         out[j] = float(np.sum(w * s))
     return out
+
+
+# --------------------------------------------------------------------------
+# Regularised filtered backprojection (Section 6, eq. reg_sol and the filter
+# after it): f_lam = B F_lam g, each projection filtered in t by the
+# frequency response |nu| / (1 + lam |nu|) and backprojected with the factor
+# dtheta = pi / n_angles (B = dtheta A^T).  nu is in cycles per pixel (for
+# lam = 0 this is the ramp filter of the standard inversion formula); lam is
+# in pixels.  The filter acts on each projection zero-padded to
+# fbp_length(n_det), the smallest power of two >= 2 n_det, so that the
+# circular convolution equals the linear one on the detector.
+# --------------------------------------------------------------------------
+
+def fbp_length(n_det: int) -> int:
+    L = 1
+    while L < 2 * n_det:
+        L *= 2
+    return L
+
+
+def fbp_response(n_det: int, lam: float) -> np.ndarray:
+    """The filter's DFT samples H[m] at nu_m = fftfreq(L)[m]."""
+    nu = np.abs(np.fft.fftfreq(fbp_length(n_det)))
+    return nu / (1.0 + lam * nu)
+
+
+def fbp_filter(s: np.ndarray, lam: float) -> np.ndarray:
+    """F_lam applied to every projection (row) of s."""
+    s = np.asarray(s, dtype=np.float64)
+    n_angles, n_det = s.shape
+    L = fbp_length(n_det)
+    spec = np.fft.fft(s, n=L, axis=1) * fbp_response(n_det, lam)[None, :]
+    return np.real(np.fft.ifft(spec, axis=1))[:, :n_det]
+
+
+def fbp(s: np.ndarray, H: int, W: int, lam: float) -> np.ndarray:
+    """f_lam = (pi / n_angles) A^T F_lam s."""
+    n_angles = np.shape(s)[0]
+    return (math.pi / n_angles) * backproject(fbp_filter(s, lam), H, W)

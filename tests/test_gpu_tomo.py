@@ -52,6 +52,7 @@ GEOMS = [
     (40, 40, 33, 30),        # detector narrower than the image
     (20, 75, 4, 81),         # 0, 45, 90, 135 degrees
     (33, 129, 70, 150),      # three angle chunks, ragged
+    (200, 200, 400, 300),    # many angles, fine angle step
     (1, 1, 5, 3),
     (1, 17, 3, 1),
     (9, 1, 1, 12),

@@ -204,3 +204,54 @@ def test_single_entries_match_the_full_operators():
     rr, cc = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
     np.testing.assert_allclose(tomo.backproject_at(s, H, W, rr.ravel(), cc.ravel()),
                                B.ravel(), rtol=1e-12, atol=1e-12)
+
+
+def test_ramp_filter_impulse_response():
+    # lam = 0: the response of an impulse is the ramp filter's kernel on the
+    # L-periodic grid: h[0] = 1/4 exactly, and close to the band-limited ramp
+    # kernel h[n] = -1/(pi n)^2 (n odd), 0 (n even) of the standard
+    # inversion formula (Kak & Slaney, Section 3.3)
+    nd = 200
+    L = tomo.fbp_length(nd)
+    assert L == 512
+    e = np.zeros((1, nd))
+    e[0, 100] = 1.0
+    h = tomo.fbp_filter(e, 0.0)[0]
+    assert h[100] == pytest.approx(0.25, abs=1e-12)
+    for n in (1, 3, 5, 7):
+        assert h[100 + n] == pytest.approx(-1.0 / (math.pi * n) ** 2, rel=2e-3)
+        assert h[100 - n] == pytest.approx(h[100 + n], rel=1e-12)
+    for n in (2, 4, 6):
+        assert abs(h[100 + n]) < 1e-4
+    # lam > 0 damps the high frequencies: a smaller centre tap, same sum
+    h4 = tomo.fbp_filter(e, 4.0)[0]
+    assert 0 < h4[100] < h[100]
+
+
+def test_fbp_reconstructs_the_phantom():
+    # lam = 0, exact line integrals of an ellipse phantom: the inversion
+    # formula's discretisation error, a wrong scale, axis or filter fails
+    N, na = 128, 180
+    nd = int(math.ceil(math.hypot(N, N))) + 4
+    img, clean, _ = scenes.tomo_scene(N, N, na, nd, n_ellipses=10, noise=0.0, seed=21)
+    f = tomo.fbp(clean, N, N, 0.0)
+    assert np.linalg.norm(f - img) / np.linalg.norm(img) < 0.15
+    on = img > 0.05
+    assert abs(float(np.median(f[on] / img[on])) - 1.0) < 0.02
+
+
+def test_regularised_fbp_approximates_the_tikhonov_solution():
+    # Section 6: f_lam = B F_lam g solves the (continuous) Tikhonov problem;
+    # with B = dtheta A^T its discrete counterpart is (A^T A + lam/dtheta) f =
+    # A^T g.  The two agree up to discretisation (7 % and 5 % here; a factor
+    # of 2 in the weight gives 20 % and more)
+    N, na = 24, 40
+    nd = int(math.ceil(math.hypot(N, N))) + 4
+    _, clean, _ = scenes.tomo_scene(N, N, na, nd, n_ellipses=5, noise=0.0, seed=22)
+    A = dense_A(N, N, na, nd)
+    dth = math.pi / na
+    for lam in (4.0, 16.0):
+        fb = tomo.fbp(clean, N, N, lam)
+        ft = np.linalg.solve(A.T @ A + (lam / dth) * np.eye(N * N),
+                             A.T @ clean.ravel()).reshape(N, N)
+        assert np.linalg.norm(fb - ft) / np.linalg.norm(ft) < 0.1
