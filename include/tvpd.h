@@ -411,6 +411,19 @@ int tvpd_tomo_energy(const tvpd_tomo_geom* geom, const float* g, float lam,
 int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
                      size_t ws_bytes, double* out, void* stream);
 
+/* Regularised filtered backprojection (Section 6, eq. reg_sol and the
+ * filter after it): f_out = (pi / n_angles) A^T F_lam g, where F_lam filters
+ * every projection in t with the frequency response |nu| / (1 + lam |nu|)
+ * (nu in cycles per pixel, lam >= 0 in pixels; lam = 0 is the ramp filter of
+ * the standard inversion formula), as a linear convolution over the
+ * detector: the circular convolution on the zero-padded grid of length L,
+ * the smallest power of two >= 2 n_det.  g: device [n_angles][n_det];
+ * f_out: device [ny][nx].  The response's taps are formed on the device in
+ * O(L n_det) work per call; the filtering costs n_det^2 per projection.
+ * Uses the workspace's scratch sinogram only. */
+int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out,
+             void* ws, size_t ws_bytes, void* stream);
+
 /* tvpd_tomo_init(f0 = NULL) + tvpd_tomo_step(n_iter) + f_out = f^n_iter. */
 int tvpd_tomo_solve(const tvpd_tomo_geom* geom, const float* g,
                     const tvpd_tomo_params* prm, int32_t n_iter, float* f_out,

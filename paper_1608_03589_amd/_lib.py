@@ -124,6 +124,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_double), _P]),
     "tvpd_tomo_opnorm": (C.c_int, [C.POINTER(TomoGeom), _I32, _P, _SZ,
                                    C.POINTER(C.c_double), _P]),
+    "tvpd_fbp": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _P, _P, _SZ, _P]),
     "tvpd_tomo_solve": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,
                                   _P, _P, _SZ, _P]),
 }

@@ -44,6 +44,17 @@ constexpr int kBpPerLane = kBpRows / (kMaxBlock / kWave);  // 8 pixels per lane
 constexpr int kBpChunk = 32;         // angles staged per round
 constexpr int kBpWin = 80;           // bins per staged window (>= 71 + margins)
 constexpr int kTomoPrepTile = 32;    // transpose tile of the prep kernel
+constexpr int kFbpOut = 8 * 256;     // filtered outputs per block (8 per thread)
+constexpr int kFbpIn = 1024;         // inputs staged per round
+
+// Length of the zero-padded filtering grid: the smallest power of two
+// >= 2 n_det (so circular convolution equals linear convolution on the
+// detector).
+__host__ __device__ inline int tomo_fbp_length(int nd) {
+  int L = 1;
+  while (L < 2 * nd) L *= 2;
+  return L;
+}
 
 // Device state at the start of a tomography workspace.
 struct TomoState {
@@ -63,6 +74,7 @@ struct TomoLayout {
   int64_t max_partials;
   size_t off_trig;    // double2 per angle
   size_t off_part;    // 2 doubles per partial slot
+  size_t off_fbp;     // n_det floats: the filter's impulse response
   size_t off_planes;  // first plane
   size_t bytes;
 };
@@ -78,6 +90,7 @@ struct TomoPtrs {
   TomoState* st;
   double* trig;       // [na][2]: cos, sin
   double* part;       // partials
+  float* fbp;         // filter taps
   float* img[kTNumImg];
   float* sino[kTNumSino];
   float* fb;
@@ -131,6 +144,11 @@ int tomo_project_blocks(int na, int nd);
 int launch_tomo_backproject(const BpArgs& a, int mode, const int32_t* kptr,
                             const float* f1, float* out1, const float* px1,
                             const float* py1, hipStream_t s);
+// Regularised FBP: taps hs[0, nd) of the filter |nu| / (1 + lam |nu|), and
+// q = scale * (hs * g) row by row.
+int launch_tomo_fbp_taps(float* hs, int nd, float lam, hipStream_t s);
+int launch_tomo_fbp_filter(const float* g, float* q, const float* hs, int na, int nd,
+                           float scale, hipStream_t s);
 int launch_tomo_fill(float* p, int64_t n, float v, hipStream_t s);
 int launch_tomo_advance(TomoState* st, hipStream_t s);
 int launch_tomo_set_k(TomoState* st, int k, hipStream_t s);

@@ -315,6 +315,87 @@ __global__ __launch_bounds__(kMaxBlock) void tomo_backproject_kernel(BpKernelArg
   }
 }
 
+// Regularised filtered backprojection: the filter's impulse response.
+// hs[n] (0 <= n < nd) = (1/L) sum_m H_m cos(2 pi m n / L) with
+// H_m = |nu_m| / (1 + lam |nu_m|), nu_m the signed DFT frequency of index m
+// on the length-L grid (H is even, so the response is real and even).
+// One wave per tap, its lanes striding over m; float64, the product m n
+// reduced modulo L exactly before the cosine.
+__global__ __launch_bounds__(kMaxBlock) void tomo_fbp_taps_kernel(float* hs, int nd, int L,
+                                                                  double lam) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n = blockIdx.x * (kMaxBlock / kWave) + threadIdx.x / kWave;
+  if (n >= nd) return;                       // whole waves
+  double acc = 0.0;
+  for (int m = 1 + lane; m < L / 2; m += kWave) {
+    const double nu = (double)m / (double)L;
+    const int mn = (int)(((int64_t)m * n) % L);
+    acc += 2.0 * (nu / (1.0 + lam * nu)) * cospi(2.0 * (double)mn / (double)L);
+  }
+  acc = dev::wave_sum(acc);
+  if (lane == 0) {
+    acc += (0.5 / (1.0 + 0.5 * lam)) * ((n & 1) ? -1.0 : 1.0);   // m = L/2
+    hs[n] = (float)(acc / (double)L);
+  }
+}
+
+// q[k][i] = scale sum_j hs[|i - j|] g[k][j] for one projection k and
+// kFbpOut outputs per block: each thread accumulates 8 consecutive outputs
+// over blocks of 8 inputs from a 16-tap window (aligned LDS reads); inputs
+// and taps are staged kFbpIn inputs at a time.
+__global__ __launch_bounds__(kMaxBlock) void tomo_fbp_filter_kernel(
+    const float* g, float* q, const float* hs, int nd, float scale) {
+  __shared__ __align__(16) float gs[kFbpIn];
+  __shared__ __align__(16) float hw[kFbpOut + kFbpIn + 8];
+  const int k = blockIdx.y;
+  const int I0 = blockIdx.x * kFbpOut;
+  const int off = 8 * (int)threadIdx.x;            // i0 - I0
+  const float* gr = g + (int64_t)k * nd;
+  float acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0f;
+  for (int J0 = 0; J0 < nd; J0 += kFbpIn) {
+    const int nj = min(kFbpIn, nd - J0);
+    // hw[e] = h(d) for d = I0 - J0 - (kFbpIn - 1) + e (zero for |d| >= nd)
+    const int dmin = I0 - J0 - (kFbpIn - 1);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kFbpIn; e += kMaxBlock) gs[e] = e < nj ? gr[J0 + e] : 0.0f;
+    for (int e = threadIdx.x; e < kFbpOut + kFbpIn + 8; e += kMaxBlock) {
+      const int d = dmin + e, ad = d < 0 ? -d : d;
+      hw[e] = ad < nd ? hs[ad] : 0.0f;
+    }
+    __syncthreads();
+    // output u, input jj + t: d - dmin = off + u + (kFbpIn - 1) - jj - t
+    //   = (off + kFbpIn - 8 - jj) + (u - t + 7); the window starts at a
+    // multiple of 8
+    for (int jj = 0; jj < kFbpIn; jj += 8) {
+      const float4* w4 = reinterpret_cast<const float4*>(hw + off + kFbpIn - 8 - jj);
+      float w[16];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float4 x = w4[v];
+        w[4 * v] = x.x;
+        w[4 * v + 1] = x.y;
+        w[4 * v + 2] = x.z;
+        w[4 * v + 3] = x.w;
+      }
+      const float4 ga = *reinterpret_cast<const float4*>(gs + jj);
+      const float4 gb = *reinterpret_cast<const float4*>(gs + jj + 4);
+      const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = fmaf(w[u - t + 7], gv[t], acc[u]);
+    }
+  }
+  float* qr = q + (int64_t)k * nd;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = I0 + off + u;
+    if (i < nd) qr[i] = acc[u] * scale;
+  }
+}
+
 __global__ void tomo_fill_kernel(float* p, int64_t n, float v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -470,6 +551,20 @@ int launch_tomo_backproject(const BpArgs& a, int mode, const int32_t* kptr,
     case kBpTV: tomo_backproject_kernel<kBpTV><<<grid, kMaxBlock, 0, s>>>(ka); break;
     default: return TVPD_ERR_INVALID_ARG;
   }
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_fbp_taps(float* hs, int nd, float lam, hipStream_t s) {
+  constexpr int kTapsPerBlock = kMaxBlock / kWave;
+  tomo_fbp_taps_kernel<<<(nd + kTapsPerBlock - 1) / kTapsPerBlock, kMaxBlock, 0, s>>>(
+      hs, nd, tomo_fbp_length(nd), (double)lam);
+  return TOMO_LAUNCHED();
+}
+
+int launch_tomo_fbp_filter(const float* g, float* q, const float* hs, int na, int nd,
+                           float scale, hipStream_t s) {
+  const dim3 grid((nd + kFbpOut - 1) / kFbpOut, na);
+  tomo_fbp_filter_kernel<<<grid, kMaxBlock, 0, s>>>(g, q, hs, nd, scale);
   return TOMO_LAUNCHED();
 }
 

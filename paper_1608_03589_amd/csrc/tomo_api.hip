@@ -24,7 +24,8 @@ TomoLayout tomo_layout(int ny, int nx, int na, int nd) {
   L.max_partials = nproj + (nreg > ndot ? nreg : ndot) + 1;
   L.off_trig = kHeaderBytes;
   L.off_part = (size_t)round_up((int64_t)L.off_trig + 16 * (int64_t)na, (int64_t)kAlign);
-  L.off_planes = (size_t)round_up((int64_t)L.off_part + 16 * L.max_partials, (int64_t)kAlign);
+  L.off_fbp = (size_t)round_up((int64_t)L.off_part + 16 * L.max_partials, (int64_t)kAlign);
+  L.off_planes = (size_t)round_up((int64_t)L.off_fbp + 4 * (int64_t)nd, (int64_t)kAlign);
   L.bytes = L.off_planes +
             sizeof(float) * (size_t)(kTNumImg * L.img + kTNumSino * L.sino + L.fb + L.fbt);
   return L;
@@ -36,6 +37,7 @@ TomoPtrs tomo_ptrs(const TomoLayout& L, void* ws) {
   p.st = reinterpret_cast<TomoState*>(base);
   p.trig = reinterpret_cast<double*>(base + L.off_trig);
   p.part = reinterpret_cast<double*>(base + L.off_part);
+  p.fbp = reinterpret_cast<float*>(base + L.off_fbp);
   float* f = reinterpret_cast<float*>(base + L.off_planes);
   for (int i = 0; i < kTNumImg; ++i, f += L.img) p.img[i] = f;
   for (int i = 0; i < kTNumSino; ++i, f += L.sino) p.sino[i] = f;
@@ -329,6 +331,22 @@ int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
     return TVPD_ERR_HIP;
   *out = est;
   return TVPD_OK;
+}
+
+int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out,
+             void* ws, size_t ws_bytes, void* stream) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!g || !f_out || !(lam >= 0.0f) || !std::isfinite(lam)) return TVPD_ERR_INVALID_ARG;
+  const TomoLayout L = tomo_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  TOMO_TRY(check_ws(L, ws, ws_bytes));
+  const TomoPtrs P = tomo_ptrs(L, ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TOMO_TRY(launch_tomo_trig(P.trig, L.na, s));
+  TOMO_TRY(launch_tomo_fbp_taps(P.fbp, L.nd, lam, s));
+  // the factor dtheta of the backprojection goes with the filter
+  TOMO_TRY(launch_tomo_fbp_filter(g, P.sino[kTS], P.fbp, L.na, L.nd,
+                                  (float)(M_PI / (double)L.na), s));
+  return backward(L, P, P.sino[kTS], f_out, s);
 }
 
 int tvpd_tomo_solve(const tvpd_tomo_geom* geom, const float* g,

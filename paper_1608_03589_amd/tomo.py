@@ -90,6 +90,18 @@ class TomoSolver:
              C.c_void_p(out.data_ptr()), *self._args())
         return out
 
+    def fbp(self, s: torch.Tensor, lam: float = 0.0,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+        """Regularised filtered backprojection (pi/n_angles) A^T F_lam s,
+        F_lam the filter |nu| / (1 + lam |nu|) (lam = 0: the ramp filter)."""
+        self._check(s, "sino", (self.n_angles, self.n_det))
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        self._check(out, "out", (self.ny, self.nx))
+        call("tvpd_fbp", C.byref(self.geom), C.c_void_p(s.data_ptr()), float(lam),
+             C.c_void_p(out.data_ptr()), *self._args())
+        return out
+
     def opnorm_sq(self, iters: int = 50) -> float:
         """||A||^2 by power iteration on A^T A from the constant image."""
         v = C.c_double()

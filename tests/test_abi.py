@@ -161,6 +161,9 @@ def test_tomo_validation_without_gpu(L):
     assert L.tvpd_radon_backward(C.byref(good), dummy, None, dummy, 1 << 40, None) == -1
     out = C.c_double()
     assert L.tvpd_tomo_opnorm(C.byref(good), 0, dummy, 1 << 40, C.byref(out), None) == -1
+    assert L.tvpd_fbp(C.byref(good), dummy, -1.0, dummy, dummy, 1 << 40, None) == -1
+    assert L.tvpd_fbp(C.byref(good), None, 0.0, dummy, dummy, 1 << 40, None) == -1
+    assert L.tvpd_fbp(C.byref(good), dummy, 0.0, dummy, dummy, 16, None) == -4
     res = (C.c_double * 3)()
     assert L.tvpd_tomo_energy(C.byref(good), dummy, 0.1, 5, dummy, 1 << 40, res,
                               None) == -1
