@@ -260,3 +260,94 @@ def fbp(s: np.ndarray, H: int, W: int, lam: float) -> np.ndarray:
     """f_lam = (pi / n_angles) A^T F_lam s."""
     n_angles = np.shape(s)[0]
     return (math.pi / n_angles) * backproject(fbp_filter(s, lam), H, W)
+
+
+# --------------------------------------------------------------------------
+# Backprojection slice theorem (BST, Section 4, eq. bst, and the algorithm of
+# Section 5): the 2D Fourier transform of B g on the line through the origin
+# at angle theta equals the 1D Fourier transform of the projection at theta,
+# divided by |nu|.  In the cycles convention (transforms with exp(-2 pi i nu x))
+# F[B g](nu xi_theta) = G(nu, theta) / |nu| exactly, with B = dtheta A^T for
+# sampled data.  Steps, on a detector of spacing 1:
+#   1. G_k(nu_j) = sum_i g_k[i] exp(-2 pi i nu_j t_i), nu_j = j / M on the
+#      zero-padded grid of length M = bst_lengths()[0];
+#   2. times K(nu) = 1 / |nu|, and 1 / dnu = M at nu = 0 (the origin rule of
+#      the kernel K^sigma in Section 5);
+#   3. bilinear interpolation of these polar samples (theta_k, nu_j) at the
+#      Cartesian frequencies (p / Q, q / Q) of a Q x Q grid, zero beyond
+#      |nu| = 1/2; theta in [0, pi) with signed nu covers the plane;
+#   4. 2D inverse DFT, evaluated at the pixel centres.
+# No window is applied: with full projections (t over the whole detector)
+# the data already vanish at both ends.
+# --------------------------------------------------------------------------
+
+def bst_lengths(H: int, W: int, n_det: int):
+    """(M, Q): 1D transform length (power of two >= 2 n_det) and the side of
+    the Cartesian frequency grid (power of two >= 2 max(H, W))."""
+    M = fbp_length(n_det)
+    Q = 1
+    while Q < 2 * max(H, W):
+        Q *= 2
+    return M, Q
+
+
+def bst_spectra(s: np.ndarray, M: int) -> np.ndarray:
+    """Steps 1-2: K(nu_j) G_k(nu_j) for j = -M/2 .. M/2-1 (row k, column
+    j + M/2), complex128."""
+    s = np.asarray(s, dtype=np.float64)
+    n_angles, n_det = s.shape
+    t = detector(n_det)
+    nu = (np.arange(M) - M // 2) / M
+    G = s @ np.exp(-2j * np.pi * np.outer(t, nu))          # plain DFT
+    K = np.where(nu == 0.0, float(M), 1.0 / np.where(nu == 0.0, 1.0, np.abs(nu)))
+    return G * K[None, :]
+
+
+def bst_cartesian(P: np.ndarray, Q: int) -> np.ndarray:
+    """Step 3: the Q x Q grid of frequencies (u_p, v_q) = (p, q) / Q for
+    p, q = -Q/2 .. Q/2-1 (array index [q + Q/2, p + Q/2]), bilinear in
+    (theta, nu) from the polar samples P."""
+    n_angles, M = P.shape
+    f = (np.arange(Q) - Q // 2) / Q
+    u, v = np.meshgrid(f, f)                  # u along columns (x), v along rows (y)
+    rho = np.hypot(u, v)
+    phi = np.arctan2(v, u)                     # (-pi, pi]
+    neg = phi < 0.0
+    theta = np.where(neg, phi + np.pi, phi)
+    nu = np.where(neg, -rho, rho)
+    top = theta >= np.pi                       # phi = pi: theta pi == 0 with -nu
+    theta = np.where(top, theta - np.pi, theta)
+    nu = np.where(top, -nu, nu)
+    a = theta / (np.pi / n_angles)             # angle index, in [0, n_angles)
+    k0 = np.floor(a).astype(np.int64)
+    wa = a - k0
+    k1 = k0 + 1                                # k1 == n_angles: theta = pi, nu -> -nu
+    flip = k1 >= n_angles
+    k1 = np.where(flip, 0, k1)
+
+    def radial(k, nuv):
+        x = nuv * M + M // 2                   # radial index
+        j0 = np.floor(x).astype(np.int64)
+        wr = x - j0
+        ok0 = (j0 >= 0) & (j0 < M)
+        ok1 = (j0 + 1 >= 0) & (j0 + 1 < M)
+        p0 = np.where(ok0, P[k, np.clip(j0, 0, M - 1)], 0.0)
+        p1 = np.where(ok1, P[k, np.clip(j0 + 1, 0, M - 1)], 0.0)
+        return (1.0 - wr) * p0 + wr * p1
+
+    F = (1.0 - wa) * radial(k0, nu) + wa * radial(k1, np.where(flip, -nu, nu))
+    return np.where(rho <= 0.5, F, 0.0)
+
+
+def bst(s: np.ndarray, H: int, W: int) -> np.ndarray:
+    """B s (= dtheta A^T s up to the method's interpolation) by the BST."""
+    s = np.asarray(s, dtype=np.float64)
+    M, Q = bst_lengths(H, W, s.shape[1])
+    F = bst_cartesian(bst_spectra(s, M), Q)
+    f = (np.arange(Q) - Q // 2) / Q
+    x = np.arange(W) + 0.5 - W / 2.0
+    y = np.arange(H) + 0.5 - H / 2.0
+    # b(x, y) = sum_{p,q} F[q, p] exp(2 pi i (u_p x + v_q y)) / Q^2
+    Ex = np.exp(2j * np.pi * np.outer(f, x))   # [p, x]
+    Ey = np.exp(2j * np.pi * np.outer(y, f))   # [y, q]
+    return np.real(Ey @ F @ Ex) / (Q * Q)
