@@ -424,6 +424,30 @@ int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
 int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out,
              void* ws, size_t ws_bytes, void* stream);
 
+/* Fast backprojection by the backprojection slice theorem (Section 4, eq.
+ * bst; the algorithm of Section 5).  In the cycles convention the 2D Fourier
+ * transform of B g on the line at angle theta is G(nu, theta) / |nu|, G the 1D
+ * transform of the projection; for sampled data B = (pi / n_angles) A^T.
+ * Steps: the DFT of each zero-padded projection (length M, a power of two
+ * >= 2 n_det) times K(nu) = 1/|nu|, with 1/dnu = M at nu = 0; bilinear
+ * interpolation of these polar samples at the frequencies (p, q)/Q of a
+ * Q x Q grid (Q a power of two >= 2 max(ny, nx)), zero beyond |nu| = 1/2;
+ * the 2D inverse DFT at the pixel centres.  The result approximates
+ * (pi / n_angles) A^T g; the origin rule makes it differ by about a constant
+ * (which halves when the grids double).  Lengths are limited to M, Q <= 4096
+ * (n_det <= 2048, ny, nx <= 2048): TVPD_ERR_UNSUPPORTED beyond.  The BST has
+ * its own workspace. */
+int tvpd_bst_lengths(const tvpd_tomo_geom* geom, int32_t* M, int32_t* Q);
+int tvpd_bst_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes);
+/* img = BST backprojection of g (device [n_angles][n_det] -> [ny][nx]). */
+int tvpd_bst_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
+                         void* ws, size_t ws_bytes, void* stream);
+/* The polar samples of the second step, spec[k][j + M/2] = K(nu_j) G_k(nu_j)
+ * for nu_j = j / M, j = -M/2 .. M/2-1 (device, complex as interleaved
+ * float pairs, [n_angles][M][2]). */
+int tvpd_bst_spectra(const tvpd_tomo_geom* geom, const float* g, float* spec,
+                     void* ws, size_t ws_bytes, void* stream);
+
 /* tvpd_tomo_init(f0 = NULL) + tvpd_tomo_step(n_iter) + f_out = f^n_iter. */
 int tvpd_tomo_solve(const tvpd_tomo_geom* geom, const float* g,
                     const tvpd_tomo_params* prm, int32_t n_iter, float* f_out,

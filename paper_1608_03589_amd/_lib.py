@@ -125,6 +125,10 @@ SIGNATURES = {
     "tvpd_tomo_opnorm": (C.c_int, [C.POINTER(TomoGeom), _I32, _P, _SZ,
                                    C.POINTER(C.c_double), _P]),
     "tvpd_fbp": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _P, _P, _SZ, _P]),
+    "tvpd_bst_lengths": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_I32), C.POINTER(_I32)]),
+    "tvpd_bst_workspace_size": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_SZ)]),
+    "tvpd_bst_backproject": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
+    "tvpd_bst_spectra": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
     "tvpd_tomo_solve": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,
                                   _P, _P, _SZ, _P]),
 }

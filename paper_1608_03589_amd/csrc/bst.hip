@@ -1,0 +1,323 @@
+// Backprojection by the backprojection slice theorem (BST): the paper's fast
+// backprojection (Section 4, eq. bst; algorithm of Section 5), on the
+// geometry of the tomographic operators (tomo.h).
+//
+// In the cycles convention the theorem reads F[B g](nu xi_theta) =
+// G(nu, theta) / |nu| (B the continuous backprojection; B = dtheta A^T for
+// sampled data).  Steps:
+//   1. per projection, the DFT of the zero-padded projection, length M (a
+//      power of two >= 2 n_det), with the phase of the detector's centring;
+//   2. times K(nu) = 1/|nu|, and 1/dnu = M at nu = 0 (the origin rule);
+//   3. bilinear interpolation of the polar samples (theta_k, nu_j) at the
+//      frequencies (p, q)/Q of a Q x Q grid (Q a power of two >= 2 max(ny,
+//      nx)), zero beyond |nu| = 1/2, times the phase that puts the pixel
+//      centres on the integer grid;
+//   4. 2D inverse DFT (row transforms, a transpose, row transforms), real
+//      part at the pixels, divided by Q^2.
+// The transforms are radix-2 Stockham FFTs in LDS (lengths up to 4096), with
+// twiddles from a float64 table.  Every phase is reduced as an exact integer
+// before its sine and cosine.
+#include <cmath>
+
+#include "tomo.h"
+
+namespace tvpd {
+
+constexpr int kBstMaxLen = 4096;   // LDS FFT length limit (two 32 KiB buffers)
+
+__host__ __device__ inline int bst_pow2_at_least(int v) {
+  int L = 1;
+  while (L < v) L *= 2;
+  return L;
+}
+
+struct BstLayout {
+  int ny, nx, na, nd, M, Q;
+  size_t off_tw, off_spec, off_a, off_b, bytes;
+};
+
+BstLayout bst_layout(int ny, int nx, int na, int nd) {
+  BstLayout L;
+  L.ny = ny;
+  L.nx = nx;
+  L.na = na;
+  L.nd = nd;
+  L.M = bst_pow2_at_least(2 * nd);
+  L.Q = bst_pow2_at_least(2 * (ny > nx ? ny : nx));
+  const int tl = L.M > L.Q ? L.M : L.Q;
+  L.off_tw = kHeaderBytes;
+  L.off_spec = (size_t)round_up((int64_t)L.off_tw + 8 * (int64_t)(tl / 2), (int64_t)kAlign);
+  L.off_a = (size_t)round_up((int64_t)L.off_spec + 8 * (int64_t)na * L.M, (int64_t)kAlign);
+  L.off_b = (size_t)round_up((int64_t)L.off_a + 8 * (int64_t)L.Q * L.Q, (int64_t)kAlign);
+  L.bytes = L.off_b + 8 * (size_t)L.Q * (size_t)L.Q;
+  return L;
+}
+
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// tw[m] = exp(-2 pi i m / L), m < L/2, from float64.
+__global__ void bst_twiddle_kernel(float2* tw, int L) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= L / 2) return;
+  const double a = -2.0 * (double)m / (double)L;
+  tw[m] = make_float2((float)cospi(a), (float)sinpi(a));
+}
+
+// Radix-2 Stockham transform of length n (a power of two) in LDS, in place in
+// the sense that the result is left in *x (the buffers are swapped).  SIGN -1:
+// forward (exp(-2 pi i ...)), +1: inverse without the 1/n.  tw: table of
+// length tl/2 (tl a multiple of n).  Every thread of the block takes part.
+template <int SIGN>
+__device__ void fft_lds(float2*& x, float2*& y, int n, const float2* tw, int tl) {
+  for (int Ns = 1; Ns < n; Ns <<= 1) {
+    const int stride = tl / (2 * Ns);
+    for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
+      const int k = j & (Ns - 1);
+      const float2 v0 = x[j];
+      float2 w = tw[k * stride];
+      if (SIGN > 0) w.y = -w.y;
+      const float2 v1 = cmul(x[j + n / 2], w);
+      const int d = ((j - k) << 1) + k;
+      y[d] = make_float2(v0.x + v1.x, v0.y + v1.y);
+      y[d + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
+    }
+    __syncthreads();
+    float2* t = x;
+    x = y;
+    y = t;
+  }
+}
+
+// Steps 1-2 for projection k: spec[k][m + M/2] = K(nu) exp(-2 pi i nu t_0) DFT(g_k)
+// at nu = m / M, m = -M/2 .. M/2-1.
+__global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, float2* spec,
+                                                                const float2* tw, int nd,
+                                                                int M, int tl) {
+  __shared__ float2 buf[2][kBstMaxLen];
+  float2* x = buf[0];
+  float2* y = buf[1];
+  const int k = blockIdx.x;
+  const float* gr = g + (int64_t)k * nd;
+  for (int i = threadIdx.x; i < M; i += blockDim.x)
+    x[i] = make_float2(i < nd ? gr[i] : 0.0f, 0.0f);
+  __syncthreads();
+  fft_lds<-1>(x, y, M, tw, tl);
+  float2* out = spec + (int64_t)k * M;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    const int ms = m < M / 2 ? m : m - M;          // signed frequency index
+    // t_0 = (1 - nd) / 2: phase -2 pi ms t_0 / M = pi ms (nd - 1) / M,
+    // reduced modulo 2M exactly
+    int64_t ph = ((int64_t)ms * (nd - 1)) % (2 * (int64_t)M);
+    if (ph < 0) ph += 2 * (int64_t)M;
+    float sn, cs;
+    sincospif((float)ph / (float)M, &sn, &cs);
+    const float kk = ms == 0 ? (float)M : (float)M / (float)(ms < 0 ? -ms : ms);
+    const float2 v = cmul(x[m], make_float2(cs, sn));
+    out[ms + M / 2] = make_float2(v.x * kk, v.y * kk);
+  }
+}
+
+// Step 3 at (p, q) in DFT order: A[q][p] = phase * bilinear(spec).
+__global__ void bst_cartesian_kernel(const float2* spec, float2* A, int na, int M, int Q,
+                                     int nx, int ny) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (p >= Q) return;
+  const int ps = p < Q / 2 ? p : p - Q, qs = q < Q / 2 ? q : q - Q;
+  const double u = (double)ps / Q, v = (double)qs / Q;
+  const double rho = sqrt(u * u + v * v);
+  float2 val = make_float2(0.0f, 0.0f);
+  if (rho <= 0.5) {
+    double phi = atan2(v, u);                       // (-pi, pi]
+    double nu = rho;
+    if (phi < 0.0) {
+      phi += M_PI;
+      nu = -rho;
+    }
+    if (phi >= M_PI) {
+      phi -= M_PI;
+      nu = -nu;
+    }
+    const double aidx = phi / (M_PI / na);
+    int k0 = (int)floor(aidx);
+    if (k0 > na - 1) k0 = na - 1;                   // rounding at phi -> pi
+    const float wa = (float)(aidx - k0);
+    int k1 = k0 + 1;
+    double nu1 = nu;
+    if (k1 >= na) {                                 // theta = pi: angle 0, -nu
+      k1 = 0;
+      nu1 = -nu;
+    }
+    auto radial = [&](int k, double nv) {
+      const double xr = nv * M + M / 2;
+      const int j0 = (int)floor(xr);
+      const float wr = (float)(xr - j0);
+      const float2* row = spec + (int64_t)k * M;
+      const float2 p0 = (j0 >= 0 && j0 < M) ? row[j0] : make_float2(0.0f, 0.0f);
+      const float2 p1 = (j0 + 1 >= 0 && j0 + 1 < M) ? row[j0 + 1] : make_float2(0.0f, 0.0f);
+      return make_float2(p0.x + wr * (p1.x - p0.x), p0.y + wr * (p1.y - p0.y));
+    };
+    const float2 r0 = radial(k0, nu), r1 = radial(k1, nu1);
+    val = make_float2(r0.x + wa * (r1.x - r0.x), r0.y + wa * (r1.y - r0.y));
+    // pixel centres at n + (1 - n_side)/2: phase 2 pi (ps (1 - nx) + qs (1 - ny)) / (2Q)
+    int64_t ph = ((int64_t)ps * (1 - nx) + (int64_t)qs * (1 - ny)) % (2 * (int64_t)Q);
+    if (ph < 0) ph += 2 * (int64_t)Q;
+    float sn, cs;
+    sincospif((float)ph / (float)Q, &sn, &cs);
+    val = cmul(val, make_float2(cs, sn));
+  }
+  A[(int64_t)q * Q + p] = val;
+}
+
+// Inverse transforms of the rows of a Q x Q array, in place.
+__global__ __launch_bounds__(kMaxBlock) void bst_rows_inverse_kernel(float2* A, const float2* tw,
+                                                                     int Q, int tl) {
+  __shared__ float2 buf[2][kBstMaxLen];
+  float2* x = buf[0];
+  float2* y = buf[1];
+  float2* row = A + (int64_t)blockIdx.x * Q;
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) x[i] = row[i];
+  __syncthreads();
+  fft_lds<+1>(x, y, Q, tw, tl);
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) row[i] = x[i];
+}
+
+// B[c][r] = A[r][c] for a Q x Q complex array, 32 x 32 tiles.
+__global__ void bst_transpose_kernel(const float2* A, float2* B, int Q) {
+  __shared__ float2 t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int r = threadIdx.y; r < 32; r += 8)
+    t[r][threadIdx.x] = A[(int64_t)(r0 + r) * Q + c0 + threadIdx.x];
+  __syncthreads();
+  for (int c = threadIdx.y; c < 32; c += 8)
+    B[(int64_t)(c0 + c) * Q + r0 + threadIdx.x] = t[threadIdx.x][c];
+}
+
+// img[a][b] = Re(B[b][a]) / Q^2 (B holds the image transposed).
+__global__ void bst_extract_kernel(const float2* B, float* img, int Q, int ny, int nx,
+                                   float scale) {
+  __shared__ float t[32][33];
+  const int a0 = blockIdx.y * 32, b0 = blockIdx.x * 32;   // image rows a, columns b
+  for (int bb = threadIdx.y; bb < 32; bb += 8) {
+    const int b = b0 + bb, a = a0 + threadIdx.x;
+    t[bb][threadIdx.x] = (b < nx && a < ny) ? B[(int64_t)b * Q + a].x : 0.0f;
+  }
+  __syncthreads();
+  for (int aa = threadIdx.y; aa < 32; aa += 8) {
+    const int a = a0 + aa, b = b0 + threadIdx.x;
+    if (a < ny && b < nx) img[(int64_t)a * nx + b] = t[threadIdx.x][aa] * scale;
+  }
+}
+
+#define BST_TRY(call)                   \
+  do {                                  \
+    const int st_ = (call);             \
+    if (st_ != TVPD_OK) return st_;     \
+  } while (0)
+
+int launched() { return hipGetLastError() == hipSuccess ? TVPD_OK : TVPD_ERR_HIP; }
+
+bool geom_ok(const tvpd_tomo_geom* g) {
+  if (!g) return false;
+  return g->ny >= 1 && g->nx >= 1 && g->n_angles >= 1 && g->n_det >= 1 &&
+         g->ny <= kTomoMaxSide && g->nx <= kTomoMaxSide && g->n_det <= kTomoMaxSide &&
+         g->n_angles <= kTomoMaxAngles;
+}
+
+int supported(const BstLayout& L) {
+  return (L.M <= kBstMaxLen && L.Q <= kBstMaxLen && L.Q >= 32) ? TVPD_OK
+                                                                : TVPD_ERR_UNSUPPORTED;
+}
+
+int ws_check(const BstLayout& L, const void* ws, size_t bytes) {
+  if (!ws) return TVPD_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
+  if (bytes < L.bytes) return TVPD_ERR_WORKSPACE;
+  return TVPD_OK;
+}
+
+// Steps 1-2 into the workspace's spectra.
+int spectra(const BstLayout& L, const float* g, char* base, hipStream_t s) {
+  const int tl = L.M > L.Q ? L.M : L.Q;
+  float2* tw = reinterpret_cast<float2*>(base + L.off_tw);
+  bst_twiddle_kernel<<<(tl / 2 + 255) / 256, 256, 0, s>>>(tw, tl);
+  BST_TRY(launched());
+  bst_spectra_kernel<<<L.na, kMaxBlock, 0, s>>>(
+      g, reinterpret_cast<float2*>(base + L.off_spec), tw, L.nd, L.M, tl);
+  return launched();
+}
+
+}  // namespace
+}  // namespace tvpd
+
+using namespace tvpd;
+
+extern "C" {
+
+int tvpd_bst_lengths(const tvpd_tomo_geom* geom, int32_t* M, int32_t* Q) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!M || !Q) return TVPD_ERR_INVALID_ARG;
+  const BstLayout L = bst_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  *M = L.M;
+  *Q = L.Q;
+  return supported(L);
+}
+
+int tvpd_bst_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!bytes) return TVPD_ERR_INVALID_ARG;
+  const BstLayout L = bst_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  BST_TRY(supported(L));
+  *bytes = L.bytes;
+  return TVPD_OK;
+}
+
+int tvpd_bst_spectra(const tvpd_tomo_geom* geom, const float* g, float* spec, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!g || !spec) return TVPD_ERR_INVALID_ARG;
+  const BstLayout L = bst_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  BST_TRY(supported(L));
+  BST_TRY(ws_check(L, ws, ws_bytes));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  BST_TRY(spectra(L, g, base, s));
+  if (hipMemcpyAsync(spec, base + L.off_spec, 8 * (size_t)L.na * L.M, hipMemcpyDeviceToDevice,
+                     s) != hipSuccess)
+    return TVPD_ERR_HIP;
+  return TVPD_OK;
+}
+
+int tvpd_bst_backproject(const tvpd_tomo_geom* geom, const float* g, float* img, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!g || !img) return TVPD_ERR_INVALID_ARG;
+  const BstLayout L = bst_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  BST_TRY(supported(L));
+  BST_TRY(ws_check(L, ws, ws_bytes));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const int tl = L.M > L.Q ? L.M : L.Q;
+  float2* tw = reinterpret_cast<float2*>(base + L.off_tw);
+  float2* A = reinterpret_cast<float2*>(base + L.off_a);
+  float2* B = reinterpret_cast<float2*>(base + L.off_b);
+  BST_TRY(spectra(L, g, base, s));
+  bst_cartesian_kernel<<<dim3((L.Q + 255) / 256, L.Q), 256, 0, s>>>(
+      reinterpret_cast<const float2*>(base + L.off_spec), A, L.na, L.M, L.Q, L.nx, L.ny);
+  BST_TRY(launched());
+  bst_rows_inverse_kernel<<<L.Q, kMaxBlock, 0, s>>>(A, tw, L.Q, tl);
+  BST_TRY(launched());
+  bst_transpose_kernel<<<dim3(L.Q / 32, L.Q / 32), dim3(32, 8), 0, s>>>(A, B, L.Q);
+  BST_TRY(launched());
+  bst_rows_inverse_kernel<<<L.Q, kMaxBlock, 0, s>>>(B, tw, L.Q, tl);
+  BST_TRY(launched());
+  bst_extract_kernel<<<dim3((L.nx + 31) / 32, (L.ny + 31) / 32), dim3(32, 8), 0, s>>>(
+      B, img, L.Q, L.ny, L.nx, (float)(1.0 / ((double)L.Q * (double)L.Q)));
+  return launched();
+}
+
+}  // extern "C"

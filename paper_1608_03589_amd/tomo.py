@@ -102,6 +102,44 @@ class TomoSolver:
              C.c_void_p(out.data_ptr()), *self._args())
         return out
 
+    # -- backprojection slice theorem -------------------------------------------
+    def _bst_ws(self):
+        if getattr(self, "_bst", None) is None:
+            n = C.c_size_t()
+            call("tvpd_bst_workspace_size", C.byref(self.geom), C.byref(n))
+            self._bst = (alloc_workspace(n.value, self.device), n.value)
+        return self._bst
+
+    def bst_lengths(self):
+        """(M, Q): the 1D transform length and the Cartesian grid side."""
+        M, Q = C.c_int32(), C.c_int32()
+        call("tvpd_bst_lengths", C.byref(self.geom), C.byref(M), C.byref(Q))
+        return M.value, Q.value
+
+    def bst(self, s: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Fast backprojection by the backprojection slice theorem (approximates
+        (pi / n_angles) A^T s up to the origin rule's constant)."""
+        self._check(s, "sino", (self.n_angles, self.n_det))
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        self._check(out, "out", (self.ny, self.nx))
+        ws, n = self._bst_ws()
+        call("tvpd_bst_backproject", C.byref(self.geom), C.c_void_p(s.data_ptr()),
+             C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), n,
+             C.c_void_p(_stream(self.device)))
+        return out
+
+    def bst_spectra(self, s: torch.Tensor) -> torch.Tensor:
+        """The polar samples K(nu_j) G_k(nu_j), complex64 [n_angles][M]."""
+        self._check(s, "sino", (self.n_angles, self.n_det))
+        M, _ = self.bst_lengths()
+        out = torch.empty((self.n_angles, M), dtype=torch.complex64, device=self.device)
+        ws, n = self._bst_ws()
+        call("tvpd_bst_spectra", C.byref(self.geom), C.c_void_p(s.data_ptr()),
+             C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), n,
+             C.c_void_p(_stream(self.device)))
+        return out
+
     def opnorm_sq(self, iters: int = 50) -> float:
         """||A||^2 by power iteration on A^T A from the constant image."""
         v = C.c_double()

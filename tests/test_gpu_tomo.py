@@ -32,7 +32,7 @@ RTOL = 1e-5
 
 
 def rel(a, b):
-    a = np.asarray(a, np.float64)
+    a = np.asarray(a, np.complex128 if np.iscomplexobj(a) else np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
@@ -248,3 +248,40 @@ def test_fbp_at_full_size_sampled():
     # filter amplifies the noise of g)
     fc = solver.fbp(to_dev(clean.astype(np.float32)), 0.0).cpu().numpy()
     assert np.linalg.norm(fc - img) / np.linalg.norm(img) < 0.15
+
+
+@pytest.mark.parametrize("H,W,na,nd", [(64, 64, 48, 92), (37, 53, 30, 70), (16, 16, 7, 40),
+                                       (200, 120, 100, 300)])
+def test_bst_matches_the_oracle(H, W, na, nd):
+    print(f"case: bst {H}x{W} angles {na} bins {nd}", flush=True)
+    rng = np.random.default_rng(H * 7 + nd)
+    s = rng.normal(size=(na, nd)).astype(np.float32)
+    solver = tv.TomoSolver(H, W, na, nd, DEV)
+    M, Q = solver.bst_lengths()
+    assert (M, Q) == tomo.bst_lengths(H, W, nd)
+    spec = solver.bst_spectra(to_dev(s)).cpu().numpy()
+    spec_ref = tomo.bst_spectra(s.astype(np.float64), M)
+    print(f"spectra rel {rel(spec, spec_ref):.2e}")
+    assert rel(spec, spec_ref) <= RTOL
+    b = solver.bst(to_dev(s)).cpu().numpy()
+    ref = tomo.bst(s.astype(np.float64), H, W)
+    print(f"bst rel {rel(b, ref):.2e} max {maxrel(b, ref):.2e}")
+    assert rel(b, ref) <= RTOL and maxrel(b, ref) <= 2 * RTOL
+
+
+def test_bst_at_full_size_against_the_backprojection():
+    # 2048^2 from 1000 projections: the BST equals B g = dtheta A^T g up to
+    # the origin rule's constant and the bilinear interpolation in angle (at
+    # the highest frequencies 1000 angles are 6.4 Cartesian cells apart; at
+    # 128^2 from 400 angles, one cell, the oracle pins 0.6 %)
+    w, H, W, na, nd = _full_size()
+    print(f"case: bst {H}x{W} angles {na} bins {nd}", flush=True)
+    _, clean, _ = scenes.tomo_scene(H, W, na, nd, w["n_ellipses"], 0.0, w["seed"])
+    g = to_dev(clean.astype(np.float32))
+    solver = tv.TomoSolver(H, W, na, nd, DEV)
+    b = solver.bst(g).cpu().numpy().astype(np.float64)
+    ref = (math.pi / na) * solver.backproject(g).cpu().numpy().astype(np.float64)
+    d = b - ref
+    print(f"constant {d.mean():.4g}, rel after removing it "
+          f"{np.linalg.norm(d - d.mean()) / np.linalg.norm(ref):.3e}")
+    assert np.linalg.norm(d - d.mean()) / np.linalg.norm(ref) < 0.03
