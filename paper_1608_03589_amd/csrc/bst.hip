@@ -14,8 +14,8 @@
 //      centres on the integer grid;
 //   4. 2D inverse DFT (row transforms, a transpose, row transforms), real
 //      part at the pixels, divided by Q^2.
-// The transforms are radix-2 Stockham FFTs in LDS (lengths up to 4096), with
-// twiddles from a float64 table.  Every phase is reduced as an exact integer
+// The transforms are radix-4 Stockham FFTs in LDS (lengths up to 4096; one
+// radix-2 stage for odd powers of two), with twiddles from a float64 table.  Every phase is reduced as an exact integer
 // before its sine and cosine.
 #include <cmath>
 
@@ -46,7 +46,7 @@ BstLayout bst_layout(int ny, int nx, int na, int nd) {
   L.Q = bst_pow2_at_least(2 * (ny > nx ? ny : nx));
   const int tl = L.M > L.Q ? L.M : L.Q;
   L.off_tw = kHeaderBytes;
-  L.off_spec = (size_t)round_up((int64_t)L.off_tw + 8 * (int64_t)(tl / 2), (int64_t)kAlign);
+  L.off_spec = (size_t)round_up((int64_t)L.off_tw + 8 * (int64_t)tl, (int64_t)kAlign);
   L.off_a = (size_t)round_up((int64_t)L.off_spec + 8 * (int64_t)na * L.M, (int64_t)kAlign);
   L.off_b = (size_t)round_up((int64_t)L.off_a + 8 * (int64_t)L.Q * L.Q, (int64_t)kAlign);
   L.bytes = L.off_b + 8 * (size_t)L.Q * (size_t)L.Q;
@@ -59,36 +59,88 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// tw[m] = exp(-2 pi i m / L), m < L/2, from float64.
+// tw[m] = exp(-2 pi i m / L), m < L, from float64.
 __global__ void bst_twiddle_kernel(float2* tw, int L) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= L / 2) return;
+  if (m >= L) return;
   const double a = -2.0 * (double)m / (double)L;
   tw[m] = make_float2((float)cospi(a), (float)sinpi(a));
 }
 
-// Radix-2 Stockham transform of length n (a power of two) in LDS, in place in
-// the sense that the result is left in *x (the buffers are swapped).  SIGN -1:
-// forward (exp(-2 pi i ...)), +1: inverse without the 1/n.  tw: table of
-// length tl/2 (tl a multiple of n).  Every thread of the block takes part.
+// Stockham transform of length n (a power of two, <= 4 * 4 * blockDim.x) in
+// one LDS buffer: one radix-2 stage when log2 n is odd, then radix-4 stages
+// (Govindaraju et al. 2008); each stage reads its inputs into registers, waits
+// for the block, then writes its outputs.  SIGN -1: forward
+// (exp(-2 pi i ...)), +1: inverse without the 1/n.  tw: the full table of
+// length tl (a multiple of n).  Every thread of the block takes part.
+constexpr int kFftPerThread = kBstMaxLen / 4 / kMaxBlock;   // radix-4 butterflies
+
 template <int SIGN>
-__device__ void fft_lds(float2*& x, float2*& y, int n, const float2* tw, int tl) {
-  for (int Ns = 1; Ns < n; Ns <<= 1) {
-    const int stride = tl / (2 * Ns);
-    for (int j = threadIdx.x; j < n / 2; j += blockDim.x) {
-      const int k = j & (Ns - 1);
-      const float2 v0 = x[j];
-      float2 w = tw[k * stride];
-      if (SIGN > 0) w.y = -w.y;
-      const float2 v1 = cmul(x[j + n / 2], w);
-      const int d = ((j - k) << 1) + k;
-      y[d] = make_float2(v0.x + v1.x, v0.y + v1.y);
-      y[d + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
+__device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
+  int Ns = 1;
+  if (__builtin_ctz(n) & 1) {                      // radix-2 stage
+    float2 v[2 * kFftPerThread][2];
+#pragma unroll
+    for (int u = 0; u < 2 * kFftPerThread; ++u) {
+      const int j = threadIdx.x + u * kMaxBlock;
+      if (j < n / 2) {
+        v[u][0] = x[j];
+        v[u][1] = x[j + n / 2];
+      }
     }
     __syncthreads();
-    float2* t = x;
-    x = y;
-    y = t;
+#pragma unroll
+    for (int u = 0; u < 2 * kFftPerThread; ++u) {
+      const int j = threadIdx.x + u * kMaxBlock;
+      if (j < n / 2) {
+        x[2 * j] = make_float2(v[u][0].x + v[u][1].x, v[u][0].y + v[u][1].y);
+        x[2 * j + 1] = make_float2(v[u][0].x - v[u][1].x, v[u][0].y - v[u][1].y);
+      }
+    }
+    __syncthreads();
+    Ns = 2;
+  }
+  for (; Ns < n; Ns <<= 2) {
+    const int stride = tl / (4 * Ns);
+    float2 v[kFftPerThread][4];
+#pragma unroll
+    for (int u = 0; u < kFftPerThread; ++u) {
+      const int j = threadIdx.x + u * kMaxBlock;
+      if (j < n / 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[u][r] = x[j + r * (n / 4)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kFftPerThread; ++u) {
+      const int j = threadIdx.x + u * kMaxBlock;
+      if (j < n / 4) {
+        const int k = j & (Ns - 1);
+        float2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
+        if (SIGN > 0) {
+          w1.y = -w1.y;
+          w2.y = -w2.y;
+          w3.y = -w3.y;
+        }
+        const float2 v0 = v[u][0];
+        const float2 v1 = cmul(v[u][1], w1);
+        const float2 v2 = cmul(v[u][2], w2);
+        const float2 v3 = cmul(v[u][3], w3);
+        const float2 a0 = make_float2(v0.x + v2.x, v0.y + v2.y);
+        const float2 a1 = make_float2(v0.x - v2.x, v0.y - v2.y);
+        const float2 a2 = make_float2(v1.x + v3.x, v1.y + v3.y);
+        const float2 b = make_float2(v1.x - v3.x, v1.y - v3.y);
+        // SIGN i b
+        const float2 ib = SIGN > 0 ? make_float2(-b.y, b.x) : make_float2(b.y, -b.x);
+        const int d = ((j - k) << 2) + k;
+        x[d] = make_float2(a0.x + a2.x, a0.y + a2.y);
+        x[d + Ns] = make_float2(a1.x + ib.x, a1.y + ib.y);
+        x[d + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
+        x[d + 3 * Ns] = make_float2(a1.x - ib.x, a1.y - ib.y);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -97,15 +149,13 @@ __device__ void fft_lds(float2*& x, float2*& y, int n, const float2* tw, int tl)
 __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, float2* spec,
                                                                 const float2* tw, int nd,
                                                                 int M, int tl) {
-  __shared__ float2 buf[2][kBstMaxLen];
-  float2* x = buf[0];
-  float2* y = buf[1];
+  __shared__ float2 x[kBstMaxLen];
   const int k = blockIdx.x;
   const float* gr = g + (int64_t)k * nd;
   for (int i = threadIdx.x; i < M; i += blockDim.x)
     x[i] = make_float2(i < nd ? gr[i] : 0.0f, 0.0f);
   __syncthreads();
-  fft_lds<-1>(x, y, M, tw, tl);
+  fft_lds<-1>(x, M, tw, tl);
   float2* out = spec + (int64_t)k * M;
   for (int m = threadIdx.x; m < M; m += blockDim.x) {
     const int ms = m < M / 2 ? m : m - M;          // signed frequency index
@@ -176,13 +226,11 @@ __global__ void bst_cartesian_kernel(const float2* spec, float2* A, int na, int 
 // Inverse transforms of the rows of a Q x Q array, in place.
 __global__ __launch_bounds__(kMaxBlock) void bst_rows_inverse_kernel(float2* A, const float2* tw,
                                                                      int Q, int tl) {
-  __shared__ float2 buf[2][kBstMaxLen];
-  float2* x = buf[0];
-  float2* y = buf[1];
+  __shared__ float2 x[kBstMaxLen];
   float2* row = A + (int64_t)blockIdx.x * Q;
   for (int i = threadIdx.x; i < Q; i += blockDim.x) x[i] = row[i];
   __syncthreads();
-  fft_lds<+1>(x, y, Q, tw, tl);
+  fft_lds<+1>(x, Q, tw, tl);
   for (int i = threadIdx.x; i < Q; i += blockDim.x) row[i] = x[i];
 }
 
@@ -244,7 +292,7 @@ int ws_check(const BstLayout& L, const void* ws, size_t bytes) {
 int spectra(const BstLayout& L, const float* g, char* base, hipStream_t s) {
   const int tl = L.M > L.Q ? L.M : L.Q;
   float2* tw = reinterpret_cast<float2*>(base + L.off_tw);
-  bst_twiddle_kernel<<<(tl / 2 + 255) / 256, 256, 0, s>>>(tw, tl);
+  bst_twiddle_kernel<<<(tl + 255) / 256, 256, 0, s>>>(tw, tl);
   BST_TRY(launched());
   bst_spectra_kernel<<<L.na, kMaxBlock, 0, s>>>(
       g, reinterpret_cast<float2*>(base + L.off_spec), tw, L.nd, L.M, tl);
