@@ -197,3 +197,35 @@ def test_3d_scene_runs_and_gap_decreases():
                      return_history=True)
     gaps = np.array([h[3] for h in r["history"]])
     assert np.all(gaps >= 0) and gaps[-1] < 0.05 * gaps[0]
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_trajectory_in_the_cosine_basis(theta):
+    """The iterates themselves, not only their limit.  With lam so large that
+    the projection never acts, the dual stays a gradient, p^k = grad psi^k,
+    and -div grad is diagonal in the orthonormal type-II DCT (eigenvalue mu
+    per mode), so every mode of (f, psi) follows the scalar form of the
+    iteration from f^0 = f^{-1} = g, psi^0 = 0:
+        psi' = psi + sigma (f + theta (f - f_prev)),
+        f'   = (f - tau mu psi' + tau g) / (1 + tau).
+    This fixes the extrapolation, the order of the two updates and where each
+    step size enters, none of which the limit depends on."""
+    rng = np.random.default_rng(18)
+    H, W = 9, 13
+    g = rng.normal(size=(H, W))
+    tau, sigma = 0.3, 0.25
+    mu = (4 * np.sin(np.pi * np.arange(H) / (2 * H)) ** 2)[:, None] + \
+         (4 * np.sin(np.pi * np.arange(W) / (2 * W)) ** 2)[None, :]
+    G = pins.grad_matrix((H, W))
+    gh = sfft.dctn(g, norm="ortho")
+    fh, fh_prev, psih = gh.copy(), gh.copy(), np.zeros_like(gh)
+    f, f_prev, p = oracle.init_state(g)
+    for _ in range(10):
+        psih = psih + sigma * (fh + theta * (fh - fh_prev))
+        fh_prev, fh = fh, (fh - tau * mu * psih + tau * gh) / (1 + tau)
+        f_new, p = oracle.pdhg_iteration(f, f_prev, p, g, 1e30, tau, sigma, theta)
+        f_prev, f = f, f_new
+        np.testing.assert_allclose(f, sfft.idctn(fh, norm="ortho"), rtol=0, atol=1e-12)
+        psi = sfft.idctn(psih, norm="ortho")
+        np.testing.assert_allclose(p, (G @ psi.ravel()).reshape(2, H, W),
+                                   rtol=0, atol=1e-12)

@@ -134,6 +134,67 @@ def test_first_iteration_closed_form():
         assert np.all(st["p"] == 0)
 
 
+@pytest.mark.parametrize("reg,theta", [("tv", 1.0), ("tv", 0.5),
+                                       ("tikhonov", 1.0), ("tikhonov", 0.5)])
+def test_trajectory_with_two_orthogonal_projections(reg, theta):
+    """The iterates themselves, not only their limit.  With the angles 0 and
+    90 degrees and the bins on the pixel centres (n_det = H = W = N), A f is
+    the column sums and the row sums of f.  In orthonormal DCT bases (2D for
+    the image, 1D along each projection) A has only the entries sqrt(N), from
+    image mode (0, k) to mode k of projection 0 and from (k, 0) to mode k of
+    projection 1, and -div grad is diagonal (eigenvalue mu).  With lam so
+    large that the TV projection never acts, p = grad psi, and the iteration
+    runs mode by mode from a warm start f^0 = f^{-1}, r^0 = 0, psi^0 = 0:
+        fbar = f + theta (f - f_prev)
+        r'   = (r + sigma_r (C fbar - g)) / (1 + sigma_r)
+        psi' = psi + sigma_p fbar,  f' = f - tau (C^T r' + mu psi')   (TV)
+        f'   = (f - tau C^T r') / (1 + tau lam)                       (Tikhonov)
+    """
+    import scipy.fft as sfft
+    from pins import grad_matrix
+    N = 8
+    f0 = rng(30).normal(size=(N, N))
+    g = rng(31).normal(size=(2, N))
+    tau, sr, sp = 0.2, 0.3, 0.4
+    lam = 1e30 if reg == "tv" else 0.7
+    k = np.arange(N)
+    lap1 = 4 * np.sin(np.pi * k / (2 * N)) ** 2
+    mu = lap1[:, None] + lap1[None, :]
+    c = math.sqrt(N)
+
+    def C(fh):
+        return np.stack([c * fh[0, :], c * fh[:, 0]])
+
+    def Ct(rh):
+        out = np.zeros((N, N))
+        out[0, :] += c * rh[0]
+        out[:, 0] += c * rh[1]
+        return out
+
+    gh = sfft.dct(g, norm="ortho", axis=1)
+    fh = sfft.dctn(f0, norm="ortho")
+    fh_prev, rh, psih = fh.copy(), np.zeros((2, N)), np.zeros((N, N))
+    st = tomo.init_state(N, N, 2, N, f0)
+    G = grad_matrix((N, N))
+    for _ in range(8):
+        fbar = fh + theta * (fh - fh_prev)
+        rh = (rh + sr * (C(fbar) - gh)) / (1 + sr)
+        if reg == "tv":
+            psih = psih + sp * fbar
+            fnew = fh - tau * (Ct(rh) + mu * psih)
+        else:
+            fnew = (fh - tau * Ct(rh)) / (1 + tau * lam)
+        fh_prev, fh = fh, fnew
+        st = tomo.iteration(st, g, lam, tau, sr, sp, reg, theta)
+        np.testing.assert_allclose(st["f"], sfft.idctn(fh, norm="ortho"),
+                                   rtol=0, atol=1e-12)
+        np.testing.assert_allclose(st["r"], sfft.idct(rh, norm="ortho", axis=1),
+                                   rtol=0, atol=1e-12)
+        psi = sfft.idctn(psih, norm="ortho")
+        np.testing.assert_allclose(st["p"], (G @ psi.ravel()).reshape(2, N, N),
+                                   rtol=0, atol=1e-12)
+
+
 def test_tikhonov_limit_solves_the_normal_equation():
     H, W, na, nd = 10, 8, 12, 16
     img, _, g = scenes.tomo_scene(H, W, na, nd, n_ellipses=4, noise=0.05, seed=8)
@@ -283,6 +344,26 @@ def test_bst_interpolation_is_exact_for_radial_affine_spectra():
     ok = rho <= 0.5 - 1.0 / M
     np.testing.assert_allclose(F[ok].real, 2.0 + 3.0 * rho[ok], rtol=1e-12, atol=1e-12)
     assert np.all(F[rho > 0.5] == 0)
+
+
+def test_bst_interpolation_is_exact_for_bilinear_spectra():
+    # (1 + theta)(2 + 3 |nu|) is bilinear in (theta, nu) on every cell of the
+    # polar grid (|nu| bends only at the node nu = 0), so its Cartesian
+    # samples are exact everywhere except in the last angular cell, where
+    # theta wraps from pi back to 0 with nu -> -nu
+    na, M, Q = 12, 64, 64
+    th = tomo.angles(na)
+    nu = (np.arange(M) - M // 2) / M
+    P = ((1.0 + th)[:, None] * (2.0 + 3.0 * np.abs(nu))[None, :]).astype(complex)
+    F = tomo.bst_cartesian(P, Q)
+    f = (np.arange(Q) - Q // 2) / Q
+    u, v = np.meshgrid(f, f)
+    rho = np.hypot(u, v)
+    theta = np.mod(np.arctan2(v, u), np.pi)
+    ok = (rho <= 0.5 - 1.0 / M) & (theta <= th[-1])
+    assert ok.sum() > 0.6 * Q * Q
+    np.testing.assert_allclose(F[ok].real, (1 + theta[ok]) * (2 + 3 * rho[ok]),
+                               rtol=1e-12, atol=1e-12)
 
 
 def test_bst_equals_the_backprojection_up_to_the_origin_constant():
