@@ -322,7 +322,7 @@ int tvpd_set_fused_adjoint(int32_t on);
  * Geometry, in pixel units with detector spacing 1: image f is [ny][nx]
  * (dense, row-major), pixel (a, b) centred at x = b + 1/2 - nx/2 (along
  * columns), y = a + 1/2 - ny/2 (along rows); angles theta_k = k pi / n_angles
- * (k < n_angles, the angle mesh of Section 4); bins t_i = i + 1/2 - n_det/2;
+ * (k < n_angles, the angle mesh of Section 5); bins t_i = i + 1/2 - n_det/2;
  * a sinogram is [n_angles][n_det] (dense, t fastest).
  *
  *   A f    [k][i] = sum_ab f[a][b] max(0, 1 - |x cos theta_k + y sin theta_k - t_i|)
@@ -424,7 +424,7 @@ int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
 int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out,
              void* ws, size_t ws_bytes, void* stream);
 
-/* Fast backprojection by the backprojection slice theorem (Section 4, eq.
+/* Fast backprojection by the backprojection slice theorem (Section 3, eq.
  * bst; the algorithm of Section 5).  In the cycles convention the 2D Fourier
  * transform of B g on the line at angle theta is G(nu, theta) / |nu|, G the 1D
  * transform of the projection; for sampled data B = (pi / n_angles) A^T.

@@ -14,7 +14,7 @@ Discretisation (pixel units, detector spacing 1):
         X_ab = (b + 1/2 - W/2,  a + 1/2 - H/2)
     relative to the rotation centre (x along columns, y along rows);
   * angles theta_k = k pi / n_angles, k = 0 .. n_angles-1 (the angle mesh of
-    the paper's table of symbols, Section 4), xi_k = (cos theta_k, sin theta_k)
+    the paper's table of symbols, Section 5), xi_k = (cos theta_k, sin theta_k)
     as in Section 1 eq. L;
   * detector bins t_i = i + 1/2 - n_det / 2, i = 0 .. n_det-1.
 
@@ -60,7 +60,7 @@ REGS = ("tv", "tikhonov")
 # --------------------------------------------------------------------------
 
 def angles(n_angles: int) -> np.ndarray:
-    """theta_k = k pi / n_angles (Section 4, table of symbols)."""
+    """theta_k = k pi / n_angles (Section 5, table of symbols)."""
     return np.arange(n_angles, dtype=np.float64) * (math.pi / n_angles)
 
 
@@ -263,7 +263,7 @@ def fbp(s: np.ndarray, H: int, W: int, lam: float) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Backprojection slice theorem (BST, Section 4, eq. bst, and the algorithm of
+# Backprojection slice theorem (BST, Section 3, eq. bst, and the algorithm of
 # Section 5): the 2D Fourier transform of B g on the line through the origin
 # at angle theta equals the 1D Fourier transform of the projection at theta,
 # divided by |nu|.  In the cycles convention (transforms with exp(-2 pi i nu x))

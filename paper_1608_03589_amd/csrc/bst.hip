@@ -1,5 +1,5 @@
 // Backprojection by the backprojection slice theorem (BST): the paper's fast
-// backprojection (Section 4, eq. bst; algorithm of Section 5), on the
+// backprojection (Section 3, eq. bst; algorithm of Section 5), on the
 // geometry of the tomographic operators (tomo.h).
 //
 // In the cycles convention the theorem reads F[B g](nu xi_theta) =

@@ -4,7 +4,7 @@ The projection and the backprojection are pinned by what the geometry fixes
 exactly (adjointness, mass and first moment of every projection, line sums at
 0 and 90 degrees, the half-turn and transpose symmetries), against the
 independent line integrals of an ellipse phantom (Section 1 eq. P_theta), and
-against the backprojection of a point source (Section 5, Example I: 1/|x - a|
+against the backprojection of a point source (Section 4, Example I: 1/|x - a|
 once the printed form's sine and cosine are put back in place).  The
 iteration is pinned by its first step in closed form, by the normal equation
 of the Tikhonov problem (Section 6, eq. neq2), by the constant solution for a
