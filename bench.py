@@ -25,8 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-BYTES_PER_PIXEL_ITER = 32      # 20 B read + 12 B written per pixel and sweep
-PASS_BYTES_PER_PIXEL = 36      # a pass of n >= 2 iterations: 20 B read + 16 B written
+BYTES_PER_PIXEL_ITER = 32      # one iteration as defined: reads f^k, f^{k-1}, p^k (2), g,
+                               # writes f^{k+1}, p^{k+1} (2)
+PASS_BYTES_PER_PIXEL = 28      # a launch of n iterations: reads f^k, p^k (2), g, writes
+                               # f^{k+n}, p^{k+n} (2) (fbar^k is formed from f^k, g, p^k)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_xs5_denoise4096_traffic.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1608_03589_amd", "csrc", f)
                for f in ("kernels2d.hip", "tile2d.h", "tile2d_xs.h", "pointwise.h")]
@@ -79,10 +81,9 @@ def pass_schedule(iters, check_every, depth):
 
 
 def kernel_name(kernels, passes):
-    names = {1: "sweep2d_kernel", 2: "sweep2d_x2_kernel"}
     parts = []
     for n in kernels:
-        nm = names.get(n, f"sweep2d_xs_kernel<{n}>")
+        nm = f"sweep2d_xs_kernel<{n}>"
         parts.append(f"{nm} ({n} iteration{'s' if n > 1 else ''} per launch, "
                      f"{passes.count(n)} launches per solve)")
     return "; ".join(parts) + "; the launch at each 10th iteration also reduces the gap"
@@ -485,10 +486,9 @@ def main():
     launch_s = ms_total * 1e-3 / launches
     alg_bytes = BYTES_PER_PIXEL_ITER * pix * its_per_launch
     achieved = alg_bytes / launch_s / 1e9
-    # what a launch itself must move: reads f^k, f^{k-1}, p^k (2), g, writes
-    # f^{k+n-1}, f^{k+n}, p^{k+n} (2); 32 B for a single iteration
-    pass_bytes = sum((PASS_BYTES_PER_PIXEL if n > 1 else BYTES_PER_PIXEL_ITER) * pix
-                     for n in passes) / len(passes)
+    # what a launch itself must move: reads f^k, p^k (2), g, writes f^{k+n},
+    # p^{k+n} (2), whatever n
+    pass_bytes = PASS_BYTES_PER_PIXEL * pix
     pass_achieved = pass_bytes / launch_s / 1e9
     kernels = sorted(set(passes))
     traffic = read_traffic(pix, tv.get_tile((H, W))) if kernels == [depth] else None
@@ -552,9 +552,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "basis": ("one-pass algorithmic bytes, 32 B per pixel-iteration; "
+            "basis": ("one-iteration algorithmic bytes, 32 B per pixel-iteration; "
                       "a pass of n iterations keeps the n-1 intermediate iterates "
-                      "on chip, so this figure can exceed the peak"),
+                      "on chip and forms fbar^k from f^k, g and p^k (28 B per "
+                      "pixel and launch), so this figure can exceed the peak"),
             "pass_algorithmic_bytes_per_launch": pass_bytes,
             "pass_achieved_GBs": pass_achieved,
             "pass_frac": pass_achieved / HBM_PEAK_GBS,

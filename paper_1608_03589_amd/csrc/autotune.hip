@@ -78,7 +78,7 @@ Tile2D default_tile2d(const Layout& L) {
            (ntx * ((L.ny + th - 1) / th) + t.wpb - 1) / t.wpb > max_blocks)
       ++th;
   } else {
-    const int64_t ntx = (L.nx + kStripCols - 1) / kStripCols;
+    const int64_t ntx = (L.nx + xs_owned(depth) - 1) / xs_owned(depth);
     const int64_t target_waves = 4LL * cus;
     th = (ntx * L.ny + target_waves - 1) / target_waves;
     if (th < 8) th = 8;

@@ -63,10 +63,10 @@ struct BatchArgs {
 constexpr int kBatchMaxPass = 5;
 
 // Batch tiles: 256-column strips that own their middle kBatchStrip columns
-// (margins of kBatchMargin >= every pass length, tile2d_xs.h).
+// (margins of kBatchMargin > every pass length, tile2d_xs.h).
 constexpr int kBatchMargin = 8;
 constexpr int kBatchStrip = kStripCols - 2 * kBatchMargin;
-static_assert(kBatchMargin >= kMaxPass, "batch strip margin");
+static_assert(kBatchMargin >= kMaxPass + 1, "batch strip margin");
 
 // Iterations of the pass that starts at iteration k: at most `depth`, never
 // past max_iter, and ending before the next gap check (a check falls on the

@@ -83,8 +83,6 @@ __device__ __forceinline__ void tile_pass(const BatchArgs& a,
   const int64_t PL = D.plane;
   TileCtxS c;
   c.F = base + plain_f(k) * PL;
-  c.M = base + plain_f(k - 1) * PL;
-  c.FL = base + plain_f(k + N - 1) * PL;
   c.FN = base + plain_f(k + N) * PL;
   c.PX = base + plain_p(k) * PL;
   c.PY = c.PX + PL;
@@ -101,7 +99,8 @@ __device__ __forceinline__ void tile_pass(const BatchArgs& a,
   c.tau = D.tau;
   c.sig = D.sigma;
   c.th = D.theta;
-  sweep_tile_xs<N, kBatchMargin, CHECK>(c, sg, sp);
+  c.tau_prev = D.tau;   // every step of an image has its tau (at k = 0 any value)
+  sweep_tile_xs<N, kBatchMargin, CHECK, false>(c, sg, sp);
 }
 
 template <bool CHECK>
@@ -289,8 +288,7 @@ __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
     const int x = (int)(e - (int64_t)y * D.pitch);
     const float v = (x < D.nx) ? gi[(int64_t)y * D.nx + x] : 0.0f;
     for (int s = 0; s < kPlainPlanes2D; ++s) base[s * PL + e] = 0.0f;
-    base[plain_f(0) * PL + e] = v;   // f^0
-    base[plain_f(-1) * PL + e] = v;  // f^{-1}
+    base[plain_f(0) * PL + e] = v;   // f^0 (f^{-1} = f^0 is implied)
     base[kPlainG * PL + e] = v;      // g
   }
 }

@@ -298,7 +298,6 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
   if (!ws) return TVPD_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
   if (ws_bytes < L.bytes) return TVPD_ERR_WORKSPACE;
-  // grid of the driver: the persistent one is capped by co-residency
   // grid of the driver: about two blocks per CU (the persistent one is also
   // capped by co-residency); every block sweeps tiles grid-stride
   int cus = 0;

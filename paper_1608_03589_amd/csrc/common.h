@@ -16,8 +16,10 @@ constexpr size_t kHeaderBytes = 4096;   // state header at the workspace start
 constexpr size_t kAlign = 256;
 
 // Solver state kept in device memory at the start of a workspace.  Kernels
-// read k to find the ring slots of f^k, f^{k-1}, f^{k+1}, p^k, p^{k+1}; the
-// last block of every sweep advances k (or freezes it on convergence).
+// read k to find the ring slots of the iterates they read and write; the
+// last block of every sweep advances k (or freezes it on convergence) and
+// records the step tau of the iterations it made (the 2D sweeps form the
+// extrapolation of f^k from it).
 struct DevState {
   int32_t k;             // index of the current iterate
   int32_t k_end;         // sweeps do nothing once k >= k_end
@@ -29,7 +31,9 @@ struct DevState {
   int32_t flags;         // device-side error bits
   double P, D, gap;      // energies of the last evaluated pair
   double tol;            // relative gap tolerance (< 0: never stop)
-  double pad[8];
+  float tau_prev;        // step that produced f^k (0 after initialisation)
+  int32_t pad0;
+  double pad[7];
 };
 static_assert(sizeof(DevState) <= 256, "state header");
 
@@ -48,23 +52,23 @@ struct Layout {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Longest pass (iterations per launch) of the 2D sweep.  Passes of n >= 3
-// iterations run on overlapping strips: a wave loads 256 columns and owns
-// the middle xs_owned(n) of them (margins of xs_margin(n) >= n columns on
-// each side, a multiple of 4 for aligned float4 access).
+// Longest pass (iterations per launch) of the 2D sweep.  Passes run on
+// overlapping strips: a wave loads 256 columns and owns the middle
+// xs_owned(n) of them (margins of xs_margin(n) >= n + 1 columns on each
+// side, a multiple of 4 for aligned float4 access).
 constexpr int kMaxPass = 6;
-__host__ __device__ constexpr int xs_margin(int n) { return n <= 4 ? 4 : 8; }
+__host__ __device__ constexpr int xs_margin(int n) { return n <= 3 ? 4 : 8; }
 __host__ __device__ constexpr int xs_owned(int n) {
   return kStripCols - 2 * xs_margin(n);
 }
 constexpr int kXsOwnedMin = kStripCols - 2 * xs_margin(kMaxPass);
 
-// Plane block of the plain 2D solver: f^k in slot k mod 6 (planes 0..5),
-// p^k in slot k mod 5 (planes 6 + 2 (k mod 5), x then y), g in plane 16.  A
-// pass of n <= kMaxPass iterations reads f^k, f^{k-1}, p^k and writes
-// f^{k+n-1}, f^{k+n}, p^{k+n}: with rings of kMaxPass + 2 and kMaxPass + 1
-// slots it never overwrites an input that another tile still reads.
-constexpr int kRingF = kMaxPass + 2;
+// Plane block of the plain 2D solver: f^k in slot k mod 7 (planes 0..6),
+// p^k in slot k mod 7 (planes 7 + 2 (k mod 7), x then y), g in plane 21.  A
+// pass of n <= kMaxPass iterations reads f^k, p^k and writes f^{k+n},
+// p^{k+n}: with rings of kMaxPass + 1 slots it never overwrites an input
+// that another tile still reads.
+constexpr int kRingF = kMaxPass + 1;
 constexpr int kRingP = kMaxPass + 1;
 constexpr int kPlainPlanes2D = kRingF + 2 * kRingP + 1;
 constexpr int kPlainG = kRingF + 2 * kRingP;
@@ -131,8 +135,8 @@ struct Sweep3DArgs {
 // Host launchers (kernels2d.hip).
 hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
                          hipStream_t s);
-// One launch of n iterations (n = 1 .. kMaxPass; with n >= 2 the temporally
-// blocked kernels).  Gap check, if any, on the first iteration.
+// One launch of n iterations (n = 1 .. kMaxPass, temporally blocked for
+// n >= 2).  Gap check, if any, on the first iteration.
 hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
                           const tvpd_coeffs& c, bool with_gap, int n,
                           void* ws, hipStream_t s);

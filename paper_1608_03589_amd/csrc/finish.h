@@ -8,13 +8,14 @@
 namespace tvpd {
 namespace dev {
 
-// Completion of a sweep: the last block to finish advances k, or on a gap
-// check reduces the per-block partials (fixed order, float64), records the
-// energies and either freezes k (converged) or advances it.
+// Completion of a sweep: the last block to finish advances k and records
+// the step tau of the iterations made, or on a gap check reduces the
+// per-block partials (fixed order, float64), records the energies and
+// either freezes k (converged) or advances it.
 template <bool GAP, int STEP>
 __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
                                              int k, double acc_gap,
-                                             double acc_P) {
+                                             double acc_P, float tau) {
   __shared__ double red[2][kMaxBlock / kWave];
   __shared__ int s_last;
   const unsigned nb = gridDim.x;
@@ -36,7 +37,10 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
   if (!s_last) return;
   __threadfence();
   if constexpr (!GAP) {
-    if (threadIdx.x == 0) st->k = k + STEP;
+    if (threadIdx.x == 0) {
+      st->k = k + STEP;
+      st->tau_prev = tau;
+    }
   } else {
     double sg = 0.0, sp = 0.0;
     for (unsigned i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -55,6 +59,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
         st->iters = k;
       } else {
         st->k = k + STEP;
+        st->tau_prev = tau;
       }
     }
   }

@@ -1,14 +1,12 @@
-// Plain-solver kernels of the 2D path: the fused sweep (one launch = one
-// iteration over the whole image, see tile2d.h), initialisation, read-out and
-// the standalone energy/gap evaluation.
+// Plain-solver kernels of the 2D path: the fused sweep (one launch = a pass
+// of 1 .. kMaxPass iterations over the whole image, see tile2d_xs.h),
+// initialisation, read-out and the standalone energy/gap evaluation.
 //
-// Each sweep launch reads 20 bytes per pixel (f^k, f^{k-1}, p^k x2, g) and
-// writes 12 (f^{k+1}, p^{k+1} x2).  The last block to finish advances the
+// A pass of n iterations reads 16 bytes per pixel (f^k, p^k x2, g) and
+// writes 12 (f^{k+n}, p^{k+n} x2).  The last block to finish advances the
 // iteration counter kept in device memory, or on a gap check reduces the
 // per-block partials in a fixed order and applies the stopping rule.
 #include "finish.h"
-#include "tile2d.h"
-#include "tile2d_x2.h"
 #include "tile2d_xs.h"
 
 namespace tvpd {
@@ -16,112 +14,18 @@ namespace {
 
 using namespace dev;
 
-template <bool GAP>
-__global__ __launch_bounds__(kMaxBlock) void sweep2d_kernel(Sweep2DArgs a) {
-  DevState* st = a.st;
-  const int k = st->k;
-  if (st->converged || k >= st->k_end) return;
-
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  // Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
-  // contiguous run of tiles so that vertically adjacent bands (which share
-  // halo rows) meet in the same L2.
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
-  const int bt = xcd * q8 + min(xcd, r8) + (b >> 3);
-  const int wt = bt * a.wpb + wave;
-
-  double acc_gap = 0.0, acc_P = 0.0;
-  if (wt < a.ntiles) {
-    TileCtx c;
-    const int64_t PL = a.plane;
-    c.fk = a.base + plain_f(k) * PL;
-    c.fkm = a.base + plain_f(k - 1) * PL;
-    c.fn = a.base + plain_f(k + 1) * PL;
-    c.pxk = a.base + plain_p(k) * PL;
-    c.pyk = c.pxk + PL;
-    c.pxn = a.base + plain_p(k + 1) * PL;
-    c.pyn = c.pxn + PL;
-    c.g = a.base + kPlainG * PL;
-    int tx, ty;
-    if (a.order == 0) {
-      ty = wt / a.ntx;
-      tx = wt - ty * a.ntx;
-    } else {
-      tx = wt / a.nty;
-      ty = wt - tx * a.nty;
-    }
-    c.ny = a.ny;
-    c.nx = a.nx;
-    c.pitch = a.pitch;
-    c.x0 = tx * kStripCols;
-    c.y0 = ty * a.th;
-    c.y1 = min(c.y0 + a.th, a.ny);
-    c.lam = a.lam;
-    c.tau = a.tau;
-    c.sig = a.sigma;
-    c.th = a.theta;
-    sweep_tile<GAP>(c, acc_gap, acc_P);
-  }
-  finish_sweep<GAP, 1>(st, a.partials, k, acc_gap, acc_P);
-}
-
-// Two iterations k -> k+2 per launch (tile2d_x2.h); the gap, when asked
-// for, is that of (f^k, p^k).
-template <bool GAP>
-__global__ __launch_bounds__(kMaxBlock) void sweep2d_x2_kernel(Sweep2DArgs a) {
-  DevState* st = a.st;
-  const int k = st->k;
-  if (st->converged || k + 2 > st->k_end) return;
-  const int wave = threadIdx.x / kWave;
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
-  const int bt = xcd * q8 + min(xcd, r8) + (b >> 3);
-  const int wt = bt * a.wpb + wave;
-  double acc_gap = 0.0, acc_P = 0.0;
-  if (wt < a.ntiles) {
-    TileCtx2 c;
-    const int64_t PL = a.plane;
-    c.F = a.base + plain_f(k) * PL;
-    c.M = a.base + plain_f(k - 1) * PL;
-    c.FA = a.base + plain_f(k + 1) * PL;
-    c.FB = a.base + plain_f(k + 2) * PL;
-    c.PX = a.base + plain_p(k) * PL;
-    c.PY = c.PX + PL;
-    c.BX = a.base + plain_p(k + 2) * PL;
-    c.BY = c.BX + PL;
-    c.G = a.base + kPlainG * PL;
-    int tx, ty;
-    if (a.order == 0) {
-      ty = wt / a.ntx;
-      tx = wt - ty * a.ntx;
-    } else {
-      tx = wt / a.nty;
-      ty = wt - tx * a.nty;
-    }
-    c.ny = a.ny;
-    c.nx = a.nx;
-    c.pitch = a.pitch;
-    c.x0 = tx * kStripCols;
-    c.y0 = ty * a.th;
-    c.y1 = min(c.y0 + a.th, a.ny);
-    c.lam = a.lam;
-    c.tau = a.tau;
-    c.sig = a.sigma;
-    c.th = a.theta;
-    sweep_tile_x2<GAP>(c, acc_gap, acc_P);
-  }
-  finish_sweep<GAP, 2>(st, a.partials, k, acc_gap, acc_P);
-}
-
-// S iterations per launch on overlapping 248-column strips (tile2d_xs.h).
+// S iterations per launch on overlapping strips of xs_owned(S) owned
+// columns (tile2d_xs.h).
 template <int S, bool GAP>
 __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
   DevState* st = a.st;
   const int k = st->k;
   if (st->converged || k + S > st->k_end) return;
+  const float tau_prev = st->tau_prev;
   const int wave = threadIdx.x / kWave;
+  // Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
+  // contiguous run of tiles so that vertically adjacent bands (which share
+  // halo rows) meet in the same L2.
   const int nb = gridDim.x, b = blockIdx.x;
   const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
   const int bt = xcd * q8 + min(xcd, r8) + (b >> 3);
@@ -131,8 +35,6 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
     TileCtxS c;
     const int64_t PL = a.plane;
     c.F = a.base + plain_f(k) * PL;
-    c.M = a.base + plain_f(k - 1) * PL;
-    c.FL = a.base + plain_f(k + S - 1) * PL;
     c.FN = a.base + plain_f(k + S) * PL;
     c.PX = a.base + plain_p(k) * PL;
     c.PY = c.PX + PL;
@@ -157,9 +59,10 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
     c.tau = a.tau;
     c.sig = a.sigma;
     c.th = a.theta;
+    c.tau_prev = tau_prev;
     sweep_tile_xs<S, xs_margin(S), GAP>(c, acc_gap, acc_P);
   }
-  finish_sweep<GAP, S>(st, a.partials, k, acc_gap, acc_P);
+  finish_sweep<GAP, S>(st, a.partials, k, acc_gap, acc_P, a.tau);
 }
 
 __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
@@ -172,8 +75,7 @@ __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
     const int x = (int)(i - (int64_t)y * pitch);
     const float v = (x < nx) ? g[(int64_t)y * nx + x] : 0.0f;
     for (int s = 0; s < kPlainPlanes2D; ++s) base[s * plane + i] = 0.0f;
-    base[plain_f(0) * plane + i] = v;   // f^0
-    base[plain_f(-1) * plane + i] = v;  // f^{-1}
+    base[plain_f(0) * plane + i] = v;   // f^0 (f^{-1} = f^0 is implied)
     base[kPlainG * plane + i] = v;      // g (p^0 = 0)
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -186,6 +88,7 @@ __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
     st->flags = 0;
     st->P = st->D = st->gap = 0.0;
     st->tol = -1.0;
+    st->tau_prev = 0.0f;
     SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
                                                kSyncOffset);
     for (int i = 0; i < kSyncGroups; ++i) sa->sub[i].v = 0;
@@ -311,8 +214,8 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   a.th = t.th;
   a.wpb = t.wpb;
   a.order = t.order;
-  // the blocked kernels of depth >= 3 run on overlapping strips
-  const int strip = n >= 3 ? xs_owned(n) : kStripCols;
+  // every pass runs on overlapping strips of xs_owned(n) owned columns
+  const int strip = xs_owned(n);
   a.ntx = (L.nx + strip - 1) / strip;
   a.nty = (L.ny + t.th - 1) / t.th;
   a.ntiles = a.ntx * a.nty;
@@ -327,8 +230,8 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   const dim3 grid(nb), block(t.wpb * kWave);
   if (with_gap) {
     switch (n) {
-      case 1: hipLaunchKernelGGL((sweep2d_kernel<true>), grid, block, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((sweep2d_x2_kernel<true>), grid, block, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((sweep2d_xs_kernel<1, true>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((sweep2d_xs_kernel<2, true>), grid, block, 0, s, a); break;
       case 3: hipLaunchKernelGGL((sweep2d_xs_kernel<3, true>), grid, block, 0, s, a); break;
       case 4: hipLaunchKernelGGL((sweep2d_xs_kernel<4, true>), grid, block, 0, s, a); break;
       case 5: hipLaunchKernelGGL((sweep2d_xs_kernel<5, true>), grid, block, 0, s, a); break;
@@ -336,8 +239,8 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
     }
   } else {
     switch (n) {
-      case 1: hipLaunchKernelGGL((sweep2d_kernel<false>), grid, block, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((sweep2d_x2_kernel<false>), grid, block, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((sweep2d_xs_kernel<1, false>), grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((sweep2d_xs_kernel<2, false>), grid, block, 0, s, a); break;
       case 3: hipLaunchKernelGGL((sweep2d_xs_kernel<3, false>), grid, block, 0, s, a); break;
       case 4: hipLaunchKernelGGL((sweep2d_xs_kernel<4, false>), grid, block, 0, s, a); break;
       case 5: hipLaunchKernelGGL((sweep2d_xs_kernel<5, false>), grid, block, 0, s, a); break;
@@ -348,7 +251,7 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
 }
 
 int sweep2d_blocks(const Layout& L, const Tile2D& t, int n) {
-  const int strip = n >= 3 ? xs_owned(n) : kStripCols;
+  const int strip = xs_owned(n);
   const int ntx = (L.nx + strip - 1) / strip;
   const int nty = (L.ny + t.th - 1) / t.th;
   const int nt = ntx * nty;

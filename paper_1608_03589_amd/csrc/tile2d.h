@@ -1,6 +1,8 @@
 // Device code of the fused 2D sweep over one tile (a 256-column strip by a
-// band of rows), shared by the plain and the batched kernels so that both
-// perform bit-identical per-pixel arithmetic.
+// band of rows) for the unrolled solver's forward step, which keeps every
+// iterate and forms the extrapolation from the stored f^{k-1} (the plain and
+// the batched solvers use tile2d_xs.h), and the per-row helpers that the
+// other tiles share.
 //
 // One call performs iteration k -> k+1 of the primal-dual method on the
 // tile's rows (the regularised problem of the paper's Section 6, eq. opt,

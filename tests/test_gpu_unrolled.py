@@ -184,7 +184,9 @@ def test_checkpoint_interval_is_bitwise_neutral(ndim):
 
 def test_forward_equals_plain_solver():
     """K iterations with constant coefficients equal the plain solver's
-    first K iterations bit for bit (the same fused sweep)."""
+    first K iterations up to rounding: the unrolled forward forms the
+    extrapolation from the stored f^{k-1}, the plain solver from f^k, g and
+    p^k (the same value in exact arithmetic)."""
     _, g = batch2d(1, 96, 300, seed=720)
     K = 9
     s = 1.0 / math.sqrt(8.0)
@@ -195,7 +197,8 @@ def test_forward_equals_plain_solver():
     fp, _ = p.solve(torch.from_numpy(g[0]).to(DEV), lam=float(c[0, 0]),
                     tau=float(c[0, 1]), sigma=float(c[0, 2]), max_iter=K,
                     check_every=0, gap_tol=-1.0)
-    assert torch.equal(f[0], fp)
+    err = float(torch.linalg.norm(f[0] - fp) / torch.linalg.norm(fp))
+    assert err < 1e-6, err
 
 
 def test_autograd_function_and_crop_fd():
