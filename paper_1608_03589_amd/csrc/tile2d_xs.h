@@ -238,7 +238,7 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
 
   // The histories start with row tb (its fbar^k lacks p_y of the row above:
   // such first-row values only feed rows outside the band); rows are
-  // prefetched one step ahead into two buffers used alternately.
+  // prefetched two steps ahead into three buffers used in turn.
   {
     XsLoad Z;
     load(tb, Z);
@@ -248,17 +248,21 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
     gh[0] = Z.g;
     fbar_loaded(std::true_type{}, tb, Z, zero4(), fbh[0]);
   }
-  XsLoad X, Y;
+  XsLoad X, Y, Z;
   load(tb + 1, X);
+  load(tb + 2, Y);
   auto run = [&](auto edge) {
     int t = tb;
-    for (; t + 1 <= te; t += 2) {
-      load(t + 2, Y);
+    for (; t + 2 <= te; t += 3) {
+      load(t + 3, Z);
       step(edge, t, X);
-      load(t + 3, X);
+      load(t + 4, X);
       step(edge, t + 1, Y);
+      load(t + 5, Y);
+      step(edge, t + 2, Z);
     }
     if (t <= te) step(edge, t, X);
+    if (t + 1 <= te) step(edge, t + 1, Y);
   };
   if constexpr (SPLIT) {
     if (interior)
@@ -268,13 +272,16 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
   } else {
     // the same loop written out: inside a lambda it costs registers
     int t = tb;
-    for (; t + 1 <= te; t += 2) {
-      load(t + 2, Y);
+    for (; t + 2 <= te; t += 3) {
+      load(t + 3, Z);
       step(std::true_type{}, t, X);
-      load(t + 3, X);
+      load(t + 4, X);
       step(std::true_type{}, t + 1, Y);
+      load(t + 5, Y);
+      step(std::true_type{}, t + 2, Z);
     }
     if (t <= te) step(std::true_type{}, t, X);
+    if (t + 1 <= te) step(std::true_type{}, t + 1, Y);
   }
 }
 
