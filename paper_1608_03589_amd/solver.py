@@ -196,8 +196,9 @@ def get_pass_depth() -> int:
 
 
 def set_blocking(on: bool):
-    """Two-iteration passes (temporal blocking) for the plain and batched 2D
-    solvers on or off, process-wide; the iterates are the same either way."""
+    """Temporal blocking of the plain and batched 2D solvers on (passes of
+    up to the default depth) or off (one iteration per launch), process-wide;
+    the iterates are the same either way."""
     call("tvpd_set_blocking", 1 if on else 0)
 
 

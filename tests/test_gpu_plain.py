@@ -116,6 +116,40 @@ def test_resume_and_graph_replay_bitwise():
     assert r1.iters == r0.iters == 300 and r1.gap == r0.gap
 
 
+@pytest.mark.parametrize("depth", [5, 1])
+def test_steps_with_changing_coefficients(depth):
+    """Coefficients that change between step calls, with step lengths that cut
+    passes short.  The sweep forms the extrapolation of f^k from f^k, g, p^k
+    and the step tau that produced f^k (kept in the device state), so the
+    first pass after a change must use the previous call's tau; the oracle
+    iterates the same schedule with the textbook extrapolation."""
+    shape = (70, 301)
+    g32 = scene32(*shape, 10, 0.1, 79)
+    sched = [(7, 0.1, 0.30, 0.30), (3, 0.05, 0.20, 0.45), (11, 0.2, 0.35, 0.25),
+             (5, 0.1, 0.25, 0.40)]
+    print(f"case: depth {depth} shape {shape}", flush=True)
+    tv.set_pass_depth(depth)
+    try:
+        s = tv.PlainSolver(shape, DEV)
+        s.init(torch.from_numpy(g32).to(DEV))
+        for n, lam, tau, sig in sched:
+            s.step(n, lam, tau, sig)
+        f, p = s.state()
+        torch.cuda.synchronize()
+    finally:
+        tv.set_blocking(True)
+    assert s.iteration() == sum(c[0] for c in sched)
+    g = g32.astype(np.float64)
+    fo, fprev, po = oracle.init_state(g)
+    for n, lam, tau, sig in sched:
+        lam, tau, sig = (float(np.float32(v)) for v in (lam, tau, sig))
+        for _ in range(n):
+            fn, po = oracle.pdhg_iteration(fo, fprev, po, g, lam, tau, sig)
+            fprev, fo = fo, fn
+    assert rel(f.cpu().numpy(), fo) < RTOL
+    assert rel(p.cpu().numpy(), po) < 1e-4
+
+
 def test_solve_stops_like_oracle():
     w = WORKLOADS["denoise_256"]
     g32 = scene32(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
