@@ -17,7 +17,12 @@
  *     p^{k+1} = projection of p^k + sigma grad fbar onto {|p_i|_2 <= lam}
  *     f^{k+1} = (f^k + tau div p^{k+1} + tau g) / (1 + tau)
  *
- * from f^0 = f^{-1} = g, p^0 = 0.  Convergence needs tau sigma ||grad||^2 < 1;
+ * from f^0 = f^{-1} = g, p^0 = 0.  The 2D solvers form the extrapolation as
+ * fbar = f^k + theta tau' (g + div p^k - f^k), tau' the step that produced
+ * f^k, the same value (the data prox gives f^{k-1} = (1 + tau') f^k -
+ * tau' (g + div p^k)), so their workspace keeps no f^{k-1}; the workspace
+ * records tau' for steps whose coefficients change between calls.
+ * Convergence needs tau sigma ||grad||^2 < 1;
  * ||grad||^2 < 8 in 2D and < 12 in 3D, so tau = sigma = 1/sqrt(8) (2D) and
  * 1/sqrt(12) (3D) are always admissible.  The duality gap of a pair (f, p) is
  *     gap = sum_i 1/2 (f_i - g_i - (div p)_i)^2 + lam |(grad f)_i| - <(grad f)_i, p_i>
@@ -176,9 +181,10 @@ int tvpd_get_tile3d(const tvpd_shape* shape, int32_t* th, int32_t* tz,
                     int32_t* wpb);
 
 /* Temporal blocking of the 2D solvers.  The plain solver runs its
- * iterations as passes of up to `depth` iterations per launch (f^k, f^{k-1},
- * p^k, g read once; f^{k+n-1}, f^{k+n}, p^{k+n} written once: 36 bytes per n
- * pixel-iterations, against 32 per pixel-iteration unblocked); a gap check
+ * iterations as passes of up to `depth` iterations per launch (f^k, p^k, g
+ * read once; f^{k+n}, p^{k+n} written once: 28 bytes per n pixel-iterations,
+ * against 32 per pixel-iteration for one pass per iteration that reads
+ * f^{k-1}); a gap check
  * only ever falls on a pass's first iteration, so passes end before the next
  * check.  depth in 1 .. 6, default 5; the batched solver uses passes of 1,
  * 2 and (with depth >= 5) 5 iterations.  The iterates are bit-identical for
