@@ -17,11 +17,12 @@
  *     p^{k+1} = projection of p^k + sigma grad fbar onto {|p_i|_2 <= lam}
  *     f^{k+1} = (f^k + tau div p^{k+1} + tau g) / (1 + tau)
  *
- * from f^0 = f^{-1} = g, p^0 = 0.  The 2D solvers form the extrapolation as
- * fbar = f^k + theta tau' (g + div p^k - f^k), tau' the step that produced
- * f^k, the same value (the data prox gives f^{k-1} = (1 + tau') f^k -
- * tau' (g + div p^k)), so their workspace keeps no f^{k-1}; the workspace
- * records tau' for steps whose coefficients change between calls.
+ * from f^0 = f^{-1} = g, p^0 = 0.  The plain and batched 2D solvers form
+ * the extrapolation as fbar = f^k + theta tau' (g + div p^k - f^k), tau' the
+ * step that produced f^k, the same value (the data prox gives f^{k-1} =
+ * (1 + tau') f^k - tau' (g + div p^k)), so their workspaces keep no f^{k-1};
+ * the plain workspace records tau' for steps whose coefficients change
+ * between calls.
  * Convergence needs tau sigma ||grad||^2 < 1;
  * ||grad||^2 < 8 in 2D and < 12 in 3D, so tau = sigma = 1/sqrt(8) (2D) and
  * 1/sqrt(12) (3D) are always admissible.  The duality gap of a pair (f, p) is
