@@ -34,6 +34,12 @@
 // image never reach a stored one; with SPLIT, tiles where no mask can fire
 // walk a second copy of the loop without them.  Every load is clamped into
 // the image.
+//
+// The unrolled solver's forward passes use the same walk with three
+// differences: the extrapolation as defined (PROX = false: f^{k-1} is read
+// once per pass and each stage forms fbar from its new and its input iterate,
+// the values its adjoint recomputes from the stored iterates), coefficients
+// per stage, and every stage storing its iterate (ALL).
 #pragma once
 
 #include <type_traits>
@@ -55,20 +61,29 @@ struct TileCtxS {
   int x0, y0, y1;   // owned columns [x0, x0+256-2M), rows [y0, y1)
   float lam, tau, sig, th;
   float tau_prev;   // the step that produced f^k (any value at k = 0)
+  // PROX = false: f^{k-1}
+  const float* MF;
+  // ALL: stage s's coefficients and outputs f^{k+s}, p^{k+s} at index s-1
+  float slam[kMaxPass], stau[kMaxPass], ssig[kMaxPass];
+  float* SF[kMaxPass];
+  float* SQX[kMaxPass];
+  float* SQY[kMaxPass];
 };
 
-// One row of the loaded inputs.
+// One row of the loaded inputs (m: f^{k-1}, loaded with PROX = false only).
 struct XsLoad {
-  F4 f, px, py, g;
+  F4 f, px, py, g, m;
 };
 
-template <int S, int M, bool GAP, bool SPLIT = true>
+template <int S, int M, bool GAP, bool SPLIT = true, bool PROX = true,
+          bool ALL = false>
 __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
                                               double& acc_gap,
                                               double& acc_P) {
   static_assert(S >= 1 && M >= S + 1 && M % kColsPerLane == 0 &&
                     2 * M < kStripCols,
                 "overlap margins");
+  static_assert(!(ALL && GAP), "the per-stage variant has no gap");
   constexpr int kLeft = M;                     // columns left of the owned range
   constexpr int kOwned = kStripCols - 2 * M;
   const int lane = threadIdx.x & (kWave - 1);
@@ -90,12 +105,18 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
     L.px = ld4(c.PX + o);
     L.py = ld4(c.PY + o);
     L.g = ld4(c.G + o);
+    if constexpr (!PROX) L.m = ld4(c.MF + o);
   };
 
   // fbar^k on row y from its loads L and p_y^k of the row above (pya).
   auto fbar_loaded = [&](auto edge_tag, int y, const XsLoad& L, const F4& pya,
                          F4& out) {
     constexpr bool kEdge = decltype(edge_tag)::value;
+    if constexpr (!PROX) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out.v[j] = extrap(L.f.v[j], L.m.v[j], th);
+      return;
+    }
     const bool up = !kEdge || y > 0;
     const float pl = from_left(L.px.v[3]);
 #pragma unroll
@@ -150,6 +171,13 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       const F4& EX = (s == 1) ? lp1x : po1x[s - 1];   // p^{k+s-1}, row r
       const F4& EY = (s == 1) ? lp1y : po1y[s - 1];
       const F4& Gv = gh[s - 1];                        // g, row r
+      // the stage's coefficients
+      const float lam_s = ALL ? c.slam[s - 1] : lam;
+      const float tau_s = ALL ? c.stau[s - 1] : tau;
+      const float sig_s = ALL ? c.ssig[s - 1] : sig;
+      const float lam2_s = ALL ? lam_s * lam_s : lam2;
+      const float iopt_s = ALL ? prox_factor(tau_s) : iopt;
+      const float thtau_s = ALL ? th * tau_s : thtau;
       const float nbr = from_right(cb.v[0]);
       F4 npx, npy;
 #pragma unroll
@@ -157,8 +185,8 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
         const float right = (j < 3) ? cb.v[j + 1] : nbr;
         const float gx = (!kEdge || xg + j < nx - 1) ? right - cb.v[j] : 0.0f;
         const float gy = dn ? nb.v[j] - cb.v[j] : 0.0f;
-        project2(dual_arg(EX.v[j], sig, gx), dual_arg(EY.v[j], sig, gy), lam, lam2,
-                 npx.v[j], npy.v[j]);
+        project2(dual_arg(EX.v[j], sig_s, gx), dual_arg(EY.v[j], sig_s, gy), lam_s,
+                 lam2_s, npx.v[j], npy.v[j]);
       }
       const float left = from_left(npx.v[3]);
       const bool up = !kEdge || r > 0;
@@ -167,14 +195,23 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       for (int j = 0; j < 4; ++j) {
         const float lp = (j == 0) ? ((!kEdge || xg > 0) ? left : 0.0f) : npx.v[j - 1];
         const float d = (npx.v[j] - lp) + (npy.v[j] - (up ? cy[s].v[j] : 0.0f));
-        const float v = fmaf(tau, d, B.v[j]);
-        fnew.v[j] = fmaf(tau, Gv.v[j], v) * iopt;
-        fbnew.v[j] = extrap_prox(fnew.v[j], Gv.v[j], d, thtau);
+        const float v = fmaf(tau_s, d, B.v[j]);
+        fnew.v[j] = fmaf(tau_s, Gv.v[j], v) * iopt_s;
+        fbnew.v[j] = PROX ? extrap_prox(fnew.v[j], Gv.v[j], d, thtau_s)
+                          : extrap(fnew.v[j], B.v[j], th);
       }
       fo[s] = fnew;
       fb[s] = fbnew;
       pox[s] = npx;
       poy[s] = npy;
+      if constexpr (ALL) {
+        if (owned && r >= y0 && r < y1) {
+          const int64_t o = (int64_t)r * P + xg;
+          st4(c.SF[s - 1] + o, fnew);
+          st4(c.SQX[s - 1] + o, npx);
+          st4(c.SQY[s - 1] + o, npy);
+        }
+      }
       if constexpr (GAP) {
         // gap density and primal energy of (f^k, p^k) on row t
         // (the lane shuffles run on the whole wave: a row condition is the
@@ -207,7 +244,7 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       }
     }
     // stores: f^{k+S} and p^{k+S} of stage S's row, inside the band
-    if (owned) {
+    if (!ALL && owned) {
       const int rS = t - (S - 1);
       if (rS >= y0 && rS < y1) {
         const int64_t o = (int64_t)rS * P + xg;

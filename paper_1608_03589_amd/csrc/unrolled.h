@@ -22,6 +22,13 @@ struct StepIds {
   int fn, pn;       // outputs
 };
 
+// A forward pass k -> k+n in 2D (n <= kMaxPass): the outputs of every
+// iteration k+s at index s-1.
+struct PassIds {
+  int fk, fkm, pk;
+  int fn[kMaxPass], pn[kMaxPass];
+};
+
 // One adjoint step.
 struct AdjIds {
   int fk, fkm, pk;      // forward state of step k
@@ -34,9 +41,14 @@ struct AdjIds {
 
 hipError_t launch_u_init(const PlaneSet& P, const float* g, int id_g,
                          int id_zero, int nzero, hipStream_t s);
+// 3D only: one iteration k -> k+1.
 hipError_t launch_u_step(const PlaneSet& P, const StepIds& ids,
                          const float* coeffs, int k, float theta,
                          hipStream_t s);
+// 2D only: iterations k .. k+n-1 in one launch (1 <= n <= kMaxPass).
+hipError_t launch_u_pass2d(const PlaneSet& P, const PassIds& ids,
+                           const float* coeffs, int k, int n, float theta,
+                           hipStream_t s);
 hipError_t launch_u_read(const PlaneSet& P, int id, float* out, hipStream_t s);
 hipError_t launch_u_load(const PlaneSet& P, const float* in, int id,
                          hipStream_t s);

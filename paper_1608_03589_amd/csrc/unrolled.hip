@@ -5,8 +5,10 @@
 //     fbar    = f^k + theta (f^k - f^{k-1})
 //     p^{k+1} = P_lam(p^k + sigma grad fbar)
 //     f^{k+1} = (f^k + tau div p^{k+1} + tau g) / (1 + tau)
-// Both use the fused tile sweeps of the plain solver (tile2d.h, tile3d.h)
-// with the step's coefficients read from device memory.
+// 2D runs as passes of up to five iterations on the plain solver's strip tile
+// (tile2d_xs.h, with this extrapolation and every iterate stored), 3D one
+// iteration per launch on the plain solver's tile (tile3d.h), with the
+// steps' coefficients read from device memory.
 //
 // Adjoint step k (reverse-mode derivative of the forward step; a = dL/df^{k+1},
 // b = the part of dL/df^k collected from step k+1's extrapolation, r =
@@ -27,6 +29,7 @@
 #include "adj2d.h"
 #include "adj3d.h"
 #include "tile2d.h"
+#include "tile2d_xs.h"
 #include "tile3d.h"
 #include "unrolled.h"
 
@@ -140,8 +143,12 @@ __device__ __forceinline__ float div_point(const float* v, int64_t PL,
 
 // ----------------------------- forward ------------------------------------
 
-__global__ __launch_bounds__(kMaxBlock) void u_sweep2d_kernel(
-    PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k,
+// Iterations k .. k+S-1 of every image in one launch (tile2d_xs.h with the
+// extrapolation as defined, per-stage coefficients read from device memory,
+// and every iterate stored to its plane slot).
+template <int S>
+__global__ __launch_bounds__(kMaxBlock) void u_sweep2d_xs_kernel(
+    PlaneSet P, PassIds ids, const float* __restrict__ coeffs, int k,
     float theta, int th_rows, int wpb, int ntx, int nty) {
   const int b = blockIdx.y;
   const int wave = threadIdx.x / kWave;
@@ -151,27 +158,35 @@ __global__ __launch_bounds__(kMaxBlock) void u_sweep2d_kernel(
   const int wt = bt * wpb + wave;
   if (wt >= ntx * nty) return;
   const int ty = wt / ntx, tx = wt - ty * ntx;
-  TileCtx c;
-  c.fk = cplane(P, b, ids.fk);
-  c.fkm = cplane(P, b, ids.fkm);
-  c.pxk = cplane(P, b, ids.pk);
-  c.pyk = cplane(P, b, ids.pk + 1);
-  c.g = cplane(P, b, 0);
-  c.fn = plane(P, b, ids.fn);
-  c.pxn = plane(P, b, ids.pn);
-  c.pyn = plane(P, b, ids.pn + 1);
+  TileCtxS c;
+  c.F = cplane(P, b, ids.fk);
+  c.MF = cplane(P, b, ids.fkm);
+  c.PX = cplane(P, b, ids.pk);
+  c.PY = cplane(P, b, ids.pk + 1);
+  c.G = cplane(P, b, 0);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    c.SF[s] = plane(P, b, ids.fn[s]);
+    c.SQX[s] = plane(P, b, ids.pn[s]);
+    c.SQY[s] = plane(P, b, ids.pn[s] + 1);
+    c.slam[s] = coeffs[3 * (k + s)];
+    c.stau[s] = coeffs[3 * (k + s) + 1];
+    c.ssig[s] = coeffs[3 * (k + s) + 2];
+  }
+  c.FN = c.QX = c.QY = nullptr;
   c.ny = P.ny;
   c.nx = P.nx;
   c.pitch = P.pitch;
-  c.x0 = tx * kStripCols;
+  c.x0 = tx * xs_owned(S);
   c.y0 = ty * th_rows;
   c.y1 = min(c.y0 + th_rows, P.ny);
-  c.lam = coeffs[3 * k];
-  c.tau = coeffs[3 * k + 1];
-  c.sig = coeffs[3 * k + 2];
+  c.lam = c.slam[0];
+  c.tau = c.stau[0];
+  c.sig = c.ssig[0];
   c.th = theta;
+  c.tau_prev = 0.0f;
   double sg = 0.0, sp = 0.0;
-  sweep_tile<false>(c, sg, sp);
+  sweep_tile_xs<S, xs_margin(S), false, true, false, true>(c, sg, sp);
 }
 
 template <int TH>
@@ -541,48 +556,62 @@ hipError_t launch_u_zero(const PlaneSet& P, int id, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_u_pass2d(const PlaneSet& P, const PassIds& ids,
+                           const float* coeffs, int k, int n, float theta,
+                           hipStream_t s) {
+  if (P.ndim != 2 || n < 1 || n > kMaxPass - 1) return hipErrorInvalidValue;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+          hipSuccess || cus < 1)
+    cus = 256;
+  // the plain solver's rule for deep passes: the shortest bands whose
+  // blocks (4 waves) all fit on the GPU at once, two per CU
+  const int strip = xs_owned(n);
+  const int64_t ntx = (P.nx + strip - 1) / strip;
+  const int wpb = 4;
+  int64_t th = 8;
+  while (th < 256 &&
+         (ntx * ((P.ny + th - 1) / th) + wpb - 1) / wpb * P.nb > 2LL * cus)
+    ++th;
+  const int nty = (int)((P.ny + th - 1) / th);
+  const int nbx = (int)((ntx * nty + wpb - 1) / wpb);
+  const dim3 grid(nbx, P.nb), block(wpb * kWave);
+  switch (n) {
+    case 1: hipLaunchKernelGGL(u_sweep2d_xs_kernel<1>, grid, block, 0, s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx, nty); break;
+    case 2: hipLaunchKernelGGL(u_sweep2d_xs_kernel<2>, grid, block, 0, s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx, nty); break;
+    case 3: hipLaunchKernelGGL(u_sweep2d_xs_kernel<3>, grid, block, 0, s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx, nty); break;
+    case 4: hipLaunchKernelGGL(u_sweep2d_xs_kernel<4>, grid, block, 0, s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx, nty); break;
+    default: hipLaunchKernelGGL(u_sweep2d_xs_kernel<5>, grid, block, 0, s, P, ids, coeffs, k, theta, (int)th, wpb, (int)ntx, nty); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_u_step(const PlaneSet& P, const StepIds& ids,
                          const float* coeffs, int k, float theta,
                          hipStream_t s) {
-  if (P.ndim == 2) {
-    const int ntx = (P.nx + kStripCols - 1) / kStripCols;
-    Layout L;
-    L.ndim = 2;
-    L.nz = 1;
-    L.ny = P.ny;
-    L.nx = P.nx;
-    // bands tall enough for about one block of four waves per CU overall
-    int64_t th = ((int64_t)ntx * P.ny * P.nb + 1023) / 1024;
-    if (th < 8) th = 8;
-    if (th > 256) th = 256;
-    const int nty = (P.ny + (int)th - 1) / (int)th;
-    const int wpb = 4;
-    const int nbx = (ntx * nty + wpb - 1) / wpb;
-    hipLaunchKernelGGL(u_sweep2d_kernel, dim3(nbx, P.nb), dim3(wpb * kWave), 0,
-                       s, P, ids, coeffs, k, theta, (int)th, wpb, ntx, nty);
-  } else {
-    // the plain solver's tile for this volume shape
-    Layout L;
-    L.ndim = 3;
-    L.nz = P.nz;
-    L.ny = P.ny;
-    L.nx = P.nx;
-    const Tile3D t = tile3d_for(L);
-    if (!tile3d_ok(t)) return hipErrorInvalidValue;
-    const int ntx = (P.nx + kStripCols - 1) / kStripCols;
-    const int nty = (P.ny + t.th - 1) / t.th;
-    const int ntz = (P.nz + t.tz - 1) / t.tz;
-    const int64_t nt = (int64_t)ntx * nty * ntz;
-    if (nt > INT32_MAX / 2) return hipErrorInvalidValue;
-    const int nbx = (int)((nt + t.wpb - 1) / t.wpb);
-    const dim3 grid(nbx, P.nb), block(t.wpb * kWave);
-    if (t.th == 2)
-      hipLaunchKernelGGL(u_sweep3d_kernel<2>, grid, block, 0, s, P, ids,
-                         coeffs, k, theta, t.tz, t.wpb, ntx, nty, (int)nt);
-    else
-      hipLaunchKernelGGL(u_sweep3d_kernel<4>, grid, block, 0, s, P, ids,
-                         coeffs, k, theta, t.tz, t.wpb, ntx, nty, (int)nt);
-  }
+  if (P.ndim != 3) return hipErrorInvalidValue;   // 2D: launch_u_pass2d
+  // the plain solver's tile for this volume shape
+  Layout L;
+  L.ndim = 3;
+  L.nz = P.nz;
+  L.ny = P.ny;
+  L.nx = P.nx;
+  const Tile3D t = tile3d_for(L);
+  if (!tile3d_ok(t)) return hipErrorInvalidValue;
+  const int ntx = (P.nx + kStripCols - 1) / kStripCols;
+  const int nty = (P.ny + t.th - 1) / t.th;
+  const int ntz = (P.nz + t.tz - 1) / t.tz;
+  const int64_t nt = (int64_t)ntx * nty * ntz;
+  if (nt > INT32_MAX / 2) return hipErrorInvalidValue;
+  const int nbx = (int)((nt + t.wpb - 1) / t.wpb);
+  const dim3 grid(nbx, P.nb), block(t.wpb * kWave);
+  if (t.th == 2)
+    hipLaunchKernelGGL(u_sweep3d_kernel<2>, grid, block, 0, s, P, ids,
+                       coeffs, k, theta, t.tz, t.wpb, ntx, nty, (int)nt);
+  else
+    hipLaunchKernelGGL(u_sweep3d_kernel<4>, grid, block, 0, s, P, ids,
+                       coeffs, k, theta, t.tz, t.wpb, ntx, nty, (int)nt);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 //   p^s          : checkpoint j (segment 0: the zero planes)
 //   p^e          : checkpoint j+1, or a discard slot when e = K
 // so no state is ever copied.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 
@@ -142,8 +143,29 @@ int uws_ok(const ULayout& L, void* ws, size_t bytes) {
     if ((call) != hipSuccess) return TVPD_ERR_HIP; \
   } while (0)
 
+// Forward iterations k_from .. k_to-1 of segment j.  2D: passes of up to
+// min(pass depth, 5) iterations, each iterate stored to its slot (the slots
+// a pass writes are never among those it reads); 3D: one launch each.
 int run_steps(const UPlan& p, const PlaneSet& P, int j, int k_from, int k_to,
               const float* coeffs, float theta, hipStream_t s) {
+  if (P.ndim == 2) {
+    const int depth = std::max(1, std::min(pass_depth(), kMaxPass - 1));
+    for (int k = k_from; k < k_to;) {
+      const int n = std::min(depth, k_to - k);
+      PassIds ids;
+      ids.fk = p.f_slot(j, k);
+      ids.fkm = p.f_slot(j, k - 1);
+      ids.pk = p.p_slot(j, k);
+      for (int i = 0; i < kMaxPass; ++i) ids.fn[i] = ids.pn[i] = 0;
+      for (int i = 1; i <= n; ++i) {
+        ids.fn[i - 1] = p.f_slot(j, k + i);
+        ids.pn[i - 1] = p.p_slot(j, k + i);
+      }
+      UHIP(launch_u_pass2d(P, ids, coeffs, k, n, theta, s));
+      k += n;
+    }
+    return TVPD_OK;
+  }
   for (int k = k_from; k < k_to; ++k) {
     StepIds ids;
     ids.fk = p.f_slot(j, k);

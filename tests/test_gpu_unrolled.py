@@ -71,6 +71,28 @@ def test_unrolled_2d_parity(shape, K, ckpt):
     assert rel(gc, gc_ref) <= 1e-4
 
 
+@pytest.mark.parametrize("shape,K,ckpt", [((2, 70, 301), 13, 13),
+                                          ((3, 37, 520), 12, 5),
+                                          ((1, 9, 17), 7, 3)])
+def test_forward_passes_are_bitwise_equal(shape, K, ckpt):
+    """The 2D forward runs as passes of up to five iterations that store every
+    iterate; one-iteration passes give the same iterates, dL/dg and
+    coefficient gradients bit for bit (checkpointed segments included)."""
+    print(f"case: unrolled passes {shape} K={K} ckpt={ckpt}", flush=True)
+    _, g = batch2d(*shape, seed=910)
+    c = coeffs_for(K, 2, 11)
+    grad_f = np.random.default_rng(12).normal(size=g.shape).astype(np.float32)
+    out = {}
+    try:
+        for depth in (1, 5):
+            tv.set_pass_depth(depth)
+            out[depth] = run_gpu(g, c, ckpt, grad_f)
+    finally:
+        tv.set_blocking(True)
+    for a, b in zip(out[5], out[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("shape,K,ckpt", [((2, 37, 301), 6, 3),
                                           ((1, 130, 520), 5, 5),
                                           ((3, 9, 17), 4, 2),
