@@ -12,8 +12,10 @@
 //      frequencies (p, q)/Q of a Q x Q grid (Q a power of two >= 2 max(ny,
 //      nx)), zero beyond |nu| = 1/2, times the phase that puts the pixel
 //      centres on the integer grid;
-//   4. 2D inverse DFT (row transforms, a transpose, row transforms), real
-//      part at the pixels, divided by Q^2.
+//   4. 2D inverse DFT, real part at the pixels, divided by Q^2: transforms
+//      of the grid rows fused with step 3 (of which only the nx pixel
+//      columns are kept), a transpose of those columns, and their
+//      transforms (of which only the ny pixel rows are read).
 // The transforms are radix-4 Stockham FFTs in LDS (lengths up to 4096; one
 // radix-2 stage for odd powers of two), with twiddles from a float64 table.  Every phase is reduced as an exact integer
 // before its sine and cosine.
@@ -171,59 +173,78 @@ __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, 
   }
 }
 
-// Step 3 at (p, q) in DFT order: A[q][p] = phase * bilinear(spec).
-__global__ void bst_cartesian_kernel(const float2* spec, float2* A, int na, int M, int Q,
-                                     int nx, int ny) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  if (p >= Q) return;
-  const int ps = p < Q / 2 ? p : p - Q, qs = q < Q / 2 ? q : q - Q;
-  const double u = (double)ps / Q, v = (double)qs / Q;
-  const double rho = sqrt(u * u + v * v);
-  float2 val = make_float2(0.0f, 0.0f);
-  if (rho <= 0.5) {
-    double phi = atan2(v, u);                       // (-pi, pi]
-    double nu = rho;
-    if (phi < 0.0) {
-      phi += M_PI;
-      nu = -rho;
-    }
-    if (phi >= M_PI) {
-      phi -= M_PI;
-      nu = -nu;
-    }
-    const double aidx = phi / (M_PI / na);
-    int k0 = (int)floor(aidx);
-    if (k0 > na - 1) k0 = na - 1;                   // rounding at phi -> pi
-    const float wa = (float)(aidx - k0);
-    int k1 = k0 + 1;
-    double nu1 = nu;
-    if (k1 >= na) {                                 // theta = pi: angle 0, -nu
-      k1 = 0;
-      nu1 = -nu;
-    }
-    auto radial = [&](int k, double nv) {
-      const double xr = nv * M + M / 2;
-      const int j0 = (int)floor(xr);
-      const float wr = (float)(xr - j0);
-      const float2* row = spec + (int64_t)k * M;
-      const float2 p0 = (j0 >= 0 && j0 < M) ? row[j0] : make_float2(0.0f, 0.0f);
-      const float2 p1 = (j0 + 1 >= 0 && j0 + 1 < M) ? row[j0 + 1] : make_float2(0.0f, 0.0f);
-      return make_float2(p0.x + wr * (p1.x - p0.x), p0.y + wr * (p1.y - p0.y));
-    };
-    const float2 r0 = radial(k0, nu), r1 = radial(k1, nu1);
-    val = make_float2(r0.x + wa * (r1.x - r0.x), r0.y + wa * (r1.y - r0.y));
-    // pixel centres at n + (1 - n_side)/2: phase 2 pi (ps (1 - nx) + qs (1 - ny)) / (2Q)
-    int64_t ph = ((int64_t)ps * (1 - nx) + (int64_t)qs * (1 - ny)) % (2 * (int64_t)Q);
-    if (ph < 0) ph += 2 * (int64_t)Q;
-    float sn, cs;
-    sincospif((float)ph / (float)Q, &sn, &cs);
-    val = cmul(val, make_float2(cs, sn));
+// Step 3 at the grid frequency (ps, qs)/Q (signed indices) with polar
+// angle phi = atan2(qs, ps) in (-pi, pi] and radius rho: phase * bilinear(spec).
+__device__ float2 cartesian_value(const float2* spec, int na, int M, int Q, int nx, int ny,
+                                  int ps, int qs, double phi, double rho) {
+  if (rho > 0.5) return make_float2(0.0f, 0.0f);
+  double nu = rho;
+  if (phi < 0.0) {
+    phi += M_PI;
+    nu = -rho;
   }
-  A[(int64_t)q * Q + p] = val;
+  if (phi >= M_PI) {
+    phi -= M_PI;
+    nu = -nu;
+  }
+  const double aidx = phi / (M_PI / na);
+  int k0 = (int)floor(aidx);
+  if (k0 > na - 1) k0 = na - 1;                   // rounding at phi -> pi
+  if (k0 < 0) k0 = 0;
+  const float wa = (float)(aidx - k0);
+  int k1 = k0 + 1;
+  double nu1 = nu;
+  if (k1 >= na) {                                 // theta = pi: angle 0, -nu
+    k1 = 0;
+    nu1 = -nu;
+  }
+  auto radial = [&](int k, double nv) {
+    const double xr = nv * M + M / 2;
+    const int j0 = (int)floor(xr);
+    const float wr = (float)(xr - j0);
+    const float2* row = spec + (int64_t)k * M;
+    const float2 p0 = (j0 >= 0 && j0 < M) ? row[j0] : make_float2(0.0f, 0.0f);
+    const float2 p1 = (j0 + 1 >= 0 && j0 + 1 < M) ? row[j0 + 1] : make_float2(0.0f, 0.0f);
+    return make_float2(p0.x + wr * (p1.x - p0.x), p0.y + wr * (p1.y - p0.y));
+  };
+  const float2 r0 = radial(k0, nu), r1 = radial(k1, nu1);
+  const float2 val = make_float2(r0.x + wa * (r1.x - r0.x), r0.y + wa * (r1.y - r0.y));
+  // pixel centres at n + (1 - n_side)/2: phase 2 pi (ps (1 - nx) + qs (1 - ny)) / (2Q)
+  int64_t ph = ((int64_t)ps * (1 - nx) + (int64_t)qs * (1 - ny)) % (2 * (int64_t)Q);
+  if (ph < 0) ph += 2 * (int64_t)Q;
+  float sn, cs;
+  sincospif((float)ph / (float)Q, &sn, &cs);
+  return cmul(val, make_float2(cs, sn));
 }
 
-// Inverse transforms of the rows of a Q x Q array, in place.
+// Step 3 for grid row q and its inverse transform along p, in LDS; the
+// first nx outputs (the pixel columns) go to A[q][0 .. nx).  The points
+// (ps, qs) and (-ps, qs) share rho and one float64 arctangent:
+// atan2(qs, -ps) = +-pi - atan2(qs, ps) (the sign of qs, +pi for qs = 0).
+__global__ __launch_bounds__(kMaxBlock) void bst_cartesian_rows_kernel(
+    const float2* spec, float2* A, const float2* tw, int na, int M, int Q, int nx, int ny,
+    int tl) {
+  __shared__ float2 x[kBstMaxLen];
+  const int q = blockIdx.x;
+  const int qs = q < Q / 2 ? q : q - Q;
+  const double v = (double)qs / Q;
+  for (int a = threadIdx.x; a <= Q / 2; a += blockDim.x) {
+    const double u = (double)a / Q;
+    const double rho = sqrt(u * u + v * v);
+    const double phi = atan2(v, u);                        // point (a, qs)
+    if (a < Q / 2) x[a] = cartesian_value(spec, na, M, Q, nx, ny, a, qs, phi, rho);
+    if (a > 0) {                                           // point (-a, qs)
+      const double phm = (qs >= 0 ? M_PI : -M_PI) - phi;
+      x[Q - a] = cartesian_value(spec, na, M, Q, nx, ny, -a, qs, phm, rho);
+    }
+  }
+  __syncthreads();
+  fft_lds<+1>(x, Q, tw, tl);
+  float2* out = A + (int64_t)q * nx;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[i] = x[i];
+}
+
+// Inverse transforms of n rows of length Q, in place.
 __global__ __launch_bounds__(kMaxBlock) void bst_rows_inverse_kernel(float2* A, const float2* tw,
                                                                      int Q, int tl) {
   __shared__ float2 x[kBstMaxLen];
@@ -234,15 +255,17 @@ __global__ __launch_bounds__(kMaxBlock) void bst_rows_inverse_kernel(float2* A, 
   for (int i = threadIdx.x; i < Q; i += blockDim.x) row[i] = x[i];
 }
 
-// B[c][r] = A[r][c] for a Q x Q complex array, 32 x 32 tiles.
-__global__ void bst_transpose_kernel(const float2* A, float2* B, int Q) {
+// B[c][r] = A[r][c] for A of Q rows and nx columns (B: nx rows of Q), 32 x 32
+// tiles (Q is a multiple of 32).
+__global__ void bst_transpose_kernel(const float2* A, float2* B, int Q, int nx) {
   __shared__ float2 t[32][33];
   const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int c = c0 + threadIdx.x;
   for (int r = threadIdx.y; r < 32; r += 8)
-    t[r][threadIdx.x] = A[(int64_t)(r0 + r) * Q + c0 + threadIdx.x];
+    t[r][threadIdx.x] = c < nx ? A[(int64_t)(r0 + r) * nx + c] : make_float2(0.0f, 0.0f);
   __syncthreads();
-  for (int c = threadIdx.y; c < 32; c += 8)
-    B[(int64_t)(c0 + c) * Q + r0 + threadIdx.x] = t[threadIdx.x][c];
+  for (int cc = threadIdx.y; cc < 32; cc += 8)
+    if (c0 + cc < nx) B[(int64_t)(c0 + cc) * Q + r0 + threadIdx.x] = t[threadIdx.x][cc];
 }
 
 // img[a][b] = Re(B[b][a]) / Q^2 (B holds the image transposed).
@@ -354,14 +377,17 @@ int tvpd_bst_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
   float2* A = reinterpret_cast<float2*>(base + L.off_a);
   float2* B = reinterpret_cast<float2*>(base + L.off_b);
   BST_TRY(spectra(L, g, base, s));
-  bst_cartesian_kernel<<<dim3((L.Q + 255) / 256, L.Q), 256, 0, s>>>(
-      reinterpret_cast<const float2*>(base + L.off_spec), A, L.na, L.M, L.Q, L.nx, L.ny);
+  // rows of the grid: step 3 and the transforms along x, keeping the nx
+  // pixel columns (A: Q rows of nx)
+  bst_cartesian_rows_kernel<<<L.Q, kMaxBlock, 0, s>>>(
+      reinterpret_cast<const float2*>(base + L.off_spec), A, tw, L.na, L.M, L.Q, L.nx, L.ny,
+      tl);
   BST_TRY(launched());
-  bst_rows_inverse_kernel<<<L.Q, kMaxBlock, 0, s>>>(A, tw, L.Q, tl);
+  // the pixel columns as rows (B: nx rows of Q), transformed along y
+  bst_transpose_kernel<<<dim3((L.nx + 31) / 32, L.Q / 32), dim3(32, 8), 0, s>>>(A, B, L.Q,
+                                                                                L.nx);
   BST_TRY(launched());
-  bst_transpose_kernel<<<dim3(L.Q / 32, L.Q / 32), dim3(32, 8), 0, s>>>(A, B, L.Q);
-  BST_TRY(launched());
-  bst_rows_inverse_kernel<<<L.Q, kMaxBlock, 0, s>>>(B, tw, L.Q, tl);
+  bst_rows_inverse_kernel<<<L.nx, kMaxBlock, 0, s>>>(B, tw, L.Q, tl);
   BST_TRY(launched());
   bst_extract_kernel<<<dim3((L.nx + 31) / 32, (L.ny + 31) / 32), dim3(32, 8), 0, s>>>(
       B, img, L.Q, L.ny, L.nx, (float)(1.0 / ((double)L.Q * (double)L.Q)));
