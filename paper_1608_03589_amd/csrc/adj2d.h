@@ -17,10 +17,12 @@
 // The forward quantities are recomputed with the forward sweep's arithmetic
 // (pointwise.h), so the projection takes the forward's branch.
 //
-// Layout of the walk as in the forward tile (tile2d.h): a wave owns the
-// strip, walks the band top to bottom carrying the previous row's p_y^{k+1}
-// and t_y, takes x-neighbours from adjacent lanes and recomputes the values
-// owned by other tiles (column x0-1, row y0-1).  Per pixel it reads f^k,
+// Layout of the walk: a wave owns a 256-column strip (one float4 per lane),
+// walks a band of rows top to bottom carrying the previous row's p_y^{k+1}
+// and t_y, takes x-neighbours from adjacent lanes, reads the strip's outer
+// columns (x0-1, x0+256) at one shared address per row, and recomputes the
+// values owned by other tiles (column x0-1, row y0-1) with the owner's
+// arithmetic, so the result does not depend on the tiling.  Per pixel it reads f^k,
 // f^{k-1}, p^k (2), g, a, b, r (2) and gbar, and writes a', b', r' (2) and
 // gbar: 60 bytes, against 92 for a forward-difference pass followed by a
 // backward-difference pass that hands p^{k+1} and t over through memory.
