@@ -17,7 +17,8 @@
 //      columns are kept), a transpose of those columns, and their
 //      transforms (of which only the ny pixel rows are read).
 // The transforms are radix-4 Stockham FFTs in LDS (lengths up to 4096; one
-// radix-2 stage for odd powers of two), with twiddles from a float64 table.  Every phase is reduced as an exact integer
+// radix-2 stage for odd powers of two; a padded LDS layout against bank
+// conflicts), with twiddles from a float64 table.  Every phase is reduced as an exact integer
 // before its sine and cosine.
 #include <cmath>
 
@@ -25,7 +26,11 @@
 
 namespace tvpd {
 
-constexpr int kBstMaxLen = 4096;   // LDS FFT length limit (two 32 KiB buffers)
+constexpr int kBstMaxLen = 4096;   // LDS FFT length limit
+// LDS index of element i of a transform: one spare slot per 8 elements, so
+// that the strided writes of the early Stockham stages spread over the banks.
+constexpr int kBstLds = kBstMaxLen + kBstMaxLen / 8;
+__device__ __forceinline__ int lds_at(int i) { return i + (i >> 3); }
 
 __host__ __device__ inline int bst_pow2_at_least(int v) {
   int L = 1;
@@ -86,8 +91,8 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
     for (int u = 0; u < 2 * kFftPerThread; ++u) {
       const int j = threadIdx.x + u * kMaxBlock;
       if (j < n / 2) {
-        v[u][0] = x[j];
-        v[u][1] = x[j + n / 2];
+        v[u][0] = x[lds_at(j)];
+        v[u][1] = x[lds_at(j + n / 2)];
       }
     }
     __syncthreads();
@@ -95,8 +100,8 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
     for (int u = 0; u < 2 * kFftPerThread; ++u) {
       const int j = threadIdx.x + u * kMaxBlock;
       if (j < n / 2) {
-        x[2 * j] = make_float2(v[u][0].x + v[u][1].x, v[u][0].y + v[u][1].y);
-        x[2 * j + 1] = make_float2(v[u][0].x - v[u][1].x, v[u][0].y - v[u][1].y);
+        x[lds_at(2 * j)] = make_float2(v[u][0].x + v[u][1].x, v[u][0].y + v[u][1].y);
+        x[lds_at(2 * j + 1)] = make_float2(v[u][0].x - v[u][1].x, v[u][0].y - v[u][1].y);
       }
     }
     __syncthreads();
@@ -110,7 +115,7 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
       const int j = threadIdx.x + u * kMaxBlock;
       if (j < n / 4) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[u][r] = x[j + r * (n / 4)];
+        for (int r = 0; r < 4; ++r) v[u][r] = x[lds_at(j + r * (n / 4))];
       }
     }
     __syncthreads();
@@ -136,10 +141,10 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
         // SIGN i b
         const float2 ib = SIGN > 0 ? make_float2(-b.y, b.x) : make_float2(b.y, -b.x);
         const int d = ((j - k) << 2) + k;
-        x[d] = make_float2(a0.x + a2.x, a0.y + a2.y);
-        x[d + Ns] = make_float2(a1.x + ib.x, a1.y + ib.y);
-        x[d + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
-        x[d + 3 * Ns] = make_float2(a1.x - ib.x, a1.y - ib.y);
+        x[lds_at(d)] = make_float2(a0.x + a2.x, a0.y + a2.y);
+        x[lds_at(d + Ns)] = make_float2(a1.x + ib.x, a1.y + ib.y);
+        x[lds_at(d + 2 * Ns)] = make_float2(a0.x - a2.x, a0.y - a2.y);
+        x[lds_at(d + 3 * Ns)] = make_float2(a1.x - ib.x, a1.y - ib.y);
       }
     }
     __syncthreads();
@@ -151,11 +156,21 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
 __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, float2* spec,
                                                                 const float2* tw, int nd,
                                                                 int M, int tl) {
-  __shared__ float2 x[kBstMaxLen];
+  __shared__ float2 x[kBstLds];
   const int k = blockIdx.x;
   const float* gr = g + (int64_t)k * nd;
-  for (int i = threadIdx.x; i < M; i += blockDim.x)
-    x[i] = make_float2(i < nd ? gr[i] : 0.0f, 0.0f);
+  constexpr int kPer = kBstMaxLen / kMaxBlock;
+  float v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kMaxBlock;
+    v[u] = i < nd ? gr[i] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kMaxBlock;
+    if (i < M) x[lds_at(i)] = make_float2(v[u], 0.0f);
+  }
   __syncthreads();
   fft_lds<-1>(x, M, tw, tl);
   float2* out = spec + (int64_t)k * M;
@@ -168,7 +183,7 @@ __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, 
     float sn, cs;
     sincospif((float)ph / (float)M, &sn, &cs);
     const float kk = ms == 0 ? (float)M : (float)M / (float)(ms < 0 ? -ms : ms);
-    const float2 v = cmul(x[m], make_float2(cs, sn));
+    const float2 v = cmul(x[lds_at(m)], make_float2(cs, sn));
     out[ms + M / 2] = make_float2(v.x * kk, v.y * kk);
   }
 }
@@ -224,7 +239,7 @@ __device__ float2 cartesian_value(const float2* spec, int na, int M, int Q, int 
 __global__ __launch_bounds__(kMaxBlock) void bst_cartesian_rows_kernel(
     const float2* spec, float2* A, const float2* tw, int na, int M, int Q, int nx, int ny,
     int tl) {
-  __shared__ float2 x[kBstMaxLen];
+  __shared__ float2 x[kBstLds];
   const int q = blockIdx.x;
   const int qs = q < Q / 2 ? q : q - Q;
   const double v = (double)qs / Q;
@@ -232,27 +247,40 @@ __global__ __launch_bounds__(kMaxBlock) void bst_cartesian_rows_kernel(
     const double u = (double)a / Q;
     const double rho = sqrt(u * u + v * v);
     const double phi = atan2(v, u);                        // point (a, qs)
-    if (a < Q / 2) x[a] = cartesian_value(spec, na, M, Q, nx, ny, a, qs, phi, rho);
+    if (a < Q / 2) x[lds_at(a)] = cartesian_value(spec, na, M, Q, nx, ny, a, qs, phi, rho);
     if (a > 0) {                                           // point (-a, qs)
       const double phm = (qs >= 0 ? M_PI : -M_PI) - phi;
-      x[Q - a] = cartesian_value(spec, na, M, Q, nx, ny, -a, qs, phm, rho);
+      x[lds_at(Q - a)] = cartesian_value(spec, na, M, Q, nx, ny, -a, qs, phm, rho);
     }
   }
   __syncthreads();
   fft_lds<+1>(x, Q, tw, tl);
   float2* out = A + (int64_t)q * nx;
-  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[i] = x[i];
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[i] = x[lds_at(i)];
 }
 
 // Inverse transforms of n rows of length Q, in place.
 __global__ __launch_bounds__(kMaxBlock) void bst_rows_inverse_kernel(float2* A, const float2* tw,
                                                                      int Q, int tl) {
-  __shared__ float2 x[kBstMaxLen];
+  __shared__ float2 x[kBstLds];
   float2* row = A + (int64_t)blockIdx.x * Q;
-  for (int i = threadIdx.x; i < Q; i += blockDim.x) x[i] = row[i];
+  // every load of the row issued before the first use (a fixed count per
+  // thread, so the loop unrolls)
+  constexpr int kPer = kBstMaxLen / kMaxBlock;
+  float2 v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kMaxBlock;
+    if (i < Q) v[u] = row[i];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kMaxBlock;
+    if (i < Q) x[lds_at(i)] = v[u];
+  }
   __syncthreads();
   fft_lds<+1>(x, Q, tw, tl);
-  for (int i = threadIdx.x; i < Q; i += blockDim.x) row[i] = x[i];
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) row[i] = x[lds_at(i)];
 }
 
 // B[c][r] = A[r][c] for A of Q rows and nx columns (B: nx rows of Q), 32 x 32
