@@ -16,9 +16,9 @@
 //      of the grid rows fused with step 3 (of which only the nx pixel
 //      columns are kept), a transpose of those columns, and their
 //      transforms (of which only the ny pixel rows are read).
-// The transforms are radix-4 Stockham FFTs in LDS (lengths up to 4096; one
-// radix-2 stage for odd powers of two; a padded LDS layout against bank
-// conflicts), with twiddles from a float64 table.  Every phase is reduced as an exact integer
+// The transforms are radix-16 Stockham FFTs in LDS (lengths up to 4096; a
+// radix-2 and/or radix-4 stage for the remaining factor; a padded LDS layout
+// against bank conflicts), with twiddles from a float64 table.  Every phase is reduced as an exact integer
 // before its sine and cosine.
 #include <cmath>
 
@@ -27,10 +27,10 @@
 namespace tvpd {
 
 constexpr int kBstMaxLen = 4096;   // LDS FFT length limit
-// LDS index of element i of a transform: one spare slot per 8 elements, so
-// that the strided writes of the early Stockham stages spread over the banks.
-constexpr int kBstLds = kBstMaxLen + kBstMaxLen / 8;
-__device__ __forceinline__ int lds_at(int i) { return i + (i >> 3); }
+// LDS index of element i of a transform: one spare slot per 16 elements, so
+// that the strided writes of the Stockham stages spread over the banks.
+constexpr int kBstLds = kBstMaxLen + kBstMaxLen / 16;
+__device__ __forceinline__ int lds_at(int i) { return i + (i >> 4); }
 
 __host__ __device__ inline int bst_pow2_at_least(int v) {
   int L = 1;
@@ -74,18 +74,91 @@ __global__ void bst_twiddle_kernel(float2* tw, int L) {
   tw[m] = make_float2((float)cospi(a), (float)sinpi(a));
 }
 
-// Stockham transform of length n (a power of two, <= 4 * 4 * blockDim.x) in
-// one LDS buffer: one radix-2 stage when log2 n is odd, then radix-4 stages
-// (Govindaraju et al. 2008); each stage reads its inputs into registers, waits
-// for the block, then writes its outputs.  SIGN -1: forward
-// (exp(-2 pi i ...)), +1: inverse without the 1/n.  tw: the full table of
-// length tl (a multiple of n).  Every thread of the block takes part.
+// Stockham transform of length n (a power of two, <= 4096) in one LDS buffer
+// (Govindaraju et al. 2008): radix-16 stages, each thread holding one
+// 16-point butterfly in registers (a 4 x 4 decomposition with constant inner
+// twiddles), after one radix-2 and/or one radix-4 stage for the remaining
+// factor of n; each stage reads its inputs into registers, waits for the
+// block, then writes its outputs.  SIGN -1: forward (exp(-2 pi i ...)), +1:
+// inverse without the 1/n.  tw: the full table of length tl (a multiple of
+// n).  Every thread of the block takes part.
 constexpr int kFftPerThread = kBstMaxLen / 4 / kMaxBlock;   // radix-4 butterflies
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+// SIGN i a
+template <int SIGN>
+__device__ __forceinline__ float2 cmul_i(float2 a) {
+  return SIGN > 0 ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// 4-point DFT with root SIGN i, in place.
+template <int SIGN>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  const float2 t2 = cadd(a1, a3), t3 = cmul_i<SIGN>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a1 = cadd(t1, t3);
+  a2 = csub(t0, t2);
+  a3 = csub(t1, t3);
+}
+
+// 16-point DFT with root exp(SIGN 2 pi i / 16), in place and in natural
+// order: inputs n = 4 n1 + n2, outputs k = k1 + 4 k2.
+template <int SIGN>
+__device__ __forceinline__ void dft16(float2 v[16]) {
+  // cos and sin of m pi / 8
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508977f;
+  constexpr float h = 0.70710678118654752f;
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<SIGN>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+  // v[4 k1 + n2] now holds the k1 output of column n2; times W^(n2 k1)
+  auto w16 = [](int m) {
+    float c, sn;
+    switch (m) {
+      case 1: c = c1; sn = s1; break;
+      case 2: c = h; sn = h; break;
+      case 3: c = s1; sn = c1; break;
+      case 4: c = 0.0f; sn = 1.0f; break;
+      case 6: c = -h; sn = h; break;
+      default: c = -c1; sn = -s1; break;   // m = 9
+    }
+    return make_float2(c, SIGN > 0 ? sn : -sn);
+  };
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) v[4 * k1 + n2] = cmul(v[4 * k1 + n2], w16(n2 * k1));
+  float2 y[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+    dft4<SIGN>(a0, a1, a2, a3);
+    y[k1] = a0;
+    y[k1 + 4] = a1;
+    y[k1 + 8] = a2;
+    y[k1 + 12] = a3;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = y[r];
+}
+
+template <int SIGN>
+__device__ __forceinline__ float2 twiddle(const float2* tw, int m) {
+  float2 w = tw[m];
+  if (SIGN > 0) w.y = -w.y;
+  return w;
+}
 
 template <int SIGN>
 __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
   int Ns = 1;
-  if (__builtin_ctz(n) & 1) {                      // radix-2 stage
+  const int lg = __builtin_ctz(n);
+  if (lg & 1) {                                    // radix-2 stage
     float2 v[2 * kFftPerThread][2];
 #pragma unroll
     for (int u = 0; u < 2 * kFftPerThread; ++u) {
@@ -100,14 +173,14 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
     for (int u = 0; u < 2 * kFftPerThread; ++u) {
       const int j = threadIdx.x + u * kMaxBlock;
       if (j < n / 2) {
-        x[lds_at(2 * j)] = make_float2(v[u][0].x + v[u][1].x, v[u][0].y + v[u][1].y);
-        x[lds_at(2 * j + 1)] = make_float2(v[u][0].x - v[u][1].x, v[u][0].y - v[u][1].y);
+        x[lds_at(2 * j)] = cadd(v[u][0], v[u][1]);
+        x[lds_at(2 * j + 1)] = csub(v[u][0], v[u][1]);
       }
     }
     __syncthreads();
     Ns = 2;
   }
-  for (; Ns < n; Ns <<= 2) {
+  if (lg & 2) {                                    // radix-4 stage
     const int stride = tl / (4 * Ns);
     float2 v[kFftPerThread][4];
 #pragma unroll
@@ -124,28 +197,34 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
       const int j = threadIdx.x + u * kMaxBlock;
       if (j < n / 4) {
         const int k = j & (Ns - 1);
-        float2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
-        if (SIGN > 0) {
-          w1.y = -w1.y;
-          w2.y = -w2.y;
-          w3.y = -w3.y;
-        }
-        const float2 v0 = v[u][0];
-        const float2 v1 = cmul(v[u][1], w1);
-        const float2 v2 = cmul(v[u][2], w2);
-        const float2 v3 = cmul(v[u][3], w3);
-        const float2 a0 = make_float2(v0.x + v2.x, v0.y + v2.y);
-        const float2 a1 = make_float2(v0.x - v2.x, v0.y - v2.y);
-        const float2 a2 = make_float2(v1.x + v3.x, v1.y + v3.y);
-        const float2 b = make_float2(v1.x - v3.x, v1.y - v3.y);
-        // SIGN i b
-        const float2 ib = SIGN > 0 ? make_float2(-b.y, b.x) : make_float2(b.y, -b.x);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) v[u][r] = cmul(v[u][r], twiddle<SIGN>(tw, r * k * stride));
+        dft4<SIGN>(v[u][0], v[u][1], v[u][2], v[u][3]);
         const int d = ((j - k) << 2) + k;
-        x[lds_at(d)] = make_float2(a0.x + a2.x, a0.y + a2.y);
-        x[lds_at(d + Ns)] = make_float2(a1.x + ib.x, a1.y + ib.y);
-        x[lds_at(d + 2 * Ns)] = make_float2(a0.x - a2.x, a0.y - a2.y);
-        x[lds_at(d + 3 * Ns)] = make_float2(a1.x - ib.x, a1.y - ib.y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[lds_at(d + r * Ns)] = v[u][r];
       }
+    }
+    __syncthreads();
+    Ns *= 4;
+  }
+  for (; Ns < n; Ns <<= 4) {                       // radix-16 stages
+    const int stride = tl / (16 * Ns);
+    const int j = threadIdx.x;                     // n / 16 <= blockDim.x
+    float2 v[16];
+    if (j < n / 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = x[lds_at(j + r * (n / 16))];
+    }
+    __syncthreads();
+    if (j < n / 16) {
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<SIGN>(tw, r * k * stride));
+      dft16<SIGN>(v);
+      const int d = ((j - k) << 4) + k;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[lds_at(d + r * Ns)] = v[r];
     }
     __syncthreads();
   }
