@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kMaxBlock) void tomo_backproject_kernel(BpKernelArg
   for (int m = 0; m < kBpPerLane; ++m) acc[m] = 0.0f;
   for (int kc = 0; kc < a.na; kc += kBpChunk) {
     const int nk = min(kBpChunk, a.na - kc);
-    if (threadIdx.x < nk) {
+    if ((int)threadIdx.x < nk) {
       const int k = kc + threadIdx.x;
       const double c = a.trig[2 * k], s = a.trig[2 * k + 1];
       const double ur = xr * c + yr * s;

@@ -17,7 +17,6 @@ from dataclasses import dataclass
 
 import torch
 
-from . import _lib
 from ._lib import Coeffs, Params, Result, Shape, call
 
 WS_ALIGN = 256

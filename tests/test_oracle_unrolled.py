@@ -2,7 +2,6 @@
 import math
 
 import numpy as np
-import pytest
 
 import oracle
 from oracle.unrolled import unrolled_backward_batch, unrolled_forward_batch
