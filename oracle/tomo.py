@@ -291,15 +291,21 @@ def bst_lengths(H: int, W: int, n_det: int):
     return M, Q
 
 
-def bst_spectra(s: np.ndarray, M: int) -> np.ndarray:
+def bst_spectra(s: np.ndarray, M: int, lam: float | None = None) -> np.ndarray:
     """Steps 1-2: K(nu_j) G_k(nu_j) for j = -M/2 .. M/2-1 (row k, column
-    j + M/2), complex128."""
+    j + M/2), complex128.  K = 1/|nu| with the origin rule, or with lam the
+    kernel 1/(1 + lam |nu|) of the regularised Fourier slice theorem
+    (Section 6, eq. reg_fst): the ramp of the filter F_lam cancels 1/|nu|, so
+    the BST of these spectra is B F_lam g, the regularised FBP (eq. reg_sol)."""
     s = np.asarray(s, dtype=np.float64)
     n_angles, n_det = s.shape
     t = detector(n_det)
     nu = (np.arange(M) - M // 2) / M
     G = s @ np.exp(-2j * np.pi * np.outer(t, nu))          # plain DFT
-    K = np.where(nu == 0.0, float(M), 1.0 / np.where(nu == 0.0, 1.0, np.abs(nu)))
+    if lam is None:
+        K = np.where(nu == 0.0, float(M), 1.0 / np.where(nu == 0.0, 1.0, np.abs(nu)))
+    else:
+        K = 1.0 / (1.0 + lam * np.abs(nu))
     return G * K[None, :]
 
 
@@ -339,11 +345,12 @@ def bst_cartesian(P: np.ndarray, Q: int) -> np.ndarray:
     return np.where(rho <= 0.5, F, 0.0)
 
 
-def bst(s: np.ndarray, H: int, W: int) -> np.ndarray:
-    """B s (= dtheta A^T s up to the method's interpolation) by the BST."""
+def bst(s: np.ndarray, H: int, W: int, lam: float | None = None) -> np.ndarray:
+    """B s (= dtheta A^T s up to the method's interpolation) by the BST; with
+    lam the regularised FBP B F_lam s through the same steps (fbp_bst)."""
     s = np.asarray(s, dtype=np.float64)
     M, Q = bst_lengths(H, W, s.shape[1])
-    F = bst_cartesian(bst_spectra(s, M), Q)
+    F = bst_cartesian(bst_spectra(s, M, lam), Q)
     f = (np.arange(Q) - Q // 2) / Q
     x = np.arange(W) + 0.5 - W / 2.0
     y = np.arange(H) + 0.5 - H / 2.0
@@ -351,3 +358,13 @@ def bst(s: np.ndarray, H: int, W: int) -> np.ndarray:
     Ex = np.exp(2j * np.pi * np.outer(f, x))   # [p, x]
     Ey = np.exp(2j * np.pi * np.outer(y, f))   # [y, q]
     return np.real(Ey @ F @ Ex) / (Q * Q)
+
+
+def fbp_bst(s: np.ndarray, H: int, W: int, lam: float) -> np.ndarray:
+    """The regularised FBP f_lam = B F_lam s (Section 6, eq. reg_sol) with B
+    computed by the BST: the spectra times 1/(1 + lam |nu|) (eq. reg_fst),
+    gridded and inverted as in bst().  Equals fbp() up to the interpolation
+    of the polar samples."""
+    if not lam >= 0.0:
+        raise ValueError("lam must be >= 0")
+    return bst(s, H, W, float(lam))

@@ -170,6 +170,12 @@ CASES = [
      [pin(T_tomo.test_bst_of_a_disc_at_its_centre)]),
     ("bst-inverse-mirrored", tomo, "bst", "np.outer(f, x))", "np.outer(f, -x))",
      [BST_BP]),
+    ("fbp-bst-kernel", tomo, "bst_spectra", "1.0 / (1.0 + lam * np.abs(nu))",
+     "1.0 / (1.0 + lam * nu * nu)",
+     [pin(T_tomo.test_fbp_through_the_bst_matches_the_exact_backprojection)]),
+    ("fbp-bst-dc", tomo, "bst_spectra", "1.0 / (1.0 + lam * np.abs(nu))",
+     "np.where(nu == 0.0, 0.0, 1.0 / (1.0 + lam * np.abs(nu)))",
+     [pin(T_tomo.test_fbp_through_the_bst_keeps_the_mass_and_reconstructs)]),
 ]
 
 
