@@ -302,7 +302,8 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 def bench_tomo(dev):
     """Reconstruction of a 2048^2 slice from 1000 projections of 2048 rays
     (TV regulariser): 20 iterations of the primal-dual method, the two
-    operators on their own, the regularised filtered backprojection and the
+    operators on their own, the regularised filtered backprojection with the
+    exact backprojection and through the slice theorem, and the
     backprojection by the slice theorem."""
     import torch
     import paper_1608_03589_amd as tv
@@ -330,6 +331,8 @@ def bench_tomo(dev):
     ms_fbp, _ = timed(lambda: solver.fbp(gt, 0.0, back), stream, 5)
     solver.bst(gt, back)
     ms_bst, _ = timed(lambda: solver.bst(gt, back), stream, 5)
+    solver.fbp_bst(gt, 0.0, back)
+    ms_fbp_bst, _ = timed(lambda: solver.fbp_bst(gt, 0.0, back), stream, 5)
 
     def run():
         solver.init()
@@ -339,7 +342,8 @@ def bench_tomo(dev):
     pairs = H * W * na
     e = solver.energy(gt, lam, "tv")
     log(f"tomo: {ms / iters:.3f} ms per iteration, A {ms_radon:.3f} ms, "
-        f"A^T {ms_bp:.3f} ms, regularised FBP {ms_fbp:.3f} ms, BST {ms_bst:.3f} ms")
+        f"A^T {ms_bp:.3f} ms, regularised FBP {ms_fbp:.3f} ms, BST {ms_bst:.3f} ms, "
+        f"regularised FBP through the BST {ms_fbp_bst:.3f} ms")
     tf_bp = pairs * TOMO_FLOPS_BP / (ms_bp * 1e-3) / 1e12
     tf_proj = pairs * TOMO_FLOPS_PROJ / (ms_radon * 1e-3) / 1e12
     return {
@@ -354,6 +358,7 @@ def bench_tomo(dev):
         "backproject_ms": ms_bp,
         "fbp_ms": ms_fbp,
         "bst_backproject_ms": ms_bst,
+        "fbp_bst_ms": ms_fbp_bst,
         "gpairs_per_s_radon": pairs / (ms_radon * 1e-3) / 1e9,
         "gpairs_per_s_backproject": pairs / (ms_bp * 1e-3) / 1e9,
         "roofline": {

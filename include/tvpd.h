@@ -449,6 +449,19 @@ int tvpd_bst_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes);
 /* img = BST backprojection of g (device [n_angles][n_det] -> [ny][nx]). */
 int tvpd_bst_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
                          void* ws, size_t ws_bytes, void* stream);
+/* Regularised filtered backprojection f_lam = B F_lam g (Section 6, eq.
+ * reg_sol) with B computed by the BST: the steps of tvpd_bst_backproject with
+ * K(nu) = 1/(1 + lam |nu|) in the second step, because the Fourier transform
+ * of F_lam g on a line is G(nu) |nu| / (1 + lam |nu|) and the theorem divides
+ * by |nu| (eq. reg_fst).  The kernel is finite at nu = 0, so no origin rule
+ * enters and the mean of the image is kept.  g: device [n_angles][n_det];
+ * img: device [ny][nx], overwritten; ws: the BST workspace
+ * (tvpd_bst_workspace_size), caller-owned; nothing is allocated.  lam >= 0
+ * and finite, else TVPD_ERR_INVALID_ARG; lam = 0 is the plain ramp-filtered
+ * backprojection (eq. reg_fbp with lam = 0).  The same length limits as
+ * tvpd_bst_backproject.  Asynchronous on `stream`. */
+int tvpd_fbp_bst(const tvpd_tomo_geom* geom, const float* g, float lam, float* img,
+                 void* ws, size_t ws_bytes, void* stream);
 /* The polar samples of the second step, spec[k][j + M/2] = K(nu_j) G_k(nu_j)
  * for nu_j = j / M, j = -M/2 .. M/2-1 (device, complex as interleaved
  * float pairs, [n_angles][M][2]). */

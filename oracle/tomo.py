@@ -360,6 +360,21 @@ def bst(s: np.ndarray, H: int, W: int, lam: float | None = None) -> np.ndarray:
     return np.real(Ey @ F @ Ex) / (Q * Q)
 
 
+def bst_at(s: np.ndarray, H: int, W: int, rows, cols, lam: float | None = None) -> np.ndarray:
+    """bst(s, H, W, lam)[rows[j], cols[j]]: the same grid F, with the inverse
+    DFT evaluated at the listed pixels only (for images too large for the
+    dense transform matrices of bst())."""
+    s = np.asarray(s, dtype=np.float64)
+    M, Q = bst_lengths(H, W, s.shape[1])
+    F = bst_cartesian(bst_spectra(s, M, lam), Q)
+    f = (np.arange(Q) - Q // 2) / Q
+    x = np.asarray(cols, dtype=np.float64) + 0.5 - W / 2.0
+    y = np.asarray(rows, dtype=np.float64) + 0.5 - H / 2.0
+    Fx = F @ np.exp(2j * np.pi * np.outer(f, x))            # [q, j]: sum over p
+    Ey = np.exp(2j * np.pi * np.outer(y, f))                # [j, q]
+    return np.real(np.sum(Ey * Fx.T, axis=1)) / (Q * Q)
+
+
 def fbp_bst(s: np.ndarray, H: int, W: int, lam: float) -> np.ndarray:
     """The regularised FBP f_lam = B F_lam s (Section 6, eq. reg_sol) with B
     computed by the BST: the spectra times 1/(1 + lam |nu|) (eq. reg_fst),

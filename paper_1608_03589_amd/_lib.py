@@ -129,6 +129,7 @@ SIGNATURES = {
     "tvpd_bst_workspace_size": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_SZ)]),
     "tvpd_bst_backproject": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
     "tvpd_bst_spectra": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
+    "tvpd_fbp_bst": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _P, _P, _SZ, _P]),
     "tvpd_tomo_solve": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,
                                   _P, _P, _SZ, _P]),
 }

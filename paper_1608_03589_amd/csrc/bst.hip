@@ -16,10 +16,15 @@
 //      of the grid rows fused with step 3 (of which only the nx pixel
 //      columns are kept), a transpose of those columns, and their
 //      transforms (of which only the ny pixel rows are read).
+// The regularised filtered backprojection f_lam = B F_lam g (Section 6, eq.
+// reg_sol) runs the same steps with K(nu) = 1/(1 + lam |nu|) in step 2: the
+// ramp |nu| of the filter F_lam cancels the 1/|nu| of the theorem (eq.
+// reg_fst), which leaves a kernel with no singularity at the origin.
 // The transforms are radix-16 Stockham FFTs in LDS (lengths up to 4096; a
 // radix-2 and/or radix-4 stage for the remaining factor; a padded LDS layout
 // against bank conflicts), with twiddles from a float64 table.  Every phase is reduced as an exact integer
 // before its sine and cosine.
+#include <cfloat>
 #include <cmath>
 
 #include "tomo.h"
@@ -231,10 +236,12 @@ __device__ void fft_lds(float2* x, int n, const float2* tw, int tl) {
 }
 
 // Steps 1-2 for projection k: spec[k][m + M/2] = K(nu) exp(-2 pi i nu t_0) DFT(g_k)
-// at nu = m / M, m = -M/2 .. M/2-1.
+// at nu = m / M, m = -M/2 .. M/2-1.  lam < 0: the backprojection kernel
+// K = 1/|nu| (M at nu = 0); lam >= 0: K = 1/(1 + lam |nu|), the ramp of the
+// regularised filter cancelled against 1/|nu| (Section 6, eq. reg_fst).
 __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, float2* spec,
                                                                 const float2* tw, int nd,
-                                                                int M, int tl) {
+                                                                int M, int tl, float lam) {
   __shared__ float2 x[kBstLds];
   const int k = blockIdx.x;
   const float* gr = g + (int64_t)k * nd;
@@ -261,7 +268,9 @@ __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, 
     if (ph < 0) ph += 2 * (int64_t)M;
     float sn, cs;
     sincospif((float)ph / (float)M, &sn, &cs);
-    const float kk = ms == 0 ? (float)M : (float)M / (float)(ms < 0 ? -ms : ms);
+    const int am = ms < 0 ? -ms : ms;
+    const float kk = lam < 0.0f ? (am == 0 ? (float)M : (float)M / (float)am)
+                                : 1.0f / fmaf(lam, (float)am / (float)M, 1.0f);
     const float2 v = cmul(x[lds_at(m)], make_float2(cs, sn));
     out[ms + M / 2] = make_float2(v.x * kk, v.y * kk);
   }
@@ -418,15 +427,52 @@ int ws_check(const BstLayout& L, const void* ws, size_t bytes) {
   return TVPD_OK;
 }
 
-// Steps 1-2 into the workspace's spectra.
-int spectra(const BstLayout& L, const float* g, char* base, hipStream_t s) {
+// Steps 1-2 into the workspace's spectra (lam as in bst_spectra_kernel).
+int spectra(const BstLayout& L, const float* g, char* base, float lam, hipStream_t s) {
   const int tl = L.M > L.Q ? L.M : L.Q;
   float2* tw = reinterpret_cast<float2*>(base + L.off_tw);
   bst_twiddle_kernel<<<(tl + 255) / 256, 256, 0, s>>>(tw, tl);
   BST_TRY(launched());
   bst_spectra_kernel<<<L.na, kMaxBlock, 0, s>>>(
-      g, reinterpret_cast<float2*>(base + L.off_spec), tw, L.nd, L.M, tl);
+      g, reinterpret_cast<float2*>(base + L.off_spec), tw, L.nd, L.M, tl, lam);
   return launched();
+}
+
+// Steps 3-4: the spectra in the workspace to the image.
+int grid_inverse(const BstLayout& L, char* base, float* img, hipStream_t s) {
+  const int tl = L.M > L.Q ? L.M : L.Q;
+  const float2* tw = reinterpret_cast<const float2*>(base + L.off_tw);
+  float2* A = reinterpret_cast<float2*>(base + L.off_a);
+  float2* B = reinterpret_cast<float2*>(base + L.off_b);
+  // rows of the grid: step 3 and the transforms along x, keeping the nx
+  // pixel columns (A: Q rows of nx)
+  bst_cartesian_rows_kernel<<<L.Q, kMaxBlock, 0, s>>>(
+      reinterpret_cast<const float2*>(base + L.off_spec), A, tw, L.na, L.M, L.Q, L.nx, L.ny,
+      tl);
+  BST_TRY(launched());
+  // the pixel columns as rows (B: nx rows of Q), transformed along y
+  bst_transpose_kernel<<<dim3((L.nx + 31) / 32, L.Q / 32), dim3(32, 8), 0, s>>>(A, B, L.Q,
+                                                                                L.nx);
+  BST_TRY(launched());
+  bst_rows_inverse_kernel<<<L.nx, kMaxBlock, 0, s>>>(B, tw, L.Q, tl);
+  BST_TRY(launched());
+  bst_extract_kernel<<<dim3((L.nx + 31) / 32, (L.ny + 31) / 32), dim3(32, 8), 0, s>>>(
+      B, img, L.Q, L.ny, L.nx, (float)(1.0 / ((double)L.Q * (double)L.Q)));
+  return launched();
+}
+
+// The whole pipeline from g to img with the spectra's kernel chosen by lam.
+int run_bst(const tvpd_tomo_geom* geom, const float* g, float* img, float lam, void* ws,
+            size_t ws_bytes, void* stream) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!g || !img) return TVPD_ERR_INVALID_ARG;
+  const BstLayout L = bst_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  BST_TRY(supported(L));
+  BST_TRY(ws_check(L, ws, ws_bytes));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  BST_TRY(spectra(L, g, base, lam, s));
+  return grid_inverse(L, base, img, s);
 }
 
 }  // namespace
@@ -463,7 +509,7 @@ int tvpd_bst_spectra(const tvpd_tomo_geom* geom, const float* g, float* spec, vo
   BST_TRY(ws_check(L, ws, ws_bytes));
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  BST_TRY(spectra(L, g, base, s));
+  BST_TRY(spectra(L, g, base, -1.0f, s));
   if (hipMemcpyAsync(spec, base + L.off_spec, 8 * (size_t)L.na * L.M, hipMemcpyDeviceToDevice,
                      s) != hipSuccess)
     return TVPD_ERR_HIP;
@@ -472,33 +518,13 @@ int tvpd_bst_spectra(const tvpd_tomo_geom* geom, const float* g, float* spec, vo
 
 int tvpd_bst_backproject(const tvpd_tomo_geom* geom, const float* g, float* img, void* ws,
                          size_t ws_bytes, void* stream) {
-  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
-  if (!g || !img) return TVPD_ERR_INVALID_ARG;
-  const BstLayout L = bst_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
-  BST_TRY(supported(L));
-  BST_TRY(ws_check(L, ws, ws_bytes));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
-  const int tl = L.M > L.Q ? L.M : L.Q;
-  float2* tw = reinterpret_cast<float2*>(base + L.off_tw);
-  float2* A = reinterpret_cast<float2*>(base + L.off_a);
-  float2* B = reinterpret_cast<float2*>(base + L.off_b);
-  BST_TRY(spectra(L, g, base, s));
-  // rows of the grid: step 3 and the transforms along x, keeping the nx
-  // pixel columns (A: Q rows of nx)
-  bst_cartesian_rows_kernel<<<L.Q, kMaxBlock, 0, s>>>(
-      reinterpret_cast<const float2*>(base + L.off_spec), A, tw, L.na, L.M, L.Q, L.nx, L.ny,
-      tl);
-  BST_TRY(launched());
-  // the pixel columns as rows (B: nx rows of Q), transformed along y
-  bst_transpose_kernel<<<dim3((L.nx + 31) / 32, L.Q / 32), dim3(32, 8), 0, s>>>(A, B, L.Q,
-                                                                                L.nx);
-  BST_TRY(launched());
-  bst_rows_inverse_kernel<<<L.nx, kMaxBlock, 0, s>>>(B, tw, L.Q, tl);
-  BST_TRY(launched());
-  bst_extract_kernel<<<dim3((L.nx + 31) / 32, (L.ny + 31) / 32), dim3(32, 8), 0, s>>>(
-      B, img, L.Q, L.ny, L.nx, (float)(1.0 / ((double)L.Q * (double)L.Q)));
-  return launched();
+  return run_bst(geom, g, img, -1.0f, ws, ws_bytes, stream);
+}
+
+int tvpd_fbp_bst(const tvpd_tomo_geom* geom, const float* g, float lam, float* img, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (!(lam >= 0.0f) || !(lam <= FLT_MAX)) return TVPD_ERR_INVALID_ARG;
+  return run_bst(geom, g, img, lam, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

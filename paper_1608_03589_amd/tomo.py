@@ -129,6 +129,21 @@ class TomoSolver:
              C.c_void_p(_stream(self.device)))
         return out
 
+    def fbp_bst(self, s: torch.Tensor, lam: float,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+        """Regularised filtered backprojection B F_lam s with B by the slice
+        theorem: the spectra times 1/(1 + lam |nu|) (Section 6, eq. reg_fst)
+        gridded and inverted as in bst().  lam >= 0."""
+        self._check(s, "sino", (self.n_angles, self.n_det))
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        self._check(out, "out", (self.ny, self.nx))
+        ws, n = self._bst_ws()
+        call("tvpd_fbp_bst", C.byref(self.geom), C.c_void_p(s.data_ptr()), float(lam),
+             C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), n,
+             C.c_void_p(_stream(self.device)))
+        return out
+
     def bst_spectra(self, s: torch.Tensor) -> torch.Tensor:
         """The polar samples K(nu_j) G_k(nu_j), complex64 [n_angles][M]."""
         self._check(s, "sino", (self.n_angles, self.n_det))

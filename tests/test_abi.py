@@ -168,3 +168,31 @@ def test_tomo_validation_without_gpu(L):
     res = (C.c_double * 3)()
     assert L.tvpd_tomo_energy(C.byref(good), dummy, 0.1, 5, dummy, 1 << 40, res,
                               None) == -1
+
+
+def test_bst_validation_without_gpu(L):
+    from paper_1608_03589_amd._lib import TomoGeom
+    good = TomoGeom(64, 48, 30, 90)
+    M, Q = C.c_int32(), C.c_int32()
+    assert L.tvpd_bst_lengths(C.byref(good), C.byref(M), C.byref(Q)) == 0
+    assert (M.value, Q.value) == (256, 128)
+    n = C.c_size_t()
+    assert L.tvpd_bst_workspace_size(C.byref(good), C.byref(n)) == 0
+    # lengths beyond the LDS transforms: n_det 2049 needs M = 8192
+    big = TomoGeom(64, 48, 30, 2049)
+    assert L.tvpd_bst_workspace_size(C.byref(big), C.byref(n)) == -6
+    dummy = C.c_void_p(256)
+    # the regularisation weight is checked first, then shape, pointers and
+    # workspace, all before any HIP call
+    for lam in (-1.0, float("nan"), float("inf"), -1e-30):
+        assert L.tvpd_fbp_bst(C.byref(good), dummy, lam, dummy, dummy, 1 << 40, None) == -1
+    assert L.tvpd_fbp_bst(C.byref(TomoGeom(0, 4, 4, 4)), dummy, 1.0, dummy, dummy, 1 << 40,
+                          None) == -2
+    assert L.tvpd_fbp_bst(C.byref(good), None, 1.0, dummy, dummy, 1 << 40, None) == -1
+    assert L.tvpd_fbp_bst(C.byref(good), dummy, 1.0, None, dummy, 1 << 40, None) == -1
+    assert L.tvpd_fbp_bst(C.byref(good), dummy, 1.0, dummy, None, 1 << 40, None) == -1
+    assert L.tvpd_fbp_bst(C.byref(good), dummy, 1.0, dummy, C.c_void_p(256 + 8), 1 << 40,
+                          None) == -3
+    assert L.tvpd_fbp_bst(C.byref(good), dummy, 1.0, dummy, dummy, 16, None) == -4
+    assert L.tvpd_fbp_bst(C.byref(big), dummy, 1.0, dummy, dummy, 1 << 40, None) == -6
+    assert L.tvpd_bst_backproject(C.byref(good), dummy, dummy, dummy, 16, None) == -4

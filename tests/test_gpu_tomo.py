@@ -285,3 +285,58 @@ def test_bst_at_full_size_against_the_backprojection():
     print(f"constant {d.mean():.4g}, rel after removing it "
           f"{np.linalg.norm(d - d.mean()) / np.linalg.norm(ref):.3e}")
     assert np.linalg.norm(d - d.mean()) / np.linalg.norm(ref) < 0.03
+
+
+@pytest.mark.parametrize("lam", [0.0, 3.5])
+@pytest.mark.parametrize("H,W,na,nd", [(64, 64, 48, 92), (37, 53, 30, 70), (16, 16, 7, 40),
+                                       (200, 120, 100, 300)])
+def test_fbp_bst_matches_the_oracle(H, W, na, nd, lam):
+    print(f"case: fbp_bst {H}x{W} angles {na} bins {nd} lam {lam}", flush=True)
+    rng = np.random.default_rng(H * 11 + nd)
+    s = rng.normal(size=(na, nd)).astype(np.float32)
+    solver = tv.TomoSolver(H, W, na, nd, DEV)
+    b = solver.fbp_bst(to_dev(s), lam).cpu().numpy()
+    ref = tomo.fbp_bst(s.astype(np.float64), H, W, lam)
+    print(f"fbp_bst rel {rel(b, ref):.2e} max {maxrel(b, ref):.2e}")
+    assert rel(b, ref) <= RTOL and maxrel(b, ref) <= 2 * RTOL
+    # the same workspace serves the plain BST afterwards
+    bb = solver.bst(to_dev(s)).cpu().numpy()
+    assert rel(bb, tomo.bst(s.astype(np.float64), H, W)) <= RTOL
+
+
+def test_bst_and_fbp_bst_at_full_size_sampled():
+    # 2048^2 from 1000 projections of 2048 rays: 40 pixels (corners, centre,
+    # random) of both BST pipelines against the oracle's grid evaluated there
+    w, H, W, na, nd = _full_size()
+    print(f"case: bst/fbp_bst {H}x{W} angles {na} bins {nd} (sampled)", flush=True)
+    img, clean, _ = scenes.tomo_scene(H, W, na, nd, w["n_ellipses"], 0.0, w["seed"])
+    c32 = clean.astype(np.float32)
+    g = to_dev(c32)
+    solver = tv.TomoSolver(H, W, na, nd, DEV)
+    rng = np.random.default_rng(12)
+    rows = np.concatenate(([0, 0, H - 1, H - 1, H // 2, 777, 1500, 31], rng.integers(0, H, 32)))
+    cols = np.concatenate(([0, W - 1, 0, W - 1, W // 2, 1201, 300, 2000],
+                           rng.integers(0, W, 32)))
+    for lam in (None, 0.0, 10.0):
+        out = solver.bst(g) if lam is None else solver.fbp_bst(g, lam)
+        out = out.cpu().numpy().astype(np.float64)
+        ref = tomo.bst_at(c32.astype(np.float64), H, W, rows, cols, lam)
+        err = np.max(np.abs(out[rows, cols] - ref)) / np.max(np.abs(out))
+        print(f"lam {lam}: max error / max |image| {err:.2e}", flush=True)
+        assert err <= 2 * RTOL
+        if lam == 0.0:
+            # the mass of the projections is kept (no origin rule), and the
+            # phantom is reconstructed
+            assert abs(out.sum() / clean[0].sum() - 1.0) < 0.01
+            on = img > 0.05
+            assert abs(float(np.median(out[on] / img[on])) - 1.0) < 0.03
+            assert np.linalg.norm(out - img) / np.linalg.norm(img) < 0.15
+        if lam == 10.0:
+            # against the FBP with the exact backprojection, up to its lost
+            # mean: the difference is the bilinear interpolation in angle
+            # (1000 angles are 6.4 grid cells apart at the highest frequencies)
+            ex = solver.fbp(g, lam).cpu().numpy().astype(np.float64)
+            d = out - ex
+            r = np.linalg.norm(d - d.mean()) / np.linalg.norm(ex)
+            print(f"against the exact backprojection: rel after the mean {r:.3e}")
+            assert r < 0.07

@@ -176,6 +176,11 @@ CASES = [
     ("fbp-bst-dc", tomo, "bst_spectra", "1.0 / (1.0 + lam * np.abs(nu))",
      "np.where(nu == 0.0, 0.0, 1.0 / (1.0 + lam * np.abs(nu)))",
      [pin(T_tomo.test_fbp_through_the_bst_keeps_the_mass_and_reconstructs)]),
+    ("bst-at-axes-swapped", tomo, "bst_at", "x = np.asarray(cols", "x = np.asarray(rows",
+     [pin(T_tomo.test_sampled_bst_equals_the_whole_image, None)]),
+    ("bst-at-conjugate", tomo, "bst_at", "np.exp(2j * np.pi * np.outer(y, f))",
+     "np.exp(-2j * np.pi * np.outer(y, f))",
+     [pin(T_tomo.test_sampled_bst_equals_the_whole_image, None)]),
 ]
 
 

@@ -436,3 +436,18 @@ def test_fbp_through_the_bst_keeps_the_mass_and_reconstructs():
     assert np.linalg.norm(b - img) / np.linalg.norm(img) < 0.15
     with pytest.raises(ValueError):
         tomo.fbp_bst(clean, N, N, -1.0)
+
+
+@pytest.mark.parametrize("lam", [None, 0.0, 2.5])
+def test_sampled_bst_equals_the_whole_image(lam):
+    # bst_at evaluates the inverse DFT of the same grid at listed pixels
+    # (rows and columns of a non-square image in arbitrary order, repeats
+    # included)
+    H, W, na, nd = 20, 13, 11, 30
+    s = np.random.default_rng(4).normal(size=(na, nd))
+    full = tomo.bst(s, H, W, lam)
+    rows = np.array([0, 19, 7, 7, 3, 12, 19, 0])
+    cols = np.array([12, 0, 5, 6, 12, 1, 12, 0])
+    got = tomo.bst_at(s, H, W, rows, cols, lam)
+    np.testing.assert_allclose(got, full[rows, cols], rtol=0,
+                               atol=1e-12 * np.max(np.abs(full)))
