@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
   BatchHdr* h = a.hdr;
   unsigned gen = __hip_atomic_load(&sync_of(h)->gen.v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_in_block();
   const int nw = gridDim.x * a.wpb;
   const int gw = blockIdx.x * a.wpb + wave;
   int k = 0;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a,
   if (k + n > a.max_iter) return;
   const int nact = h->n_active;
   if (nact == 0) return;
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_in_block();
   const int nw = gridDim.x * a.wpb;
   const int gw = blockIdx.x * a.wpb + wave;
   if (wave < a.wpb)

@@ -15,6 +15,14 @@ constexpr int kMaxBlock = 256;          // threads per block (4 waves)
 constexpr size_t kHeaderBytes = 4096;   // state header at the workspace start
 constexpr size_t kAlign = 256;
 
+// Index of the calling wave in its block as a wave-uniform value.  The
+// compiler cannot prove threadIdx.x / 64 uniform, so tile coordinates and
+// descriptors derived from it would be kept in vector registers (one copy
+// per lane) and the loops bounded by them would be treated as divergent.
+__device__ __forceinline__ int wave_in_block() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+}
+
 // Solver state kept in device memory at the start of a workspace.  Kernels
 // read k to find the ring slots of the iterates they read and write; the
 // last block of every sweep advances k (or freezes it on convergence) and

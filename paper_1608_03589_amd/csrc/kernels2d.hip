@@ -22,6 +22,8 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
   const int k = st->k;
   if (st->converged || k + S > st->k_end) return;
   const float tau_prev = st->tau_prev;
+  // (not wave_in_block(): with uniform tile coordinates the compiler's
+  // schedule of the depth-5 walk needs more than 256 registers)
   const int wave = threadIdx.x / kWave;
   // Blocks are dispatched round-robin over the 8 XCDs; hand each XCD a
   // contiguous run of tiles so that vertically adjacent bands (which share

@@ -142,19 +142,28 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
   // row t and, for stage s < S, fbar^{k+s} of its previous row (fbh[s]).
   // Stage s < S: f^{k+s} and p^{k+s} of its previous row (fo1, po1x, po1y).
   // Every stage: p_y^{k+s} of its previous row (cy).
+  // (Index S of fbh, fo1, po1x, po1y is never written: it stands for the
+  // outputs of a stage S that the ramp-up below skips.)
   F4 lf1 = zero4(), lp1x = zero4(), lp1y = zero4(), lp2y = zero4();
-  F4 gh[S], fbh[S];
-  F4 fo1[S], po1x[S], po1y[S], cy[S + 1];
+  F4 gh[S], fbh[S + 1];
+  F4 fo1[S + 1], po1x[S + 1], po1y[S + 1], cy[S + 1];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    gh[s] = fbh[s] = zero4();
-    fo1[s] = po1x[s] = po1y[s] = zero4();
+  for (int s = 0; s < S; ++s) gh[s] = zero4();
+#pragma unroll
+  for (int s = 0; s <= S; ++s) {
+    fbh[s] = fo1[s] = po1x[s] = po1y[s] = cy[s] = zero4();
   }
-#pragma unroll
-  for (int s = 0; s <= S; ++s) cy[s] = zero4();
 
-  // One walk step: L holds the loads of row t+1.
-  auto step = [&](auto edge_tag, int t, const XsLoad& L) {
+  // Ramp-up.  Stage s is needed on rows [y0-S+s-1, y1+S-s-1]: f^{k+s} on
+  // [y0-(S-s), y1+(S-s)) and p^{k+s} one row further up, for the divergence
+  // of the row below.  It reaches the first of them at step tb + 2s - 1, so
+  // during the first 2S - 1 steps only the stages s <= (t - tb + 1) / 2 run;
+  // the others would compute rows that nothing reads (S^2 stage-rows per
+  // band).  A skipped stage leaves its histories as they are.
+  auto ramp = [&](int t) { return min(S, (t - tb + 1) >> 1); };
+
+  // One walk step: L holds the loads of row t+1; stages 1..m run.
+  auto step = [&](auto edge_tag, int t, const XsLoad& L, auto m) {
     constexpr bool kEdge = decltype(edge_tag)::value;
     // fb[s]: fbar^{k+s} on row t-s+1 (stage s+1's next row); fb[0] from the
     // loads of row t+1
@@ -162,6 +171,13 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
     fbar_loaded(edge_tag, t + 1, L, lp1y, fb[0]);
 #pragma unroll
     for (int s = 1; s <= S; ++s) {
+      if (s > m) {
+        fo[s] = fo1[s];
+        fb[s] = fbh[s];
+        pox[s] = po1x[s];
+        poy[s] = cy[s];
+        continue;
+      }
       const int r = t - (s - 1);           // row of stage s
       const bool dn = !kEdge || r + 1 < ny;
       // inputs of stage s (see the header)
@@ -288,18 +304,28 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
   XsLoad X, Y, Z;
   load(tb + 1, X);
   load(tb + 2, Y);
+  constexpr std::integral_constant<int, S> kAll{};
   auto run = [&](auto edge) {
     int t = tb;
+    for (; t + 2 <= te && t < tb + 2 * S - 1; t += 3) {
+      load(t + 3, Z);
+      step(edge, t, X, ramp(t));
+      load(t + 4, X);
+      step(edge, t + 1, Y, ramp(t + 1));
+      load(t + 5, Y);
+      step(edge, t + 2, Z, ramp(t + 2));
+    }
     for (; t + 2 <= te; t += 3) {
       load(t + 3, Z);
-      step(edge, t, X);
+      step(edge, t, X, kAll);
       load(t + 4, X);
-      step(edge, t + 1, Y);
+      step(edge, t + 1, Y, kAll);
       load(t + 5, Y);
-      step(edge, t + 2, Z);
+      step(edge, t + 2, Z, kAll);
     }
-    if (t <= te) step(edge, t, X);
-    if (t + 1 <= te) step(edge, t + 1, Y);
+    // (a walk shorter than the ramp-up runs every stage on its last steps)
+    if (t <= te) step(edge, t, X, kAll);
+    if (t + 1 <= te) step(edge, t + 1, Y, kAll);
   };
   if constexpr (SPLIT) {
     if (interior)
@@ -307,18 +333,27 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
     else
       run(std::true_type{});
   } else {
-    // the same loop written out: inside a lambda it costs registers
+    // the same loops written out: inside a lambda they cost registers
+    constexpr std::true_type kE{};
     int t = tb;
+    for (; t + 2 <= te && t < tb + 2 * S - 1; t += 3) {
+      load(t + 3, Z);
+      step(kE, t, X, ramp(t));
+      load(t + 4, X);
+      step(kE, t + 1, Y, ramp(t + 1));
+      load(t + 5, Y);
+      step(kE, t + 2, Z, ramp(t + 2));
+    }
     for (; t + 2 <= te; t += 3) {
       load(t + 3, Z);
-      step(std::true_type{}, t, X);
+      step(kE, t, X, kAll);
       load(t + 4, X);
-      step(std::true_type{}, t + 1, Y);
+      step(kE, t + 1, Y, kAll);
       load(t + 5, Y);
-      step(std::true_type{}, t + 2, Z);
+      step(kE, t + 2, Z, kAll);
     }
-    if (t <= te) step(std::true_type{}, t, X);
-    if (t + 1 <= te) step(std::true_type{}, t + 1, Y);
+    if (t <= te) step(kE, t, X, kAll);
+    if (t + 1 <= te) step(kE, t + 1, Y, kAll);
   }
 }
 

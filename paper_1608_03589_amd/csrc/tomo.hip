@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kMaxBlock) void tomo_backproject_kernel(BpKernelArg
 __global__ __launch_bounds__(kMaxBlock) void tomo_fbp_taps_kernel(float* hs, int nd, int L,
                                                                   double lam) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int n = blockIdx.x * (kMaxBlock / kWave) + threadIdx.x / kWave;
+  const int n = blockIdx.x * (kMaxBlock / kWave) + wave_in_block();
   if (n >= nd) return;                       // whole waves
   double acc = 0.0;
   for (int m = 1 + lane; m < L / 2; m += kWave) {

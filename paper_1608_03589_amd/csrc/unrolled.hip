@@ -151,6 +151,8 @@ __global__ __launch_bounds__(kMaxBlock) void u_sweep2d_xs_kernel(
     PlaneSet P, PassIds ids, const float* __restrict__ coeffs, int k,
     float theta, int th_rows, int wpb, int ntx, int nty) {
   const int b = blockIdx.y;
+  // (not wave_in_block(): with uniform tile coordinates the compiler's
+  // schedule of the depth-5 walk needs more than 256 registers)
   const int wave = threadIdx.x / kWave;
   const int nbx = gridDim.x, bx = blockIdx.x;
   const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(kMaxBlock) void u_sweep3d_kernel(
     PlaneSet P, StepIds ids, const float* __restrict__ coeffs, int k,
     float theta, int tz, int wpb, int ntx, int nty, int ntiles) {
   const int b = blockIdx.y;
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_in_block();
   const int nbx = gridDim.x, bx = blockIdx.x;
   const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
   const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(kMaxBlock) void u_adj2d_kernel(
     double* __restrict__ pa, double* __restrict__ pb) {
   __shared__ double red[2][kMaxBlock / kWave];
   const int b = blockIdx.y;
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_in_block();
   const int nbx = gridDim.x, bx = blockIdx.x;
   const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
   const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(kMaxBlock) void u_adj3d_kernel(
   constexpr int TH = 2;
   __shared__ double red[2][kMaxBlock / kWave];
   const int b = blockIdx.y;
-  const int wave = threadIdx.x / kWave;
+  const int wave = wave_in_block();
   const int nbx = gridDim.x, bx = blockIdx.x;
   const int q8 = nbx >> 3, r8 = nbx & 7, xcd = bx & 7;
   const int bt = xcd * q8 + min(xcd, r8) + (bx >> 3);
