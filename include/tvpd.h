@@ -231,7 +231,9 @@ int tvpd_tune_load(const char* cache_path, int32_t* count);
  * autotuned or default value); wpb: waves per block (0 = autotuned or
  * default, else 1, 2 or 4); th_short: rows per band of the second tile
  * table, used once the running images no longer fill the grid (0 = default
- * 8; at most th). */
+ * 8; at most th); two more tables halve the band (at least 1 row) and take
+ * over as images stop, whenever their tiles still fit the grid's waves.  The
+ * tiling never changes the iterates. */
 typedef struct tvpd_batch_opts {
   int32_t mode;
   int32_t th;
@@ -239,7 +241,9 @@ typedef struct tvpd_batch_opts {
   int32_t th_short;
 } tvpd_batch_opts;
 
-/* Workspace bytes for a batch of n shapes (host arrays; ndim must be 2). */
+/* Workspace bytes for a batch of n shapes (host arrays; ndim must be 2).
+ * TVPD_ERR_UNSUPPORTED when the tile tables would need more than 2^31 - 1
+ * entries (4 per image row and 256-column strip). */
 int tvpd_batch_workspace_size(int32_t n, const tvpd_shape* shapes,
                               size_t* bytes);
 

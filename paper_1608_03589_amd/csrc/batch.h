@@ -7,13 +7,15 @@ namespace tvpd {
 
 constexpr int kBatchErrBarrier = 1;  // a grid barrier wait ran out
 constexpr int kBatchStopped = 2;     // an image stopped at the last check
+// Tile tables: tall bands, then bands of 8, 4 and 2 rows (by default).
+constexpr int kBatchTables = 4;
 
 // Per-image description (device, read-only during a solve).
 struct ImgDesc {
   int64_t off;       // float offset of the image's plane block in the arena
   int64_t plane;     // floats per plane
   int32_t ny, nx, pitch;
-  int32_t tile_first[2], tile_count[2];  // per tile table
+  int32_t tile_first[kBatchTables], tile_count[kBatchTables];  // per table
   float lam, tau, sigma, theta;
   double tol;        // relative gap tolerance (< 0: never stop)
 };
@@ -37,7 +39,7 @@ struct BatchHdr {
   int32_t k;             // iteration of the running images
   int32_t n_active;      // entries of the active tile list
   int32_t flags;         // error bits
-  int32_t table;         // tile table in use: 0 tall bands, 1 short bands
+  int32_t table;         // tile table in use: 0 tall bands, then shorter ones
 };
 
 struct BatchArgs {

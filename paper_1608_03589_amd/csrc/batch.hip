@@ -151,21 +151,29 @@ __device__ void reduce_image(const BatchArgs& a, int i, int k, int tbl,
   __syncthreads();
 }
 
+// Tiles of table `tbl` over the images that still run.
+__device__ int running_tiles(const BatchArgs& a, int tbl) {
+  int n = 0;
+  for (int i = 0; i < a.nimg; ++i)
+    if (!a.state[i].converged) n += a.imgs[i].tile_count[tbl];
+  return n;
+}
+
 // Rebuild the active tile list from the images that still run (one block).
 // Once fewer tall-band tiles than waves remain, switch for good to the
-// short-band table: the iterates do not depend on the tiling, and short
-// bands keep the GPU busy while only a few images are left.
+// first short-band table, and from there to a table of shorter bands
+// whenever its tiles still fit the waves: the iterates do not depend on the
+// tiling, and a shorter band is a shorter serial walk for its wave, which
+// is what a pass costs while only a few images are left.
 __device__ void compact_active(const BatchArgs& a) {
   __shared__ int s_pos;
   __shared__ int s_tbl;
   if (threadIdx.x == 0) {
     int tbl = a.hdr->table;
-    if (tbl == 0) {
-      int n0 = 0;
-      for (int i = 0; i < a.nimg; ++i)
-        if (!a.state[i].converged) n0 += a.imgs[i].tile_count[0];
-      if (n0 < a.switch_tiles) tbl = 1;
-    }
+    if (tbl == 0 && running_tiles(a, 0) < a.switch_tiles) tbl = 1;
+    while (tbl >= 1 && tbl + 1 < kBatchTables &&
+           running_tiles(a, tbl + 1) <= a.switch_tiles)
+      ++tbl;
     a.hdr->table = tbl;
     s_tbl = tbl;
     s_pos = 0;

@@ -47,8 +47,9 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
     L.img_plane.push_back(plane);
     L.img_off.push_back(arena);
     arena += kPlainPlanes2D * plane;
-    // both tile tables together hold at most two tiles per (strip, row)
-    L.tmax += 2 * (int64_t)((s[i].nx + kBatchStrip - 1) / kBatchStrip) * s[i].ny;
+    // each tile table holds at most ny tiles per strip (bands of >= 1 row)
+    L.tmax += (int64_t)((s[i].nx + kBatchStrip - 1) / kBatchStrip) *
+              kBatchTables * s[i].ny;
   }
   size_t o = kHeaderBytes;
   L.off_imgs = o;
@@ -110,8 +111,9 @@ struct BatchSetup {
   int ntiles;
 };
 
-// Rows per band of the short-band table (a band walk of a pass of n
-// iterations covers 2n-1 extra rows, so very short bands waste work).
+// Rows per band of the first short-band table; the later ones halve it
+// (a band walk of a pass of n iterations covers 2n extra rows, so short
+// bands pay off only once few images are left).
 constexpr int kShortBand = 8;
 
 void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
@@ -123,9 +125,12 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   int64_t* offs = reinterpret_cast<int64_t*>(h + L.off_offs);
   TileDesc* tiles = reinterpret_cast<TileDesc*>(h + L.off_tiles);
   int32_t* active = reinterpret_cast<int32_t*>(h + L.off_active);
-  const int ths[2] = {th, std::min(th, th_short > 0 ? th_short : kShortBand)};
+  int ths[kBatchTables];
+  ths[0] = th;
+  ths[1] = std::min(th, th_short > 0 ? th_short : kShortBand);
+  for (int j = 2; j < kBatchTables; ++j) ths[j] = std::max(1, ths[j - 1] / 2);
   int t = 0;
-  for (int tbl = 0; tbl < 2; ++tbl) {
+  for (int tbl = 0; tbl < kBatchTables; ++tbl) {
     for (int i = 0; i < n; ++i) {
       ImgDesc& D = imgs[i];
       D.tile_first[tbl] = t;
@@ -142,7 +147,6 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
       D.tile_count[tbl] = t - D.tile_first[tbl];
     }
   }
-  int n0 = 0;
   for (int i = 0; i < n; ++i) {
     ImgDesc& D = imgs[i];
     D.off = L.img_off[i];
@@ -156,10 +160,16 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
     D.theta = prm[i].c.theta;
     D.tol = prm[i].gap_tol;
     offs[i] = offsets[i];
-    n0 += D.tile_count[0];
   }
-  // start on the short bands when the tall ones cannot fill the grid
-  const int tbl0 = n0 < nwaves ? 1 : 0;
+  // start on short bands when the tall ones cannot fill the grid (the rule
+  // of compact_active)
+  auto tiles_of = [&](int tbl) {
+    int c = 0;
+    for (int i = 0; i < n; ++i) c += imgs[i].tile_count[tbl];
+    return c;
+  };
+  int tbl0 = tiles_of(0) < nwaves ? 1 : 0;
+  while (tbl0 >= 1 && tbl0 + 1 < kBatchTables && tiles_of(tbl0 + 1) <= nwaves) ++tbl0;
   int na = 0;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < imgs[i].tile_count[tbl0]; ++j)
@@ -295,6 +305,7 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
                        int mode, int th, int th_short, int wpb, void* ws,
                        size_t ws_bytes, tvpd_result* res, hipStream_t s) {
   const BatchLayout L = make_batch_layout(n, shapes);
+  if (L.tmax > INT32_MAX) return TVPD_ERR_UNSUPPORTED;  // tile indices are int32
   if (!ws) return TVPD_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
   if (ws_bytes < L.bytes) return TVPD_ERR_WORKSPACE;
@@ -374,7 +385,9 @@ int tvpd_batch_workspace_size(int32_t n, const tvpd_shape* shapes,
                               size_t* bytes) {
   if (!bytes) return TVPD_ERR_INVALID_ARG;
   if (!shapes_ok(n, shapes)) return TVPD_ERR_SHAPE;
-  *bytes = make_batch_layout(n, shapes).bytes;
+  const BatchLayout L = make_batch_layout(n, shapes);
+  if (L.tmax > INT32_MAX) return TVPD_ERR_UNSUPPORTED;  // tile indices are int32
+  *bytes = L.bytes;
   return TVPD_OK;
 }
 

@@ -196,3 +196,17 @@ def test_bst_validation_without_gpu(L):
     assert L.tvpd_fbp_bst(C.byref(good), dummy, 1.0, dummy, dummy, 16, None) == -4
     assert L.tvpd_fbp_bst(C.byref(big), dummy, 1.0, dummy, dummy, 1 << 40, None) == -6
     assert L.tvpd_bst_backproject(C.byref(good), dummy, dummy, dummy, 16, None) == -4
+
+
+def test_batch_workspace_size_bounds_the_tile_tables(L):
+    from paper_1608_03589_amd._lib import Shape
+    n = C.c_size_t()
+    ok = (Shape * 2)(Shape(2, 1, 300, 700), Shape(2, 1, 17, 5))
+    assert L.tvpd_batch_workspace_size(2, ok, C.byref(n)) == 0
+    # the arena alone: 4 planes of 300 x 700 and of 17 x 8 (pitch) floats
+    assert n.value > 4 * 4 * (300 * 700 + 17 * 8)
+    # 4 tile tables of one entry per row and 256-column strip must fit int32
+    big = (Shape * 1)(Shape(2, 1, 1 << 20, 1 << 20))
+    assert L.tvpd_batch_workspace_size(1, big, C.byref(n)) == -6
+    assert L.tvpd_batch_workspace_size(0, ok, C.byref(n)) == -2
+    assert L.tvpd_batch_workspace_size(2, ok, None) == -1
