@@ -19,7 +19,8 @@ __global__ __launch_bounds__(kMaxBlock) void sweep3d_kernel(Sweep3DArgs a) {
   DevState* st = a.st;
   const int k = st->k;
   if (st->converged || k >= st->k_end) return;
-  const int wave = wave_in_block();
+  // (not wave_in_block(): measured 2-3 % slower in the 3D kernels)
+  const int wave = threadIdx.x / kWave;
   // each XCD (blocks dispatched round-robin over 8) gets a contiguous run of
   // tiles: neighbouring bands and segments share halo rows in its L2
   const int nb = gridDim.x, b = blockIdx.x;
