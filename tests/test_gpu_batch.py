@@ -174,3 +174,31 @@ def test_batch64_workload():
     fr, _, _ = oracle.run_fixed(g64, w["lam"], S2, S2, rs[i].iters)
     err = np.linalg.norm(fs[i].cpu().numpy() - fr) / np.linalg.norm(fr)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["persistent", "graph"])
+def test_batch_table_switches_do_not_change_iterates(mode):
+    """The 64-image workload stopping image by image, so that the driver
+    moves from the tall bands through the 8-, 4- and 2-row tables (or the
+    halvings of another first short band) while the images stop: every
+    tiling gives the same stopping iterations and the same iterates bit for
+    bit."""
+    w = WORKLOADS["batch64_uneven"]
+    data = batch_scenes(w["n"], w["seed"], w["n_shapes"])
+    gts = [torch.from_numpy(d[1].astype(np.float32)).to(DEV) for d in data]
+    b = tv.BatchedSolver([tuple(g.shape) for g in gts], DEV)
+    ref = None
+    for th, th_short in [(32, 8), (16, 4), (24, 3), (64, 1)]:
+        print(f"case: batch64 {mode} th={th} th_short={th_short}", flush=True)
+        fs, rs = b.solve(gts, lam=w["lam"], max_iter=w["max_iter"],
+                         check_every=w["check_every"], gap_tol=w["gap_tol"],
+                         mode=mode, th=th, wpb=4, th_short=th_short)
+        out = ([f.cpu().numpy().copy() for f in fs], [r.iters for r in rs])
+        assert all(r.converged for r in rs)
+        if ref is None:
+            ref = out
+            assert len(set(out[1])) > 10   # many stopping iterations
+        else:
+            assert out[1] == ref[1]
+            for a, c in zip(out[0], ref[0]):
+                assert np.array_equal(a, c)
