@@ -176,6 +176,11 @@ CASES = [
     ("fbp-bst-dc", tomo, "bst_spectra", "1.0 / (1.0 + lam * np.abs(nu))",
      "np.where(nu == 0.0, 0.0, 1.0 / (1.0 + lam * np.abs(nu)))",
      [pin(T_tomo.test_fbp_through_the_bst_keeps_the_mass_and_reconstructs)]),
+    ("bst-kernel-squared", tomo, "bst_spectra",
+     "1.0 / np.where(nu == 0.0, 1.0, np.abs(nu))", "1.0 / np.where(nu == 0.0, 1.0, nu * nu)",
+     [pin(T_tomo.test_bst_spectra_of_a_disc_follow_example_ii, None)]),
+    ("bst-dft-sign-example-ii", tomo, "bst_spectra", "np.exp(-2j", "np.exp(2j",
+     [pin(T_tomo.test_bst_spectra_of_a_disc_follow_example_ii, 2.5)]),
     ("bst-at-axes-swapped", tomo, "bst_at", "x = np.asarray(cols", "x = np.asarray(rows",
      [pin(T_tomo.test_sampled_bst_equals_the_whole_image, None)]),
     ("bst-at-conjugate", tomo, "bst_at", "np.exp(2j * np.pi * np.outer(y, f))",

@@ -451,3 +451,37 @@ def test_sampled_bst_equals_the_whole_image(lam):
     got = tomo.bst_at(s, H, W, rows, cols, lam)
     np.testing.assert_allclose(got, full[rows, cols], rtol=0,
                                atol=1e-12 * np.max(np.abs(full)))
+
+
+@pytest.mark.parametrize("lam", [None, 0.0, 2.5])
+def test_bst_spectra_of_a_disc_follow_example_ii(lam):
+    # Section 3, Example II: the projections of a disc have the transform of
+    # the disc on every slice, J1(sigma)/sigma for the unit disc, and the
+    # BST's Fourier samples of b are that over |sigma|.  In cycles per pixel,
+    # for a disc of radius R centred at c, the projection at angle theta is
+    # 2 sqrt(R^2 - (t - u0)^2) with u0 = c . xi_theta, and its transform is
+    # G(nu) = exp(-2 pi i nu u0) R J1(2 pi R |nu|) / |nu| (pi R^2 at nu = 0).
+    # The step-2 samples are K(nu) G(nu): K = 1/|nu| (compared after the
+    # factor |nu|, away from the origin rule) or 1/(1 + lam |nu|).  The
+    # remaining difference is the sampling of the projection (its square-root
+    # edge), about 1e-3 of pi R^2; a conjugated phase gives 0.55.
+    from scipy.special import j1
+    R, cx, cy = 30.0, 7.3, -4.1
+    nd, na, M = 256, 3, 512
+    t = tomo.detector(nd)
+    th = tomo.angles(na)
+    u0 = cx * np.cos(th) + cy * np.sin(th)
+    s = 2.0 * np.sqrt(np.maximum(R * R - (t[None, :] - u0[:, None]) ** 2, 0.0))
+    nu = (np.arange(M) - M // 2) / M
+    a = np.abs(nu)
+    G = np.where(a == 0.0, math.pi * R * R,
+                 R * j1(2.0 * math.pi * R * a) / np.where(a == 0.0, 1.0, a))
+    G = G[None, :] * np.exp(-2j * math.pi * np.outer(u0, nu))
+    P = tomo.bst_spectra(s, M, lam)
+    if lam is None:
+        sel = (a > 0.0) & (a <= 0.25)
+        err = np.abs(P[:, sel] * a[sel] - G[:, sel])
+    else:
+        sel = a <= 0.25
+        err = np.abs(P[:, sel] - G[:, sel] / (1.0 + lam * a[sel]))
+    assert err.max() <= 3e-3 * math.pi * R * R
