@@ -181,6 +181,8 @@ CASES = [
      [pin(T_tomo.test_bst_spectra_of_a_disc_follow_example_ii, None)]),
     ("bst-dft-sign-example-ii", tomo, "bst_spectra", "np.exp(-2j", "np.exp(2j",
      [pin(T_tomo.test_bst_spectra_of_a_disc_follow_example_ii, 2.5)]),
+    ("bst-inverse-scale-slice", tomo, "bst", "/ (Q * Q)", "/ (2 * Q * Q)",
+     [pin(T_tomo.test_bst_slice_of_a_disc_follows_the_analytic_backprojection)]),
     ("bst-at-axes-swapped", tomo, "bst_at", "x = np.asarray(cols", "x = np.asarray(rows",
      [pin(T_tomo.test_sampled_bst_equals_the_whole_image, None)]),
     ("bst-at-conjugate", tomo, "bst_at", "np.exp(2j * np.pi * np.outer(y, f))",
