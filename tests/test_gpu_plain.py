@@ -324,3 +324,28 @@ def test_blocked_passes_are_bitwise_equal(shape, tile):
         for ce in (10, 7, 3):
             a, b = out[(depth, "solve", ce)], out[(1, "solve", ce)]
             assert a[1] == b[1] and np.array_equal(a[0], b[0]), (depth, ce)
+
+
+@pytest.mark.parametrize("seed,lam", [(15, 0.3), (16, 0.1)])
+def test_solution_level_against_the_minimiser(seed, lam):
+    """Solution-level parity.  E is 1-strongly convex, so for any feasible
+    pair (f, p) the gap bounds the distance to the unique minimiser:
+    0.5 ||f - u*||^2 <= P(f) - P(u*) <= gap(f, p).  The GPU's iterate after
+    many iterations therefore lies within sqrt(2 gap) of u*, which a generic
+    constrained optimiser finds on the explicit dual problem of an 8x8 image
+    (to about 2e-6 per pixel); the device's own gap of its float32 pair
+    enters the bound."""
+    import pins
+    rng = np.random.default_rng(seed)
+    g32 = rng.normal(size=(8, 8)).astype(np.float32)
+    f_bf, _ = pins.tv2d_bruteforce(g32.astype(np.float64), lam)
+    print(f"case: minimiser 8x8 seed {seed} lam {lam}", flush=True)
+    f, res = tv.PlainSolver(g32.shape, DEV).solve(
+        torch.from_numpy(g32).to(DEV), lam, max_iter=60000, check_every=100,
+        gap_tol=-1.0)
+    d = float(np.linalg.norm(f.cpu().numpy().astype(np.float64) - f_bf))
+    bound = math.sqrt(2.0 * max(res.gap, 0.0)) + 2e-6 * 8
+    print(f"distance {d:.3e}, gap {res.gap:.3e}, bound {bound:.3e}")
+    assert res.gap >= -1e-9 * res.primal
+    assert d <= bound
+    assert d <= 1e-4 * np.linalg.norm(f_bf)   # the bound is not vacuous here
