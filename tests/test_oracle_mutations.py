@@ -183,6 +183,10 @@ CASES = [
      [pin(T_tomo.test_bst_spectra_of_a_disc_follow_example_ii, 2.5)]),
     ("bst-inverse-scale-slice", tomo, "bst", "/ (Q * Q)", "/ (2 * Q * Q)",
      [pin(T_tomo.test_bst_slice_of_a_disc_follows_the_analytic_backprojection)]),
+    ("detector-cell-edges", tomo, "detector", "+ 0.5 - n_det / 2.0", "- n_det / 2.0",
+     [pin(T_tomo.test_sinogram_mesh_follows_the_table_of_symbols)]),
+    ("angles-over-two-pi", tomo, "angles", "(math.pi / n_angles)", "(2.0 * math.pi / n_angles)",
+     [pin(T_tomo.test_sinogram_mesh_follows_the_table_of_symbols)]),
     ("bst-at-axes-swapped", tomo, "bst_at", "x = np.asarray(cols", "x = np.asarray(rows",
      [pin(T_tomo.test_sampled_bst_equals_the_whole_image, None)]),
     ("bst-at-conjugate", tomo, "bst_at", "np.exp(2j * np.pi * np.outer(y, f))",

@@ -516,3 +516,20 @@ def test_bst_spectra_of_a_disc_follow_example_ii(lam):
         sel = a <= 0.25
         err = np.abs(P[:, sel] - G[:, sel] / (1.0 + lam * a[sel]))
     assert err.max() <= 3e-3 * math.pi * R * R
+
+
+def test_sinogram_mesh_follows_the_table_of_symbols():
+    # tests/golden/mesh_symbols.txt: angles k pi / N_theta and detector cell
+    # centres on [-1, 1] with step 2 / N_t (Section 5, table of symbols); the
+    # oracle's detector is in pixel units, the table's values times N_t / 2.
+    import os
+    fn = os.path.join(os.path.dirname(__file__), "golden", "mesh_symbols.txt")
+    rows = [ln.split() for ln in open(fn) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 12
+    for kind, n, i, v in rows:
+        n, i, v = int(n), int(i), float(v)
+        if kind == "angle":
+            assert abs(tomo.angles(n)[i] - v) <= 1e-15
+            assert len(tomo.angles(n)) == n
+        else:
+            assert abs(tomo.detector(n)[i] - v * n / 2.0) <= 1e-12
