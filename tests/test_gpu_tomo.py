@@ -287,10 +287,11 @@ def test_bst_at_full_size_against_the_backprojection():
     assert np.linalg.norm(d - d.mean()) / np.linalg.norm(ref) < 0.03
 
 
-@pytest.mark.parametrize("lam", [0.0, 3.5])
+@pytest.mark.parametrize("lam", [0.0, 3.5, 1e30])
 @pytest.mark.parametrize("H,W,na,nd", [(64, 64, 48, 92), (37, 53, 30, 70), (16, 16, 7, 40),
                                        (200, 120, 100, 300)])
 def test_fbp_bst_matches_the_oracle(H, W, na, nd, lam):
+    # lam = 1e30 leaves only the origin sample (K = 1 there, ~1e-27 elsewhere)
     print(f"case: fbp_bst {H}x{W} angles {na} bins {nd} lam {lam}", flush=True)
     rng = np.random.default_rng(H * 11 + nd)
     s = rng.normal(size=(na, nd)).astype(np.float32)
