@@ -66,7 +66,7 @@ enum {
   TVPD_ERR_ALIGNMENT = -3,   /* workspace not 256-byte aligned */
   TVPD_ERR_WORKSPACE = -4,   /* workspace smaller than required */
   TVPD_ERR_HIP = -5,         /* a HIP runtime call failed */
-  TVPD_ERR_UNSUPPORTED = -6, /* valid request this build does not handle */
+  TVPD_ERR_UNSUPPORTED = -6, /* valid request the library does not handle */
   TVPD_ERR_STEP = -7,        /* tau * sigma * ||grad||^2 >= 1 (or <= 0) */
   TVPD_ERR_DEVICE = -8       /* a device-side check failed (see string) */
 };
