@@ -113,6 +113,15 @@ const char* tvpd_status_string(int status);
 /* Library version as 10000*major + 100*minor + patch. */
 int tvpd_version(void);
 
+/* Release the host resources the calling thread's solver drivers keep
+ * between calls: pinned staging buffers, events and the stream used for
+ * graph capture (tvpd_solve and tvpd_solve_batched create them on their
+ * first call on a device and reuse them).  Call it before the thread or the
+ * process ends, while the HIP runtime is still up; later calls recreate what
+ * they need.  Must not overlap a running solve of the same thread.  Always
+ * returns TVPD_OK. */
+int tvpd_release_thread_resources(void);
+
 /* ---------------------------------------------------------------------
  * Plain solver (one image or volume).
  * ------------------------------------------------------------------- */

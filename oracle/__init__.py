@@ -16,7 +16,7 @@ per image axis, p[0] along x (the last array axis), p[1] along y, p[2] along z.
 Contents
   pdhg      grad / div / projection, one iteration, the stopping rule,
             energies and the duality gap, the quadratic (Tikhonov-gradient)
-            variant, plain and batched solves
+            variant, the plain solve (a batch is solved image by image)
   unrolled  K unrolled iterations with per-iteration (lam, tau, sigma) and the
             reverse-mode adjoint of that unrolled map
   tomo      the tomographic data term: discrete Radon transform and its
@@ -31,7 +31,7 @@ the point-source backprojection (their exact pins are the geometric ones).
 """
 from .pdhg import (  # noqa: F401
     grad, div, project_ball, pdhg_iteration, primal_energy, dual_energy,
-    gap_density, energy_gap, solve, solve_batched, quadratic_iteration,
+    gap_density, energy_gap, solve, quadratic_iteration,
     step_bound, init_state, run_fixed, prox_data,
 )
 from .unrolled import (  # noqa: F401

@@ -249,14 +249,6 @@ def solve(g, lam, tau=None, sigma=None, theta=1.0, max_iter=1000,
     return out
 
 
-def solve_batched(gs, lam, tau=None, sigma=None, theta=1.0, max_iter=1000,
-                  check_every=10, gap_tol=1e-4):
-    """Batch semantics: every image is solved exactly as :func:`solve` would
-    solve it alone, with its own stopping iteration."""
-    return [solve(g, lam, tau, sigma, theta, max_iter, check_every, gap_tol)
-            for g in gs]
-
-
 def run_fixed(g, lam, tau, sigma, n_iter, theta=1.0):
     """n_iter iterations from the initial state; returns (f^n, f^{n-1}, p^n)."""
     f, f_prev, p = init_state(g)

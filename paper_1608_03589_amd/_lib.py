@@ -5,6 +5,7 @@ Loading fails loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -75,6 +76,7 @@ _F = C.c_float
 SIGNATURES = {
     "tvpd_status_string": (C.c_char_p, [C.c_int]),
     "tvpd_version": (C.c_int, []),
+    "tvpd_release_thread_resources": (C.c_int, []),
     "tvpd_workspace_size": (C.c_int, [C.POINTER(Shape), C.POINTER(_SZ)]),
     "tvpd_init": (C.c_int, [C.POINTER(Shape), _P, _P, _SZ, _P]),
     "tvpd_step": (C.c_int, [C.POINTER(Shape), C.POINTER(Coeffs), _I32, _P, _SZ, _P]),
@@ -151,6 +153,9 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = h
+        # pinned buffers, events and the capture stream of the solve drivers
+        # are released while the HIP runtime is still up
+        atexit.register(h.tvpd_release_thread_resources)
     return _lib
 
 

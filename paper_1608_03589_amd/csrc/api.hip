@@ -89,40 +89,45 @@ int ws_ok(const Layout& L, const void* ws, size_t bytes) {
 
 // Per-thread host resources for polling the device convergence flag while
 // the next chunk of iterations is already queued.
-struct Poller {
-  int device = -1;
-  int32_t* host = nullptr;  // pinned, 2 slots of DevState-sized copies
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  hipStream_t capture = nullptr;
-  bool ok = false;
-};
-thread_local Poller t_poll;
+thread_local HostPoll t_poll;
 
-int poller_get(Poller** out) {
+}  // namespace
+
+void host_poll_release(HostPoll& p) {
+  int cur = -1;
+  const bool switch_dev = p.device >= 0 && hipGetDevice(&cur) == hipSuccess &&
+                          cur != p.device &&
+                          hipSetDevice(p.device) == hipSuccess;
+  if (p.capture) (void)hipStreamDestroy(p.capture);
+  for (int i = 0; i < 2; ++i)
+    if (p.ev[i]) (void)hipEventDestroy(p.ev[i]);
+  if (p.host) (void)hipHostFree(p.host);
+  if (switch_dev) (void)hipSetDevice(cur);
+  p = HostPoll{};
+}
+
+int host_poll_get(HostPoll& p, size_t host_bytes) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return TVPD_ERR_HIP;
-  Poller& p = t_poll;
-  if (p.ok && p.device == dev) {
-    *out = &p;
-    return TVPD_OK;
-  }
-  if (p.ok) {
-    // device changed: the old resources belong to another device
-    p.ok = false;
-  }
-  if (hipHostMalloc((void**)&p.host, 2 * sizeof(DevState),
-                    hipHostMallocDefault) != hipSuccess)
-    return TVPD_ERR_HIP;
-  for (int i = 0; i < 2; ++i)
-    if (hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) != hipSuccess)
-      return TVPD_ERR_HIP;
-  if (hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking) != hipSuccess)
-    return TVPD_ERR_HIP;
+  if (p.ok && p.device == dev) return TVPD_OK;
+  host_poll_release(p);
   p.device = dev;
+  bool good = hipHostMalloc(&p.host, host_bytes, hipHostMallocDefault) ==
+              hipSuccess;
+  for (int i = 0; i < 2 && good; ++i)
+    good = hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) ==
+           hipSuccess;
+  good = good && hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking) ==
+                     hipSuccess;
+  if (!good) {
+    host_poll_release(p);
+    return TVPD_ERR_HIP;
+  }
   p.ok = true;
-  *out = &p;
   return TVPD_OK;
 }
+
+namespace {
 
 #define TVPD_HIP(call)                                    \
   do {                                                    \
@@ -194,8 +199,8 @@ namespace {
 int solve_plain(const Layout& L, const float* g, float* f_out,
                 const tvpd_params& prm, void* ws, tvpd_result* res,
                 hipStream_t s) {
-  Poller* poll = nullptr;
-  int rc = poller_get(&poll);
+  HostPoll* poll = &t_poll;
+  int rc = host_poll_get(*poll, 2 * sizeof(DevState));
   if (rc) return rc;
   TVPD_HIP(launch_init(L, g, ws, s));
   TVPD_HIP(launch_set_params(ws, prm.max_iter, prm.gap_tol, s));
@@ -316,6 +321,12 @@ const char* tvpd_status_string(int status) {
 }
 
 int tvpd_version(void) { return kVersion; }
+
+int tvpd_release_thread_resources(void) {
+  host_poll_release(t_poll);
+  release_batch_thread_resources();
+  return TVPD_OK;
+}
 
 int tvpd_workspace_size(const tvpd_shape* shape, size_t* bytes) {
   if (!bytes) return TVPD_ERR_INVALID_ARG;

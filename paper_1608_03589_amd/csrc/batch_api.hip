@@ -196,36 +196,7 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   a.depth = pass_depth() < kBatchMaxPass ? pass_depth() : kBatchMaxPass;
 }
 
-struct PinnedHdr {
-  int device = -1;
-  BatchHdr* host = nullptr;
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  hipStream_t capture = nullptr;
-  bool ok = false;
-};
-thread_local PinnedHdr t_pin;
-
-int pinned_get(PinnedHdr** out) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return TVPD_ERR_HIP;
-  PinnedHdr& p = t_pin;
-  if (p.ok && p.device == dev) {
-    *out = &p;
-    return TVPD_OK;
-  }
-  if (hipHostMalloc((void**)&p.host, 2 * sizeof(BatchHdr),
-                    hipHostMallocDefault) != hipSuccess)
-    return TVPD_ERR_HIP;
-  for (int i = 0; i < 2; ++i)
-    if (hipEventCreateWithFlags(&p.ev[i], hipEventDisableTiming) != hipSuccess)
-      return TVPD_ERR_HIP;
-  if (hipStreamCreateWithFlags(&p.capture, hipStreamNonBlocking) != hipSuccess)
-    return TVPD_ERR_HIP;
-  p.device = dev;
-  p.ok = true;
-  *out = &p;
-  return TVPD_OK;
-}
+thread_local HostPoll t_pin;
 
 // Launches of iterations k0 .. k0+n-1: passes as batch_pass_len schedules
 // them (the same schedule as the persistent driver), a check on the first
@@ -246,8 +217,9 @@ hipError_t enqueue_batch_iters(const BatchArgs& a, int grid, int k0, int n,
 }
 
 int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
-  PinnedHdr* pin = nullptr;
-  if (int rc = pinned_get(&pin)) return rc;
+  HostPoll* pin = &t_pin;
+  if (int rc = host_poll_get(*pin, 2 * sizeof(BatchHdr))) return rc;
+  BatchHdr* hst = static_cast<BatchHdr*>(pin->host);
   const int ce = a.check_every;
   const int chunk = ce > 0 ? ce * ((32 + ce - 1) / ce) : 32;
   // one graph of `chunk` iterations, checks at multiples of check_every
@@ -267,13 +239,14 @@ int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
   int rc = TVPD_OK;
   int64_t launched = 0;
   int slot = 0, inflight = 0;
+  bool all_stopped = false;
   while (launched + chunk <= a.max_iter) {
     if (hipGraphLaunch(exec, s) != hipSuccess) {
       rc = TVPD_ERR_HIP;
       break;
     }
     launched += chunk;
-    if (hipMemcpyAsync(&pin->host[slot], a.hdr, sizeof(BatchHdr),
+    if (hipMemcpyAsync(&hst[slot], a.hdr, sizeof(BatchHdr),
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipEventRecord(pin->ev[slot], s) != hipSuccess) {
       rc = TVPD_ERR_HIP;
@@ -286,12 +259,16 @@ int run_graph_blocks(const BatchArgs& a, int grid, hipStream_t s) {
         break;
       }
       inflight = 1;
-      if (pin->host[prev].n_active == 0) break;
+      if (hst[prev].n_active == 0) {
+        all_stopped = true;
+        break;
+      }
     }
     slot ^= 1;
   }
-  // the last partial block, launched directly (no-ops once all stopped)
-  if (rc == TVPD_OK && launched < a.max_iter &&
+  // the iterations of max_iter beyond the last whole block, launched
+  // directly; none once every image has stopped
+  if (rc == TVPD_OK && !all_stopped && launched < a.max_iter &&
       enqueue_batch_iters(a, grid, (int)launched, (int)(a.max_iter - launched),
                           s) != hipSuccess)
     rc = TVPD_ERR_HIP;
@@ -375,6 +352,9 @@ int batch_args_ok(int n, const tvpd_shape* shapes, const int64_t* offsets,
 }
 
 }  // namespace
+
+void release_batch_thread_resources() { host_poll_release(t_pin); }
+
 }  // namespace tvpd
 
 using namespace tvpd;

@@ -188,4 +188,24 @@ int tune_save3d(const char* path, const tvpd_shape& s, const Tile3D& t,
 int tune_load(const char* path, int* count);
 int pass_depth();         // longest pass in use, 1 .. kMaxPass (api.hip)
 
+// Host resources a driver keeps for polling device state while further work
+// is queued: pinned staging for two copies of a header, two events and a
+// stream for graph capture, all owned by one host thread and created on one
+// device (api.hip).
+struct HostPoll {
+  int device = -1;
+  void* host = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipStream_t capture = nullptr;
+  bool ok = false;
+};
+// Make p hold resources for the current device with `host_bytes` of pinned
+// staging; resources held for another device are released first (with that
+// device current).  On failure everything is released.
+int host_poll_get(HostPoll& p, size_t host_bytes);
+// Release whatever p holds; p is then empty and may be reused.
+void host_poll_release(HostPoll& p);
+// Release the calling thread's batch-driver resources (batch_api.hip).
+void release_batch_thread_resources();
+
 }  // namespace tvpd

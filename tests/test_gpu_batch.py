@@ -14,11 +14,13 @@ import torch
 import oracle
 import paper_1608_03589_amd as tv
 from scenes import WORKLOADS, batch_scenes, scene2d
+from stopcheck import assert_stop_guard
 
 pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
 S2 = 1.0 / math.sqrt(8.0)
+LAM32 = float(np.float32(0.1))   # the device holds lam in float32
 
 SMALL_SHAPES = [(37, 301), (130, 513), (64, 64), (5, 3), (200, 140), (1, 9),
                 (257, 260)]
@@ -36,6 +38,15 @@ def plain(g32, **kw):
     s = tv.PlainSolver(g32.shape, DEV)
     f, r = s.solve(torch.from_numpy(g32).to(DEV), **kw)
     return f.cpu().numpy(), r
+
+
+def plain_state(g32, k):
+    s = tv.PlainSolver(g32.shape, DEV)
+    s.init(torch.from_numpy(g32).to(DEV))
+    if k > 0:
+        s.step(k, 0.1)
+    f, p = s.state()
+    return f.cpu().numpy(), p.cpu().numpy()
 
 
 @pytest.mark.parametrize("mode", ["persistent", "graph", "launches"])
@@ -110,8 +121,12 @@ def test_batch_against_oracle():
     for g, f, r in zip(imgs, fs, rs):
         g64 = g.astype(np.float64)
         ref = oracle.solve(g64, 0.1, S2, S2, max_iter=600, check_every=10,
-                           gap_tol=1e-3)
-        assert abs(r.iters - ref["iters"]) <= 10
+                           gap_tol=1e-3, return_history=True)
+        # the plain solver's iterates stand for the batch's (equal bit for bit,
+        # tested above)
+        assert_stop_guard(ref, g64, LAM32, 1e-3, 10,
+                          lambda k: plain_state(g, k))
+        assert r.iters == ref["iters"]
         fr, _, _ = oracle.run_fixed(g64, 0.1, S2, S2, r.iters)
         err = np.linalg.norm(f.cpu().numpy() - fr) / max(np.linalg.norm(fr), 1e-30)
         assert err <= 1e-5

@@ -14,6 +14,7 @@ import torch
 import oracle
 import paper_1608_03589_amd as tv
 from scenes import WORKLOADS, scene2d
+from stopcheck import assert_stop_guard
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +38,16 @@ def gpu_fixed(g32, n, lam=0.1, tile=None, use_graph=-1):
     f, p = s.state()
     torch.cuda.synchronize()
     return f.cpu().numpy(), p.cpu().numpy(), s
+
+
+def device_state(g32, k, lam, theta=1.0):
+    """(f^k, p^k) of the device's fixed-coefficient iteration from g."""
+    s = tv.PlainSolver(g32.shape, DEV)
+    s.init(torch.from_numpy(g32).to(DEV))
+    if k > 0:
+        s.step(k, lam, None, None, theta)
+    f, p = s.state()
+    return f.cpu().numpy(), p.cpu().numpy()
 
 
 def scene32(H, W, n_shapes, noise, seed):
@@ -162,7 +173,10 @@ def test_solve_stops_like_oracle():
             torch.from_numpy(g32).to(DEV), w["lam"], max_iter=w["iters"],
             check_every=10, gap_tol=1e-4, use_graph=use_graph)
         assert res.converged and ref["converged"]
-        assert abs(res.iters - ref["iters"]) <= 10
+        if use_graph == 0:
+            assert_stop_guard(ref, g64, LAM32, 1e-4, 10,
+                              lambda k: device_state(g32, k, w["lam"]))
+        assert res.iters == ref["iters"]
         hist = {h[0]: h for h in ref["history"]}
         _, P_ref, _, gap_ref = hist[res.iters]
         assert abs(res.primal - P_ref) <= 1e-5 * P_ref

@@ -14,6 +14,7 @@ import torch
 import oracle
 import paper_1608_03589_amd as tv
 from scenes import scene3d
+from stopcheck import assert_stop_guard
 
 pytestmark = pytest.mark.gpu
 
@@ -108,10 +109,21 @@ def test_stopping_matches_oracle():
     _, r = tv.PlainSolver(g32.shape, DEV).solve(
         torch.from_numpy(g32).to(DEV), lam=0.1, max_iter=400, check_every=10,
         gap_tol=1e-3)
-    ref = oracle.solve(g32.astype(np.float64), 0.1, S3, S3, max_iter=400,
-                       check_every=10, gap_tol=1e-3)
+    g64 = g32.astype(np.float64)
+    ref = oracle.solve(g64, 0.1, S3, S3, max_iter=400, check_every=10,
+                       gap_tol=1e-3, return_history=True)
     assert r.converged and ref["converged"]
-    assert abs(r.iters - ref["iters"]) <= 10
+
+    def state_at(k):
+        s = tv.PlainSolver(g32.shape, DEV)
+        s.init(torch.from_numpy(g32).to(DEV))
+        if k > 0:
+            s.step(k, 0.1)
+        f, p = s.state()
+        return f.cpu().numpy(), p.cpu().numpy()
+
+    assert_stop_guard(ref, g64, LAM32, 1e-3, 10, state_at)
+    assert r.iters == ref["iters"]
 
 
 def test_plain_equals_unrolled_forward():

@@ -317,3 +317,48 @@ def test_unrolled_256cube_properties():
     # mass conservation of the forward
     assert abs(f64.sum().item() - gt.double().sum().item()) <= 1e-5 * gt.double().abs().sum().item()
     assert peak < 12.0
+
+
+def test_unrolled_256cube_corner_windows_against_the_oracle():
+    """The 3D workload in its own launch configuration (256^3, K = 100,
+    checkpoint every 10) against the oracle on crops.  One iteration couples a
+    voxel only to voxels at most one step away along each axis, so f^K on a
+    window of side w at a corner of the volume depends only on the crop of side
+    w + K + 1 at that corner, whose three outer faces are the volume's own
+    boundary.  For the gradient, dL/df^K is supported on the window: the
+    adjoint of iteration k then reaches at most w + K - k voxels deep, while
+    the crop's forward state of iteration k is exact up to c - k - 1 voxels
+    deep, so on the same crop dL/dg and the coefficient gradients are those of
+    the full volume."""
+    w = WORKLOADS["unrolled_256cube"]
+    clean, noisy = scene3d(w["D"], w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    g = noisy[None].astype(np.float32)
+    K, ck, win = w["K"], w["ckpt_every"], 8
+    c = K + win + 2
+    coeffs = coeffs_for(K, 3, 16, spread=0.1)
+    print(f"case: unrolled 256^3 K={K} ckpt={ck} corner windows {win}, crops {c}",
+          flush=True)
+    solver = tv.UnrolledSolver(g.shape, K, ck, 1.0, DEV)
+    gt, ct = torch.from_numpy(g).to(DEV), torch.from_numpy(coeffs).to(DEV)
+    f = solver.forward(gt, ct)
+    grad_f = torch.zeros_like(f)
+    grad_f[0, :win, :win, :win] = 1.0 / win ** 3
+    gg, gc = solver.backward(ct, grad_f)
+    torch.cuda.synchronize()
+    f, gg, gc = f[0].cpu().numpy(), gg[0].cpu().numpy(), gc.cpu().numpy()
+    c64 = coeffs.astype(np.float64)
+    g64 = g[0].astype(np.float64)
+    hi = g64[-c:, -c:, -c:]
+    f_hi = oracle.unrolled_forward(hi, c64)
+    print("oracle forward at the far corner done", flush=True)
+    assert rel(f[-win:, -win:, -win:], f_hi[-win:, -win:, -win:]) <= 1e-5
+    lo = g64[:c, :c, :c]
+    gf_lo = np.zeros_like(lo)
+    gf_lo[:win, :win, :win] = 1.0 / win ** 3
+    f_lo = oracle.unrolled_forward(lo, c64)
+    assert rel(f[:win, :win, :win], f_lo[:win, :win, :win]) <= 1e-5
+    gg_ref, gc_ref = oracle.unrolled_backward(lo, c64, gf_lo)
+    print("oracle backward at the near corner done", flush=True)
+    assert rel(gg[:c - 1, :c - 1, :c - 1], gg_ref[:c - 1, :c - 1, :c - 1]) <= 1e-4
+    assert np.all(gg[c:, :, :] == 0) and np.all(gg[:, c:, :] == 0) and np.all(gg[:, :, c:] == 0)
+    assert rel(gc, gc_ref) <= 1e-4
