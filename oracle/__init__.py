@@ -21,7 +21,10 @@ Contents
             reverse-mode adjoint of that unrolled map
   tomo      the tomographic data term: discrete Radon transform and its
             adjoint backprojection, the primal-dual iteration for
-            1/2 ||A f - g||^2 + TV or Tikhonov regulariser, energies, ||A||^2
+            1/2 ||A f - g||^2 + TV or Tikhonov regulariser, energies, ||A||^2,
+            the regularised FBP and the backprojection slice theorem
+  logpolar  the log-polar backprojection (Andersson's convolution formula,
+            the four-step algorithm of the paper's Section 5)
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, exact finite algorithms or brute force (see the test

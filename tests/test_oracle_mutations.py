@@ -17,15 +17,17 @@ import textwrap
 import pytest
 
 import oracle
+import oracle.logpolar as logpolar
 import oracle.pdhg as pdhg
 import oracle.tomo as tomo
 import oracle.unrolled as unrolled
+import test_oracle_logpolar as T_lp
 import test_oracle_operators as T_ops
 import test_oracle_solver as T_sol
 import test_oracle_tomo as T_tomo
 import test_oracle_unrolled as T_unr
 
-MODULES = (oracle, pdhg, tomo, unrolled)
+MODULES = (oracle, pdhg, tomo, unrolled, logpolar)
 
 
 def mutant(module, name, old, new):
@@ -192,6 +194,50 @@ CASES = [
     ("bst-at-conjugate", tomo, "bst_at", "np.exp(2j * np.pi * np.outer(y, f))",
      "np.exp(-2j * np.pi * np.outer(y, f))",
      [pin(T_tomo.test_sampled_bst_equals_the_whole_image, None)]),
+    # --- log-polar backprojection ------------------------------------------------
+    ("lp-mesh-first-form", logpolar, "mesh", "math.log(0.5 / R)", "math.log(1.0 / R)",
+     [pin(T_lp.test_mesh_matches_the_papers_example)]),
+    ("lp-mesh-step", logpolar, "mesh", "ds = 2.0 / n_det", "ds = 1.0 / n_det",
+     [pin(T_lp.test_mesh_steps_and_ends, 128, 128, 185)]),
+    ("lp-mesh-no-corners", logpolar, "mesh", "max(0.0, math.log(r_max / R))", "0.0",
+     [pin(T_lp.test_mesh_steps_and_ends, 64, 100, 64)]),
+    ("lp-conv-no-padding", logpolar, "conv_length", "2 * m.n_rho - 1", "m.n_rho",
+     [pin(T_lp.test_convolution_equals_the_direct_sum)]),
+    ("lp-step1-sides-swapped", logpolar, "to_logpolar",
+     "(j, 1.0) if j < n_angles else (j - n_angles, -1.0)",
+     "(j, -1.0) if j < n_angles else (j - n_angles, 1.0)",
+     [pin(T_lp.test_step1_is_exact_for_linear_projections)]),
+    ("lp-step1-bin-origin", logpolar, "to_logpolar", "n_det / 2.0 - 0.5", "n_det / 2.0",
+     [pin(T_lp.test_step1_is_exact_for_linear_projections)]),
+    ("lp-step1-no-zero-beyond", logpolar, "to_logpolar",
+     "np.concatenate(([0.0], s[k], [0.0]))", "np.concatenate(([s[k, 0]], s[k], [s[k, -1]]))",
+     [pin(T_lp.test_step1_is_exact_for_linear_projections)]),
+    ("lp-kernel-root", logpolar, "kernel", "root = -np.log(c[pos])", "root = 1.0 - c[pos]",
+     [pin(T_lp.test_kernel_has_unit_mass_at_the_root)]),
+    ("lp-kernel-height", logpolar, "kernel", "return out / m.drho", "return out",
+     [pin(T_lp.test_kernel_has_unit_mass_at_the_root)]),
+    ("lp-kernel-box", logpolar, "kernel",
+     "np.maximum(0.0, 1.0 - np.abs(a[None, :] - root[:, None]) / m.drho)",
+     "(np.abs(a[None, :] - root[:, None]) <= m.drho).astype(float)",
+     [pin(T_lp.test_kernel_has_unit_mass_at_the_root)]),
+    ("lp-conv-angle-weight", logpolar, "convolve", "m.drho * m.dphi * out", "m.drho * out",
+     [pin(T_lp.test_convolution_equals_the_direct_sum)]),
+    ("lp-conv-correlation", logpolar, "convolve", "np.fft.ifft2(G * Kf)",
+     "np.fft.ifft2(G * np.conj(Kf))",
+     [pin(T_lp.test_convolution_equals_the_direct_sum)]),
+    ("lp-cartesian-axes", logpolar, "to_cartesian", "np.arctan2(Y, X)", "np.arctan2(X, Y)",
+     [pin(T_lp.test_cartesian_step_is_exact_for_bilinear_data)]),
+    ("lp-cartesian-first-node", logpolar, "to_cartesian", "(m.rho0 + m.drho)", "m.rho0",
+     [pin(T_lp.test_cartesian_step_is_exact_for_bilinear_data)]),
+    ("lp-cartesian-weights", logpolar, "to_cartesian",
+     "(1 - wu) * bL[j0, i0] + wu * bL[j0, i0 + 1]",
+     "wu * bL[j0, i0] + (1 - wu) * bL[j0, i0 + 1]",
+     [pin(T_lp.test_cartesian_step_is_exact_for_bilinear_data)]),
+    ("lp-whole-method-angle-mirror", logpolar, "to_logpolar",
+     "ext = np.concatenate(([0.0], s[k], [0.0]))",
+     "ext = np.concatenate(([0.0], s[(n_angles - k) % n_angles], [0.0]))",
+     [pin(T_lp.test_rotation_by_one_angle_step_shifts_the_result),
+      pin(T_lp.test_equals_the_backprojection_without_the_lines_through_the_origin)]),
 ]
 
 
