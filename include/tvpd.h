@@ -68,7 +68,8 @@ enum {
   TVPD_ERR_HIP = -5,         /* a HIP runtime call failed */
   TVPD_ERR_UNSUPPORTED = -6, /* valid request the library does not handle */
   TVPD_ERR_STEP = -7,        /* tau * sigma * ||grad||^2 >= 1 (or <= 0) */
-  TVPD_ERR_DEVICE = -8       /* a device-side check failed (see string) */
+  TVPD_ERR_DEVICE = -8,      /* a device-side check failed (see string) */
+  TVPD_ERR_SCRATCH = -9      /* request larger than a static scratch area */
 };
 
 /* Image or volume shape.  ndim = 2: nz must be 1.  Sizes >= 1. */
@@ -443,6 +444,19 @@ int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
  * Uses the workspace's scratch sinogram only. */
 int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out,
              void* ws, size_t ws_bytes, void* stream);
+
+/* tvpd_fbp without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same result as tvpd_fbp, bit for bit (the same
+ * kernels); g and f_out as there.  The angle table, the filter taps and the
+ * filtered sinogram live in a static device array of 32 MiB that the library
+ * holds on each device it runs on until the process ends; the call allocates
+ * nothing.  Limit: n_angles * n_det <= 8093696 (TVPD_ERR_SCRATCH beyond), the
+ * other limits as for tvpd_fbp.  Every call on one device shares that array:
+ * calls that overlap in time on one device (other streams or threads) race
+ * and must be serialised by the caller. */
+int tvpd_fbp_noalloc(const tvpd_tomo_geom* geom, const float* g, float lam,
+                     float* f_out, void* stream);
 
 /* Fast backprojection by the backprojection slice theorem (Section 3, eq.
  * bst; the algorithm of Section 5).  In the cycles convention the 2D Fourier

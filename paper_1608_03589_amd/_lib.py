@@ -17,6 +17,7 @@ STATUS = {
     0: "TVPD_OK", -1: "TVPD_ERR_INVALID_ARG", -2: "TVPD_ERR_SHAPE",
     -3: "TVPD_ERR_ALIGNMENT", -4: "TVPD_ERR_WORKSPACE", -5: "TVPD_ERR_HIP",
     -6: "TVPD_ERR_UNSUPPORTED", -7: "TVPD_ERR_STEP", -8: "TVPD_ERR_DEVICE",
+    -9: "TVPD_ERR_SCRATCH",
 }
 
 
@@ -127,6 +128,7 @@ SIGNATURES = {
     "tvpd_tomo_opnorm": (C.c_int, [C.POINTER(TomoGeom), _I32, _P, _SZ,
                                    C.POINTER(C.c_double), _P]),
     "tvpd_fbp": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _P, _P, _SZ, _P]),
+    "tvpd_fbp_noalloc": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _P, _P]),
     "tvpd_bst_lengths": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_I32), C.POINTER(_I32)]),
     "tvpd_bst_workspace_size": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_SZ)]),
     "tvpd_bst_backproject": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),

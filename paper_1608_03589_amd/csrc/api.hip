@@ -316,6 +316,7 @@ const char* tvpd_status_string(int status) {
     case TVPD_ERR_UNSUPPORTED: return "unsupported request";
     case TVPD_ERR_STEP: return "step sizes violate tau*sigma*||grad||^2 < 1";
     case TVPD_ERR_DEVICE: return "device-side check failed";
+    case TVPD_ERR_SCRATCH: return "request exceeds the static scratch area";
     default: return "unknown status";
   }
 }

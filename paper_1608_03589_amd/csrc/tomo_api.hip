@@ -1,6 +1,7 @@
 // C ABI of the tomographic data term: argument checks, workspace layout and
 // the host side of the iteration (see include/tvpd.h for the semantics).
 #include <cmath>
+#include <mutex>
 
 #include "tomo.h"
 
@@ -149,6 +150,42 @@ int one_iteration(const TomoLayout& L, const TomoPtrs& P, const float* g,
   TOMO_TRY(launch_tomo_backproject(ba, tv ? kBpTV : kBpTikhonov, &P.st->k, I[kTF1],
                                    I[kTF1], I[kTPX1], I[kTPY1], s));
   return launch_tomo_advance(P.st, s);
+}
+
+// Static scratch of tvpd_fbp_noalloc: the angle table (double2 per angle,
+// room for kTomoMaxAngles), the filter taps (room for kTomoMaxSide) and the
+// filtered sinogram (what is left of kNoAllocBytes).  Each device holds its
+// own copy for the life of the process; every call on a device shares it.
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+constexpr size_t kNoAllocTrigOff = 0;
+constexpr size_t kNoAllocTapOff = 65536 * 16;
+constexpr size_t kNoAllocSinoOff = kNoAllocTapOff + 4 * size_t(kTomoMaxSide);
+constexpr size_t kNoAllocSinoFloats = (kNoAllocBytes - kNoAllocSinoOff) / 4;
+static_assert(16 * size_t(kTomoMaxAngles) <= kNoAllocTapOff, "angle table");
+static_assert(kNoAllocSinoOff % 256 == 0, "sinogram alignment");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on each device, looked up once per device
+// with that device current (the symbol's host-side name is not a device
+// address).
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TVPD_ERR_HIP;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return TVPD_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return TVPD_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TVPD_OK;
 }
 
 }  // namespace
@@ -344,6 +381,30 @@ int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out
   TOMO_TRY(launch_tomo_trig(P.trig, L.na, s));
   TOMO_TRY(launch_tomo_fbp_taps(P.fbp, L.nd, lam, s));
   // the factor dtheta of the backprojection goes with the filter
+  TOMO_TRY(launch_tomo_fbp_filter(g, P.sino[kTS], P.fbp, L.na, L.nd,
+                                  (float)(M_PI / (double)L.na), s));
+  return backward(L, P, P.sino[kTS], f_out, s);
+}
+
+int tvpd_fbp_noalloc(const tvpd_tomo_geom* geom, const float* g, float lam,
+                     float* f_out, void* stream) {
+  if (!geom_ok(geom)) return TVPD_ERR_SHAPE;
+  if (!g || !f_out || !(lam >= 0.0f) || !std::isfinite(lam)) return TVPD_ERR_INVALID_ARG;
+  if ((int64_t)geom->n_angles * geom->n_det > (int64_t)kNoAllocSinoFloats)
+    return TVPD_ERR_SCRATCH;
+  void* base = nullptr;
+  TOMO_TRY(scratch_address(&base));
+  char* b = static_cast<char*>(base);
+  const TomoLayout L = tomo_layout(geom->ny, geom->nx, geom->n_angles, geom->n_det);
+  TomoPtrs P{};
+  P.trig = reinterpret_cast<double*>(b + kNoAllocTrigOff);
+  P.fbp = reinterpret_cast<float*>(b + kNoAllocTapOff);
+  P.sino[kTS] = reinterpret_cast<float*>(b + kNoAllocSinoOff);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every scratch word the kernels read is written first in this call: no
+  // clearing is needed
+  TOMO_TRY(launch_tomo_trig(P.trig, L.na, s));
+  TOMO_TRY(launch_tomo_fbp_taps(P.fbp, L.nd, lam, s));
   TOMO_TRY(launch_tomo_fbp_filter(g, P.sino[kTS], P.fbp, L.na, L.nd,
                                   (float)(M_PI / (double)L.na), s));
   return backward(L, P, P.sino[kTS], f_out, s);

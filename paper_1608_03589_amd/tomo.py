@@ -43,6 +43,25 @@ def default_steps(opnorm_sq: float, reg: str = "tv"):
     raise ValueError(reg)
 
 
+def fbp_noalloc(s: torch.Tensor, ny: int, nx: int, lam: float = 0.0,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """The regularised filtered backprojection of TomoSolver.fbp without a
+    workspace: the library keeps its scratch in a static device array
+    (n_angles * n_det <= 8093696).  Calls on one device must not overlap."""
+    _check_image(s, "sino")
+    if s.dim() != 2:
+        raise ValueError("sino must be [n_angles][n_det]")
+    if out is None:
+        out = torch.empty((ny, nx), dtype=torch.float32, device=s.device)
+    _check_image(out, "out")
+    if tuple(out.shape) != (ny, nx):
+        raise ValueError(f"out has shape {tuple(out.shape)}, expected {(ny, nx)}")
+    geom = TomoGeom(ny, nx, s.shape[0], s.shape[1])
+    call("tvpd_fbp_noalloc", C.byref(geom), C.c_void_p(s.data_ptr()), float(lam),
+         C.c_void_p(out.data_ptr()), C.c_void_p(_stream(s.device)))
+    return out
+
+
 class TomoSolver:
     """Reconstruction state for one image shape and scan geometry.
 

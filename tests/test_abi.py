@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported_and_bound(L):
 
 def test_status_strings(L):
     assert L.tvpd_status_string(0) == b"ok"
-    for code in range(-8, 0):
+    for code in range(-9, 0):
         s = L.tvpd_status_string(code)
         assert s and s != b"unknown status"
     assert L.tvpd_status_string(12345) == b"unknown status"
@@ -210,3 +210,12 @@ def test_batch_workspace_size_bounds_the_tile_tables(L):
     assert L.tvpd_batch_workspace_size(1, big, C.byref(n)) == -6
     assert L.tvpd_batch_workspace_size(0, ok, C.byref(n)) == -2
     assert L.tvpd_batch_workspace_size(2, ok, None) == -1
+
+
+def test_noalloc_fbp_refuses_requests_beyond_the_scratch(L):
+    # refused on the host before any device work: runs without a GPU
+    geom = _lib.TomoGeom(16, 16, 4096, 2048)      # 8.4 M bins > 8093696
+    dummy = C.c_void_p(256)
+    assert L.tvpd_fbp_noalloc(C.byref(geom), dummy, C.c_float(0.0), dummy, None) == -9
+    assert L.tvpd_fbp_noalloc(C.byref(geom), None, C.c_float(0.0), dummy, None) == -1
+
