@@ -103,6 +103,10 @@ class UnrolledTV(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_f):
         (coeffs,) = ctx.saved_tensors
+        if ctx.solver is None:
+            raise RuntimeError(
+                "UnrolledTV: a second backward through the same graph is not "
+                "supported (the forward states were released after the first)")
         grad_g, grad_c = ctx.solver.backward(coeffs, grad_f)
         ctx.solver = None  # release the workspace
         return grad_g, grad_c, None, None

@@ -362,3 +362,14 @@ def test_unrolled_256cube_corner_windows_against_the_oracle():
     assert rel(gg[:c - 1, :c - 1, :c - 1], gg_ref[:c - 1, :c - 1, :c - 1]) <= 1e-4
     assert np.all(gg[c:, :, :] == 0) and np.all(gg[:, c:, :] == 0) and np.all(gg[:, :, c:] == 0)
     assert rel(gc, gc_ref) <= 1e-4
+
+
+def test_second_backward_through_the_same_graph_raises():
+    _, g = batch2d(1, 9, 17, seed=730)
+    K = 3
+    coeffs = torch.from_numpy(coeffs_for(K, 2, 17)).to(DEV).requires_grad_(True)
+    gt = torch.from_numpy(g).to(DEV).requires_grad_(True)
+    loss = tv.unrolled_tv(gt, coeffs).square().sum()
+    loss.backward(retain_graph=True)
+    with pytest.raises(RuntimeError, match="second backward"):
+        loss.backward()
