@@ -495,6 +495,60 @@ int tvpd_fbp_bst(const tvpd_tomo_geom* geom, const float* g, float lam, float* i
 int tvpd_bst_spectra(const tvpd_tomo_geom* geom, const float* g, float* spec,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Log-polar backprojection: Andersson's formula (Section 2.1, eq.
+ * and_approach and and_kernel) by the algorithm of Section 5.  In log-polar
+ * coordinates x = R e^rho xi_theta (R = n_det / 2, the detector's half width
+ * as the paper's unit disc) the backprojection is the convolution of the
+ * semi-polar sinogram [g]_L(mu, phi) (2 n_angles rays phi_j = j pi / n_angles
+ * over [0, 2 pi), ray j carrying row j mod n_angles at t = +s for
+ * j < n_angles, at t = -s beyond) with K(a, b) = delta(1 - e^a cos b):
+ *   Step 1  [g]_L at the mesh nodes rho_i = rho_0 + (i + 1) drho, i < N_rho,
+ *           by linear interpolation in t (zero beyond the detector's ends);
+ *   Step 2  the kernel on the lags a_l = l drho: for each angle offset b
+ *           with cos b > 0, weights 1 - |a_l - a*| / drho at the two lags
+ *           around the root a* = -ln cos b (the hat form of eq.
+ *           calc_and_kernel; its weights sum to one);
+ *   Step 3  the convolution, periodic in the angle and linear in rho, by
+ *           FFTs, with the weights drho dphi (dphi = pi / n_angles);
+ *   Step 4  bilinear interpolation in (rho, theta) at the pixel centres
+ *           (pixels nearer the origin than the first node take its value).
+ * Mesh (table of symbols, eq. N_rho with the adaptive rho_0 of "Problem near
+ * the origin"): rho_0 = ln(1 / n_det) (half a pixel from the origin),
+ * N_rho = ceil((rho_top - rho_0) / -ln(1 - 2 / n_det)), drho = (rho_top -
+ * rho_0) / N_rho, rho_top = max(0, ln(r_max / R)) with r_max the farthest
+ * pixel centre.  The result approximates (pi / n_angles) A^T g without the
+ * lines that pass within half a pixel of the origin (a fraction
+ * (2/pi) asin(1 / (2 r)) of the angles at radius r: the method's loss near
+ * the origin).  Limits: n_det >= 4, N_rho <= 8192 (the rho transforms have
+ * length L <= 16384, the smallest power of two >= 2 N_rho - 1) and 2 n_angles
+ * <= 4096 with no prime factor other than 2, 3, 5: TVPD_ERR_UNSUPPORTED
+ * otherwise.  The geometry conventions are those of the tomography calls. */
+
+/* The mesh for `geom` (host outs): N_rho, the ray count 2 n_angles, the
+ * transform length L, rho_0 and drho.  Returns TVPD_ERR_UNSUPPORTED (after
+ * filling the outs) for a geometry beyond the limits. */
+int tvpd_lp_mesh(const tvpd_tomo_geom* geom, int32_t* n_rho, int32_t* n_phi, int32_t* L,
+                 double* rho0, double* drho);
+
+/* Workspace bytes for `geom` (host out): node and twiddle tables, the
+ * kernel's spectrum and the data's ((L/2 + 1) x 2 n_angles complex values
+ * each, rounded up to whole tiles), and [B g]_L (2 n_angles x N_rho floats). */
+int tvpd_lp_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes);
+
+/* Prepare a workspace for `geom`: node and twiddle tables and the kernel's
+ * 2D spectrum (Step 2 and its transforms), once per geometry.  Asynchronous
+ * on `stream`. */
+int tvpd_lp_plan(const tvpd_tomo_geom* geom, void* ws, size_t ws_bytes, void* stream);
+
+/* img = B g by Steps 1-4 (g: device [n_angles][n_det]; img: device
+ * [ny][nx]); lp_out (device, may be NULL) receives [B g]_L as
+ * [2 n_angles][N_rho] floats, ray-major.  The workspace must have been
+ * prepared by tvpd_lp_plan for the same geometry; otherwise img is NaN.
+ * Asynchronous on `stream`. */
+int tvpd_lp_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
+                        float* lp_out, void* ws, size_t ws_bytes, void* stream);
+
 /* tvpd_tomo_init(f0 = NULL) + tvpd_tomo_step(n_iter) + f_out = f^n_iter. */
 int tvpd_tomo_solve(const tvpd_tomo_geom* geom, const float* g,
                     const tvpd_tomo_params* prm, int32_t n_iter, float* f_out,

@@ -134,6 +134,12 @@ SIGNATURES = {
     "tvpd_bst_backproject": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
     "tvpd_bst_spectra": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
     "tvpd_fbp_bst": (C.c_int, [C.POINTER(TomoGeom), _P, _F, _P, _P, _SZ, _P]),
+    "tvpd_lp_mesh": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_I32), C.POINTER(_I32),
+                               C.POINTER(_I32), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]),
+    "tvpd_lp_workspace_size": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_SZ)]),
+    "tvpd_lp_plan": (C.c_int, [C.POINTER(TomoGeom), _P, _SZ, _P]),
+    "tvpd_lp_backproject": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _P, _SZ, _P]),
     "tvpd_tomo_solve": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,
                                   _P, _P, _SZ, _P]),
 }

@@ -174,6 +174,44 @@ class TomoSolver:
              C.c_void_p(_stream(self.device)))
         return out
 
+    # -- log-polar backprojection ----------------------------------------------
+    def lp_mesh(self):
+        """(N_rho, n_phi, L, rho_0, drho) of the log-polar mesh."""
+        n_rho, n_phi, L = C.c_int32(), C.c_int32(), C.c_int32()
+        rho0, drho = C.c_double(), C.c_double()
+        call("tvpd_lp_mesh", C.byref(self.geom), C.byref(n_rho), C.byref(n_phi),
+             C.byref(L), C.byref(rho0), C.byref(drho))
+        return n_rho.value, n_phi.value, L.value, rho0.value, drho.value
+
+    def _lp_ws(self):
+        if getattr(self, "_lp", None) is None:
+            n = C.c_size_t()
+            call("tvpd_lp_workspace_size", C.byref(self.geom), C.byref(n))
+            ws = alloc_workspace(n.value, self.device)
+            call("tvpd_lp_plan", C.byref(self.geom), C.c_void_p(ws.data_ptr()), n.value,
+                 C.c_void_p(_stream(self.device)))
+            self._lp = (ws, n.value)
+        return self._lp
+
+    def logpolar(self, s: torch.Tensor, out: torch.Tensor | None = None,
+                 lp_out: torch.Tensor | None = None) -> torch.Tensor:
+        """B s by the log-polar algorithm (Andersson's convolution formula,
+        Section 2.1; the four steps of Section 5).  lp_out, if given, receives
+        [B s]_L as [2 n_angles][N_rho]."""
+        self._check(s, "sino", (self.n_angles, self.n_det))
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        self._check(out, "out", (self.ny, self.nx))
+        ws, n = self._lp_ws()
+        if lp_out is not None:
+            n_rho, n_phi = self.lp_mesh()[:2]
+            self._check(lp_out, "lp_out", (n_phi, n_rho))
+        call("tvpd_lp_backproject", C.byref(self.geom), C.c_void_p(s.data_ptr()),
+             C.c_void_p(out.data_ptr()),
+             C.c_void_p(lp_out.data_ptr() if lp_out is not None else None),
+             C.c_void_p(ws.data_ptr()), n, C.c_void_p(_stream(self.device)))
+        return out
+
     def opnorm_sq(self, iters: int = 50) -> float:
         """||A||^2 by power iteration on A^T A from the constant image."""
         v = C.c_double()

@@ -219,3 +219,28 @@ def test_noalloc_fbp_refuses_requests_beyond_the_scratch(L):
     assert L.tvpd_fbp_noalloc(C.byref(geom), dummy, C.c_float(0.0), dummy, None) == -9
     assert L.tvpd_fbp_noalloc(C.byref(geom), None, C.c_float(0.0), dummy, None) == -1
 
+
+@pytest.mark.parametrize("H,W,na,nd", [(64, 64, 48, 92), (33, 21, 45, 40), (2048, 2048, 1000, 2048),
+                                       (724, 724, 180, 1024), (5, 7, 1, 4)])
+def test_logpolar_mesh_equals_the_oracle(L, H, W, na, nd):
+    # host-only call: the library's mesh is the oracle's, node for node
+    from oracle import logpolar as lp
+    m = lp.mesh(H, W, na, nd)
+    n_rho, n_phi, Lr = C.c_int32(), C.c_int32(), C.c_int32()
+    rho0, drho = C.c_double(), C.c_double()
+    st = L.tvpd_lp_mesh(C.byref(_lib.TomoGeom(H, W, na, nd)), C.byref(n_rho), C.byref(n_phi),
+                        C.byref(Lr), C.byref(rho0), C.byref(drho))
+    assert st == 0
+    assert (n_rho.value, n_phi.value, Lr.value) == (m.n_rho, m.n_phi, lp.conv_length(m))
+    assert rho0.value == pytest.approx(m.rho0, rel=1e-15)
+    assert drho.value == pytest.approx(m.drho, rel=1e-14)
+
+
+def test_logpolar_limits(L):
+    n = C.c_size_t()
+    # 14 rays: a prime factor 7
+    assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 7, 40)), C.byref(n)) == -6
+    # N_rho beyond 8192
+    assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 8, 4096)), C.byref(n)) == -6
+    assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 8, 3)), C.byref(n)) == -6
+    assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 8, 40)), C.byref(n)) == 0
