@@ -24,7 +24,8 @@ struct ImgDesc {
 struct ImgState {
   int32_t converged;
   int32_t iters;
-  int32_t pad[2];
+  int32_t slot;      // plane slot of the returned iterate once stopped
+  int32_t pad;
   double P, D, gap;
 };
 
@@ -40,6 +41,7 @@ struct BatchHdr {
   int32_t n_active;      // entries of the active tile list
   int32_t flags;         // error bits
   int32_t table;         // tile table in use: 0 tall bands, then shorter ones
+  int32_t slot;          // plane slot of f^k and p^k of the running images
 };
 
 struct BatchArgs {

@@ -71,22 +71,22 @@ __device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
 }
 
 // Sweep one tile by a pass of n iterations k -> k+n (tile2d_xs.h, strips of
-// kBatchStrip owned columns); on check iterations lane 0 stores the tile's
-// partials (the gap of (f^k, p^k)).  Plane block of an image: the plain
-// solver's layout (f ring, dual ring, g).
+// kBatchStrip owned columns), reading the planes of `slot` and writing the
+// other slot's; on check iterations lane 0 stores the tile's partials (the
+// gap of (f^k, p^k)).  Plane block of an image: the plain solver's layout.
 template <int N, bool CHECK>
 __device__ __forceinline__ void tile_pass(const BatchArgs& a,
-                                          const TileDesc& T, int k,
+                                          const TileDesc& T, int slot,
                                           double& sg, double& sp) {
   const ImgDesc& D = a.imgs[T.img];
   float* base = a.arena + D.off;
   const int64_t PL = D.plane;
   TileCtxS c;
-  c.F = base + plain_f(k) * PL;
-  c.FN = base + plain_f(k + N) * PL;
-  c.PX = base + plain_p(k) * PL;
+  c.F = base + plain_f(slot) * PL;
+  c.FN = base + plain_f(slot ^ 1) * PL;
+  c.PX = base + plain_p(slot) * PL;
   c.PY = c.PX + PL;
-  c.QX = base + plain_p(k + N) * PL;
+  c.QX = base + plain_p(slot ^ 1) * PL;
   c.QY = c.QX + PL;
   c.G = base + kPlainG * PL;
   c.ny = D.ny;
@@ -104,14 +104,14 @@ __device__ __forceinline__ void tile_pass(const BatchArgs& a,
 }
 
 template <bool CHECK>
-__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
+__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int slot,
                                         int n) {
   const TileDesc T = a.tiles[t];
   double sg = 0.0, sp = 0.0;
   switch (n) {
-    case 1: tile_pass<1, CHECK>(a, T, k, sg, sp); break;
-    case 2: tile_pass<2, CHECK>(a, T, k, sg, sp); break;
-    default: tile_pass<5, CHECK>(a, T, k, sg, sp); break;
+    case 1: tile_pass<1, CHECK>(a, T, slot, sg, sp); break;
+    case 2: tile_pass<2, CHECK>(a, T, slot, sg, sp); break;
+    default: tile_pass<5, CHECK>(a, T, slot, sg, sp); break;
   }
   static_assert(kBatchMaxPass == 5, "one case per pass length");
   if (CHECK) {
@@ -126,8 +126,9 @@ __device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int k,
 
 // Reduce the gap partials of image i in a fixed order (whole block) and
 // apply the stopping rule; thread 0 updates the image state.  `tbl` is the
-// tile table the check iteration was swept with.
-__device__ void reduce_image(const BatchArgs& a, int i, int k, int tbl,
+// tile table the check iteration was swept with, `slot` the plane slot of
+// (f^k, p^k).
+__device__ void reduce_image(const BatchArgs& a, int i, int k, int slot, int tbl,
                              double (*red)[kMaxBlock / kWave]) {
   const ImgDesc& D = a.imgs[i];
   const int first = D.tile_first[tbl], count = D.tile_count[tbl];
@@ -145,6 +146,7 @@ __device__ void reduce_image(const BatchArgs& a, int i, int k, int tbl,
     if (D.tol >= 0.0 && sg <= D.tol * sp) {
       S.converged = 1;
       S.iters = k;
+      S.slot = slot;
       atomicOr(&a.hdr->flags, kBatchStopped);  // the active list must shrink
     }
   }
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
   const int wave = wave_in_block();
   const int nw = gridDim.x * a.wpb;
   const int gw = blockIdx.x * a.wpb + wave;
-  int k = 0;
+  int k = 0, slot = 0;
   while (k < a.max_iter) {
     const bool check = a.check_every > 0 && (k % a.check_every) == 0;
     const int n = batch_pass_len(k, a.max_iter, a.check_every, a.depth);
@@ -218,15 +220,15 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
     if (wave < a.wpb)
       for (int idx = gw; idx < nact; idx += nw) {
         if (check)
-          do_tile<true>(a, a.active[idx], k, n);
+          do_tile<true>(a, a.active[idx], slot, n);
         else
-          do_tile<false>(a, a.active[idx], k, n);
+          do_tile<false>(a, a.active[idx], slot, n);
       }
     if (!grid_barrier(h, gen)) return;
     if (check) {
       const int tbl = load_i32(&h->table);
       for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
-        if (!a.state[i].converged) reduce_image(a, i, k, tbl, red);
+        if (!a.state[i].converged) reduce_image(a, i, k, slot, tbl, red);
       if (!grid_barrier(h, gen)) return;
       // rebuild the active list only when an image stopped at this check
       if (load_i32(&h->flags) & kBatchStopped) {
@@ -239,8 +241,12 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
       }
     }
     k += n;
+    slot ^= 1;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) h->k = k;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    h->k = k;
+    h->slot = slot;
+  }
 }
 
 // One pass of n iterations over the active list (graph-block driver).  The
@@ -254,6 +260,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a,
   BatchHdr* h = a.hdr;
   const int k = h->k;
   if (k + n > a.max_iter) return;
+  const int slot = h->slot;
   const int nact = h->n_active;
   if (nact == 0) return;
   const int wave = wave_in_block();
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a,
   const int gw = blockIdx.x * a.wpb + wave;
   if (wave < a.wpb)
     for (int idx = gw; idx < nact; idx += nw)
-      do_tile<CHECK>(a, a.active[idx], k, n);
+      do_tile<CHECK>(a, a.active[idx], slot, n);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -273,13 +280,16 @@ __global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a,
   if (CHECK) {
     const int tbl = h->table;
     for (int i = 0; i < a.nimg; ++i)
-      if (!a.state[i].converged) reduce_image(a, i, k, tbl, red);
+      if (!a.state[i].converged) reduce_image(a, i, k, slot, tbl, red);
     if (load_i32(&h->flags) & kBatchStopped) {
       compact_active(a);
       if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
     }
   }
-  if (threadIdx.x == 0) h->k = k + n;
+  if (threadIdx.x == 0) {
+    h->k = k + n;
+    h->slot = slot ^ 1;
+  }
 }
 
 __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
@@ -311,11 +321,11 @@ __global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
   const ImgDesc& D = a.imgs[i];
   const ImgState& S = a.state[i];
   const int conv = S.converged;
-  const int k = conv ? S.iters : a.hdr->k;
+  const int slot = conv ? S.slot : a.hdr->slot;
   const float* base = a.arena + D.off;
   const int64_t PL = D.plane;
-  const float* f = base + plain_f(k) * PL;
-  const float* px = base + plain_p(k) * PL;
+  const float* f = base + plain_f(slot) * PL;
+  const float* px = base + plain_p(slot) * PL;
   const float* py = px + PL;
   const float* g = base + kPlainG * PL;
   const int64_t n = (int64_t)D.ny * D.nx;

@@ -40,7 +40,7 @@ struct DevState {
   double P, D, gap;      // energies of the last evaluated pair
   double tol;            // relative gap tolerance (< 0: never stop)
   float tau_prev;        // step that produced f^k (0 after initialisation)
-  int32_t pad0;
+  int32_t slot;          // 2D: plane slot of f^k and p^k (flips with every pass)
   double pad[7];
 };
 static_assert(sizeof(DevState) <= 256, "state header");
@@ -71,21 +71,17 @@ __host__ __device__ constexpr int xs_owned(int n) {
 }
 constexpr int kXsOwnedMin = kStripCols - 2 * xs_margin(kMaxPass);
 
-// Plane block of the plain 2D solver: f^k in slot k mod 7 (planes 0..6),
-// p^k in slot k mod 7 (planes 7 + 2 (k mod 7), x then y), g in plane 21.  A
-// pass of n <= kMaxPass iterations reads f^k, p^k and writes f^{k+n},
-// p^{k+n}: with rings of kMaxPass + 1 slots it never overwrites an input
-// that another tile still reads.
-constexpr int kRingF = kMaxPass + 1;
-constexpr int kRingP = kMaxPass + 1;
-constexpr int kPlainPlanes2D = kRingF + 2 * kRingP + 1;
-constexpr int kPlainG = kRingF + 2 * kRingP;
-__host__ __device__ inline int plain_f(int k) {
-  return ((k % kRingF) + kRingF) % kRingF;
-}
-__host__ __device__ inline int plain_p(int k) {
-  return kRingF + 2 * (((k % kRingP) + kRingP) % kRingP);
-}
+// Plane block of the plain 2D solver: two slots, f in plane `slot` and p in
+// planes 2 + 2 slot (x) and 3 + 2 slot (y), and g in plane 6.  The slot of
+// f^k and p^k is kept with the iteration count (DevState::slot; the batched
+// solver's header and, for an image that stopped, its ImgState).  A pass of
+// n iterations reads f^k, p^k from one slot and writes f^{k+n}, p^{k+n} to
+// the other, so it never overwrites an input that another tile of the same
+// pass still reads; the pass that advances k flips the slot.
+constexpr int kPlainPlanes2D = 7;
+constexpr int kPlainG = 6;
+__host__ __device__ inline int plain_f(int slot) { return slot; }
+__host__ __device__ inline int plain_p(int slot) { return 2 + 2 * slot; }
 
 // Plane block of the plain 3D solver: f^k in slot k mod 3 (planes 0..2),
 // p^k in slot k mod 2 (planes 3 + 3 (k mod 2), x, y, z), g in plane 9.

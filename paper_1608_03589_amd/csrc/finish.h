@@ -40,6 +40,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
     if (threadIdx.x == 0) {
       st->k = k + STEP;
       st->tau_prev = tau;
+      st->slot ^= 1;
     }
   } else {
     double sg = 0.0, sp = 0.0;
@@ -60,6 +61,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
       } else {
         st->k = k + STEP;
         st->tau_prev = tau;
+        st->slot ^= 1;
       }
     }
   }

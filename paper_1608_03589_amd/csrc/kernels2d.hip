@@ -22,6 +22,7 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
   const int k = st->k;
   if (st->converged || k + S > st->k_end) return;
   const float tau_prev = st->tau_prev;
+  const int slot = st->slot;
   // (not wave_in_block(): with uniform tile coordinates the compiler's
   // schedule of the depth-5 walk needs more than 256 registers)
   const int wave = threadIdx.x / kWave;
@@ -36,11 +37,11 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
   if (wt < a.ntiles) {
     TileCtxS c;
     const int64_t PL = a.plane;
-    c.F = a.base + plain_f(k) * PL;
-    c.FN = a.base + plain_f(k + S) * PL;
-    c.PX = a.base + plain_p(k) * PL;
+    c.F = a.base + plain_f(slot) * PL;
+    c.FN = a.base + plain_f(slot ^ 1) * PL;
+    c.PX = a.base + plain_p(slot) * PL;
     c.PY = c.PX + PL;
-    c.QX = a.base + plain_p(k + S) * PL;
+    c.QX = a.base + plain_p(slot ^ 1) * PL;
     c.QY = c.QX + PL;
     c.G = a.base + kPlainG * PL;
     int tx, ty;
@@ -91,6 +92,7 @@ __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
     st->P = st->D = st->gap = 0.0;
     st->tol = -1.0;
     st->tau_prev = 0.0f;
+    st->slot = 0;
     SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
                                                kSyncOffset);
     for (int i = 0; i < kSyncGroups; ++i) sa->sub[i].v = 0;
@@ -112,9 +114,9 @@ __global__ void set_params_kernel(DevState* st, int32_t k_end, double tol) {
 __global__ void read2d_kernel(const float* base, int64_t plane, int ny,
                               int nx, int pitch, const DevState* st,
                               float* f_out, float* p_out) {
-  const int k = st->k;
-  const float* f = base + plain_f(k) * plane;
-  const float* px = base + plain_p(k) * plane;
+  const int slot = st->slot;
+  const float* f = base + plain_f(slot) * plane;
+  const float* px = base + plain_p(slot) * plane;
   const float* py = px + plane;
   const int64_t n = (int64_t)ny * nx;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -137,9 +139,9 @@ __global__ __launch_bounds__(kMaxBlock) void energy2d_kernel(
     const DevState* st, double* partials, int skip_if_converged) {
   if (skip_if_converged && st->converged) return;
   __shared__ double red[2][kMaxBlock / kWave];
-  const int k = st->k;
-  const float* f = base + plain_f(k) * plane;
-  const float* px = base + plain_p(k) * plane;
+  const int slot = st->slot;
+  const float* f = base + plain_f(slot) * plane;
+  const float* px = base + plain_p(slot) * plane;
   const float* py = px + plane;
   const float* g = base + kPlainG * plane;
   const int64_t n = (int64_t)ny * nx;

@@ -84,6 +84,8 @@ __global__ void init3d_kernel(float* base, int64_t plane, int nz, int ny,
     st->flags = 0;
     st->P = st->D = st->gap = 0.0;
     st->tol = -1.0;
+    st->tau_prev = 0.0f;
+    st->slot = 0;
     SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
                                                kSyncOffset);
     for (int i = 0; i < kSyncGroups; ++i) sa->sub[i].v = 0;
