@@ -29,42 +29,99 @@ BYTES_PER_PIXEL_ITER = 32      # one iteration as defined: reads f^k, f^{k-1}, p
                                # writes f^{k+1}, p^{k+1} (2)
 PASS_BYTES_PER_PIXEL = 28      # a launch of n iterations: reads f^k, p^k (2), g, writes
                                # f^{k+n}, p^{k+n} (2) (fbar^k is formed from f^k, g, p^k)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep2d_xs5_denoise4096_traffic.txt")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1608_03589_amd", "csrc", f)
+# Issue ceiling of the vector ALUs without packed fp32 math (which this build
+# turns off): each CU has 4 SIMDs of 16 lanes, so one wave64 VALU instruction
+# per CU and cycle; at 2.4 GHz over 256 CUs.  (The published 157.3 TFLOP/s
+# counts a fused multiply-add as two operations and a packed pair as two.)
+VALU_PEAK_WAVE_INSTR_S = 256 * 2.4e9
+VALU_PEAK_TOPS = VALU_PEAK_WAVE_INSTR_S * 64 / 1e12      # 39.3 T lane-ops/s
+# Texture-addresser ceiling of the gathers: 4 lane addresses per clock per
+# CU, one wave64 buffer load per 16 cycles.
+TA_PEAK_WAVE_INSTR_S = 256 * 2.4e9 / 16
+
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "sweep2d_xs5_denoise4096_traffic.txt")
+SQ_FILE = os.path.join(PROFILES, "sweep2d_xs5_denoise4096_sq.txt")
+TOMO_COUNTERS_FILE = os.path.join(PROFILES, "tomo_kernels_tomo2048x1000_counters.txt")
+CSRC = os.path.join(ROOT, "paper_1608_03589_amd", "csrc")
+KERNEL_SRCS = [os.path.join(CSRC, f)
                for f in ("kernels2d.hip", "tile2d.h", "tile2d_xs.h", "pointwise.h")]
+TOMO_SRCS = [os.path.join(CSRC, f)
+             for f in ("tomo.hip", "tomo.h", "tile2d.h", "pointwise.h", "bst.hip", "lp.hip")]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
+    for f in files:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(pixels: int, tile):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary, or None when the kernel source or the tile changed since it was
-    taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def kernel_hash() -> str:
+    return source_hash(KERNEL_SRCS)
+
+
+def read_kv(path):
+    """key: value lines of a profile summary (comments start with #)."""
+    if not os.path.exists(path):
+        return {}
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
+    return kv
+
+
+def read_sweep_profile(path, key, tile):
+    """A per-launch figure of the sweep from a committed rocprofv3 summary,
+    or None when the kernel sources or the tile changed since it was taken."""
+    kv = read_kv(path)
     if kv.get("kernel_source_sha256_16") != kernel_hash():
         return None
     if kv.get("tile_th_wpb_order") != " ".join(str(v) for v in tile):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(pixels: int, tile):
+    """HBM bytes per sweep launch (copy-calibrated FETCH_SIZE + WRITE_SIZE)."""
+    return read_sweep_profile(TRAFFIC_FILE, "hbm_bytes_per_launch", tile)
+
+
+def read_tomo_counters():
+    """Per-dispatch counter figures of the tomography kernels, {kernel:
+    {key: value}}, or {} when the sources changed since they were taken."""
+    kv = read_kv(TOMO_COUNTERS_FILE)
+    if kv.get("kernel_source_sha256_16") != source_hash(TOMO_SRCS):
+        return {}
+    out = {}
+    for k, v in kv.items():
+        if "." in k:
+            kern, key = k.split(".", 1)
+            try:
+                out.setdefault(kern, {})[key] = float(v)
+            except ValueError:
+                pass
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def pass_schedule(iters, check_every, depth):
@@ -121,6 +178,72 @@ def timed(fn, stream, reps=1):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps, out
+
+
+def bench_denoise_256(dev):
+    """The small parity workload (256^2, 1000 iterations, gap every 10) as a
+    throughput case: its 2 MiB working set stays in the caches, so launch
+    latency rather than HBM sets the time.  Direct launches and launches
+    replayed from HIP graphs of 64 iterations."""
+    import torch
+    import paper_1608_03589_amd as tv
+    from scenes import WORKLOADS, scene2d
+    w = WORKLOADS["denoise_256"]
+    _, g = scene2d(w["H"], w["W"], w["n_shapes"], w["noise"], w["seed"])
+    gt = torch.from_numpy(g.astype(np.float32)).to(dev)
+    out = torch.empty_like(gt)
+    solver = tv.PlainSolver(tuple(gt.shape), dev)
+    stream = torch.cuda.current_stream(dev)
+    s = 1.0 / math.sqrt(8.0)
+    rec = {"workload": "denoise_256", "image": [w["H"], w["W"]],
+           "iterations": w["iters"], "gap_check_every": 10,
+           "launches_per_solve": len(pass_schedule(w["iters"], 10, tv.get_pass_depth()))}
+    pix_its = w["H"] * w["W"] * w["iters"]
+    for name, use_graph in (("direct", 0), ("graph", 1)):
+        def run():
+            return solver.solve(gt, w["lam"], tau=s, sigma=s, max_iter=w["iters"],
+                                check_every=10, gap_tol=-1.0, use_graph=use_graph, out=out)
+        run()
+        ms, _ = timed(run, stream, 10)
+        rec[f"{name}_ms"] = ms
+        rec[f"mpix_its_{name}"] = pix_its / (ms * 1e-3) / 1e6
+        rec[f"us_per_launch_{name}"] = ms * 1e3 / rec["launches_per_solve"]
+    # latency of the small case against the pass depth and the band height:
+    # a pass walks th + 2 depth - 1 rows serially, so small images favour
+    # short bands
+    sweep = []
+    depth0 = tv.get_pass_depth()
+    tile0 = tv.get_tile(tuple(gt.shape))
+    try:
+        for depth in (1, 2, 3, 4, 5):
+            tv.set_pass_depth(depth)
+            for th in (1, 2, 4, 8):
+                tv.set_tile(tuple(gt.shape), th, 4, 0)
+                def run():
+                    return solver.solve(gt, w["lam"], tau=s, sigma=s, max_iter=w["iters"],
+                                        check_every=10, gap_tol=-1.0, use_graph=1, out=out)
+                run()
+                ms, _ = timed(run, stream, 5)
+                sweep.append({"depth": depth, "th": th, "ms": ms,
+                              "mpix_its": pix_its / (ms * 1e-3) / 1e6})
+    finally:
+        tv.set_pass_depth(depth0)
+        tv.set_tile(tuple(gt.shape), *tile0)
+    rec["depth_band_sweep_graph"] = sweep
+    best = min(sweep, key=lambda r: r["ms"])
+    rec["best_depth_band"] = best
+    # the stopping solve of the same image (relative gap 1e-4)
+    def stop():
+        return solver.solve(gt, w["lam"], tau=s, sigma=s, max_iter=w["iters"],
+                            check_every=10, gap_tol=1e-4, out=out)
+    stop()
+    ms, (_, res) = timed(stop, stream, 10)
+    rec["stopping_solve_ms"] = ms
+    rec["stopping_solve_iters"] = res.iters
+    log(f"denoise 256: direct {rec['direct_ms']:.3f} ms, graph {rec['graph_ms']:.3f} ms "
+        f"per 1000 iterations; stopping solve {ms:.3f} ms ({res.iters} iterations); "
+        f"best depth {best['depth']} band {best['th']}: {best['ms']:.3f} ms")
+    return rec
 
 
 def bench_batched(dev):
@@ -333,6 +456,9 @@ def bench_tomo(dev):
     ms_bst, _ = timed(lambda: solver.bst(gt, back), stream, 5)
     solver.fbp_bst(gt, 0.0, back)
     ms_fbp_bst, _ = timed(lambda: solver.fbp_bst(gt, 0.0, back), stream, 5)
+    solver.logpolar(gt, back)                    # plans the log-polar workspace
+    ms_lp, _ = timed(lambda: solver.logpolar(gt, back), stream, 5)
+    n_rho, n_phi, L_rho, _, _ = solver.lp_mesh()
 
     def run():
         solver.init()
@@ -343,9 +469,38 @@ def bench_tomo(dev):
     e = solver.energy(gt, lam, "tv")
     log(f"tomo: {ms / iters:.3f} ms per iteration, A {ms_radon:.3f} ms, "
         f"A^T {ms_bp:.3f} ms, regularised FBP {ms_fbp:.3f} ms, BST {ms_bst:.3f} ms, "
-        f"regularised FBP through the BST {ms_fbp_bst:.3f} ms")
+        f"regularised FBP through the BST {ms_fbp_bst:.3f} ms, log-polar {ms_lp:.3f} ms")
     tf_bp = pairs * TOMO_FLOPS_BP / (ms_bp * 1e-3) / 1e12
     tf_proj = pairs * TOMO_FLOPS_PROJ / (ms_radon * 1e-3) / 1e12
+    cnt = read_tomo_counters()
+    # the two fast backprojections: the least HBM traffic a pipeline from the
+    # sinogram to the image can have (read g once, write the image once), the
+    # traffic its kernels measured, and the VALU issue they measured
+    io_bytes = 4 * (na * nd + H * W)
+
+    def pipeline(ms_run, kernels):
+        rec = {"ms": ms_run, "kernels": kernels,
+               "algorithmic_bytes": io_bytes,
+               "algorithmic_frac": io_bytes / (ms_run * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if all(k in cnt for k in kernels):
+            byt = sum(cnt[k].get("hbm_bytes", 0.0) for k in kernels)
+            valu = sum(cnt[k].get("valu_wave_instr", 0.0) for k in kernels)
+            rec["traffic"] = byt
+            rec["hbm_frac"] = byt / (ms_run * 1e-3) / 1e9 / HBM_PEAK_GBS
+            rec["valu_frac"] = valu / (ms_run * 1e-3) / VALU_PEAK_WAVE_INSTR_S
+            rec["bound"] = "alu" if rec["valu_frac"] > rec["hbm_frac"] else "hbm"
+            rec["frac"] = max(rec["valu_frac"], rec["hbm_frac"])
+        return rec
+
+    proj = cnt.get("tomo_project_kernel", {})
+    ta = None
+    if proj.get("vmem_rd_wave_instr"):
+        ach = proj["vmem_rd_wave_instr"] / (ms_radon * 1e-3)
+        ta = {"achieved_vmem_wave_instr_s": ach, "peak": TA_PEAK_WAVE_INSTR_S,
+              "frac": ach / TA_PEAK_WAVE_INSTR_S,
+              "ta_busy": proj.get("ta_busy"),
+              "basis": "buffer loads issued per second (rocprofv3 SQ_INSTS_VMEM_RD) against "
+                       "the texture addresser's 4 lane addresses per clock per CU"}
     return {
         "workload": "tomo_2048x1000",
         "image": [H, W], "n_angles": na, "n_det": nd, "reg": "tv", "lam": lam,
@@ -359,6 +514,16 @@ def bench_tomo(dev):
         "fbp_ms": ms_fbp,
         "bst_backproject_ms": ms_bst,
         "fbp_bst_ms": ms_fbp_bst,
+        "logpolar_backproject_ms": ms_lp,
+        "logpolar_mesh": {"n_rho": n_rho, "n_phi": n_phi, "L": L_rho},
+        "bst_pipeline": pipeline(ms_bst, ["bst_spectra_kernel", "bst_cartesian_rows_kernel",
+                                          "bst_transpose_kernel", "bst_rows_inverse_kernel",
+                                          "bst_extract_kernel"]),
+        "logpolar_pipeline": pipeline(ms_lp, ["lp_rows_forward_kernel",
+                                              "lp_angle_conv_kernel",
+                                              "lp_rows_inverse_kernel",
+                                              "lp_cartesian_kernel"]),
+        "projection_ta_bound": ta,
         "gpairs_per_s_radon": pairs / (ms_radon * 1e-3) / 1e9,
         "gpairs_per_s_backproject": pairs / (ms_bp * 1e-3) / 1e9,
         "roofline": {
@@ -391,6 +556,7 @@ def copy_calibration(dev):
 
 
 EXTRA_WORKLOADS = {
+    "denoise_256": lambda dev: bench_denoise_256(dev),
     "batch64_uneven": lambda dev: bench_batched(dev),
     "unrolled_32x512": lambda dev, ref: bench_unrolled_2d(dev, ref),
     "unrolled_256cube": lambda dev: bench_unrolled_3d(dev),
@@ -496,7 +662,29 @@ def main():
     pass_bytes = PASS_BYTES_PER_PIXEL * pix
     pass_achieved = pass_bytes / launch_s / 1e9
     kernels = sorted(set(passes))
-    traffic = read_traffic(pix, tv.get_tile((H, W))) if kernels == [depth] else None
+    tile = tv.get_tile((H, W))
+    traffic = read_traffic(pix, tile) if kernels == [depth] else None
+    valu = (read_sweep_profile(SQ_FILE, "valu_wave_instr_per_launch", tile)
+            if kernels == [depth] else None)
+    hbm_bound = {
+        "achieved": pass_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": pass_achieved / HBM_PEAK_GBS,
+        "algorithmic_bytes_per_launch": pass_bytes,
+        "basis": "what a launch of n iterations must move: reads f^k, p^k (2), g, "
+                 "writes f^{k+n}, p^{k+n} (2), 28 B per pixel",
+    }
+    alu_bound = None
+    if valu:
+        ach = valu * 64 / launch_s / 1e12
+        alu_bound = {
+            "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": ach / VALU_PEAK_TOPS,
+            "valu_wave_instructions_per_launch": valu,
+            "basis": "VALU instructions the kernel issues per launch (rocprofv3 "
+                     "SQ_INSTS_VALU, overlap margins included) x 64 lanes, against one "
+                     "wave64 instruction per CU and cycle (256 CUs, 2.4 GHz, no packed fp32)",
+        }
+    binding = alu_bound if alu_bound and alu_bound["frac"] > hbm_bound["frac"] else hbm_bound
 
     if args.copy_calibration:
         copy_calibration(dev)
@@ -508,6 +696,7 @@ def main():
         del solver, gt, out
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+        extra["denoise_256"] = bench_denoise_256(dev)
         extra["batched"] = bench_batched(dev)
         extra["unrolled_2d"] = bench_unrolled_2d(dev, mpix_its)
         extra["unrolled_3d"] = bench_unrolled_3d(dev)
@@ -523,7 +712,7 @@ def main():
             "cores": 1,
             "kind": "oracle",
             "sample": f"{n_cpu} iterations of the 4096x4096 workload, numpy "
-                      f"float64, single thread ({platform.processor() or platform.machine()}, "
+                      f"float64, single thread ({cpu_model()}, "
                       f"{os.cpu_count()} cores visible)",
         }
 
@@ -552,26 +741,23 @@ def main():
             "pass_depth": depth,
         },
         "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "basis": ("one-iteration algorithmic bytes, 32 B per pixel-iteration; "
-                      "a pass of n iterations keeps the n-1 intermediate iterates "
-                      "on chip and forms fbar^k from f^k, g and p^k (28 B per "
-                      "pixel and launch), so this figure can exceed the peak"),
-            "pass_algorithmic_bytes_per_launch": pass_bytes,
-            "pass_achieved_GBs": pass_achieved,
-            "pass_frac": pass_achieved / HBM_PEAK_GBS,
+            "bound": "alu" if binding is alu_bound else "hbm",
+            "achieved": binding["achieved"],
+            "peak": binding["peak"],
+            "unit": binding["unit"],
+            "frac": binding["frac"],
+            "bounds": {"hbm": hbm_bound, "alu": alu_bound},
+            "one_pass_equivalent_GBs": achieved,
+            "one_pass_equivalent_basis": (
+                "32 B per pixel-iteration (one HBM pass per iteration): the bandwidth a "
+                "kernel without temporal blocking would need for this throughput"),
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "traffic_vs_algorithmic": (traffic / alg_bytes) if traffic else None,
+            "traffic_vs_algorithmic": (traffic / pass_bytes) if traffic else None,
             "hbm_achieved_GBs": (traffic / launch_s / 1e9) if traffic else None,
             "kernel": kernel_name(kernels, passes),
             "pixel_iterations_per_launch": pix * its_per_launch,
-            "algorithmic_bytes_per_pixel_iteration": BYTES_PER_PIXEL_ITER,
-            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_bytes_per_launch": pass_bytes,
             "avg_launch_us": launch_s * 1e6,
         },
         "cpu_baseline": cpu,
