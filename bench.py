@@ -291,6 +291,8 @@ def bench_batched(dev):
         "effective_GBs_persistent": BYTES_PER_PIXEL_ITER * work / (ms_p * 1e-3) / 1e9,
         "speedup_vs_plain_loop": ms_l / ms_p,
         "same_iters_as_plain": all(a.iters == c.iters for a, c in zip(res, res_l)),
+        "per_image_h_w_iters": [[int(i.shape[0]), int(i.shape[1]), int(r.iters)]
+                                for i, r in zip(imgs, res)],
     }
 
 
@@ -492,7 +494,7 @@ def bench_tomo(dev):
             rec["frac"] = max(rec["valu_frac"], rec["hbm_frac"])
         return rec
 
-    proj = cnt.get("tomo_project_kernel", {})
+    proj = cnt.get("tomo_project_kernel#1", {})
     ta = None
     if proj.get("vmem_rd_wave_instr"):
         ach = proj["vmem_rd_wave_instr"] / (ms_radon * 1e-3)

@@ -239,7 +239,7 @@ int tvpd_tune_load(const char* cache_path, int32_t* count);
  * plain launches, one per pass (reference driver).  Passes hold 1, 2 or 5
  * iterations (tvpd_set_pass_depth).  th: rows per wave band (0 = the
  * autotuned or default value); wpb: waves per block (0 = autotuned or
- * default, else 1, 2 or 4); th_short: rows per band of the second tile
+ * default, else 1, 2, 4 or 8); th_short: rows per band of the second tile
  * table, used once the running images no longer fill the grid (0 = default
  * 8; at most th); two more tables halve the band (at least 1 row) and take
  * over as images stop, whenever their tiles still fit the grid's waves.  The

@@ -87,6 +87,12 @@ __host__ __device__ inline int batch_pass_len(int k, int max_iter, int ce,
 
 constexpr int kFinalBlocks = 32;  // blocks per image of the final pass
 
+// Threads per block of the batched drivers: up to 8 waves, so that one
+// block per CU holds two waves per SIMD (the grid barrier costs by the
+// block, the tile walks gain from the waves).
+constexpr int kBatchBlock = 512;
+constexpr int kBatchMaxWpb = kBatchBlock / kWave;
+
 hipError_t launch_batch_init(const BatchArgs& a, const float* g,
                              const int64_t* offs_dev, hipStream_t s);
 int batch_persistent_grid(int wpb);

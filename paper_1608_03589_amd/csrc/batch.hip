@@ -129,7 +129,7 @@ __device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int slot,
 // tile table the check iteration was swept with, `slot` the plane slot of
 // (f^k, p^k).
 __device__ void reduce_image(const BatchArgs& a, int i, int k, int slot, int tbl,
-                             double (*red)[kMaxBlock / kWave]) {
+                             double (*red)[kBatchMaxWpb]) {
   const ImgDesc& D = a.imgs[i];
   const int first = D.tile_first[tbl], count = D.tile_count[tbl];
   double sg = 0.0, sp = 0.0;
@@ -202,9 +202,9 @@ __device__ void compact_active(const BatchArgs& a) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
+__global__ __launch_bounds__(kBatchBlock) void batch_persistent_kernel(
     BatchArgs a) {
-  __shared__ double red[2][kMaxBlock / kWave];
+  __shared__ double red[2][kBatchMaxWpb];
   BatchHdr* h = a.hdr;
   unsigned gen = __hip_atomic_load(&sync_of(h)->gen.v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -253,9 +253,9 @@ __global__ __launch_bounds__(kMaxBlock) void batch_persistent_kernel(
 // last block to finish advances k and, on check iterations, reduces every
 // running image, stops the converged ones and rebuilds the active list.
 template <bool CHECK>
-__global__ __launch_bounds__(kMaxBlock) void batch_sweep_kernel(BatchArgs a,
-                                                                int n) {
-  __shared__ double red[2][kMaxBlock / kWave];
+__global__ __launch_bounds__(kBatchBlock) void batch_sweep_kernel(BatchArgs a,
+                                                                  int n) {
+  __shared__ double red[2][kBatchMaxWpb];
   __shared__ int s_last;
   BatchHdr* h = a.hdr;
   const int k = h->k;

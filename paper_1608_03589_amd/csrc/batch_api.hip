@@ -72,7 +72,7 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
 }
 
 std::mutex g_btile_mu;
-int g_btile_th = 32, g_btile_wpb = 4;
+int g_btile_th = 16, g_btile_wpb = 8;
 
 int params_ok(int n, const tvpd_shape* s, const tvpd_params* prm) {
   if (!prm) return TVPD_ERR_INVALID_ARG;
@@ -286,11 +286,13 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
   if (!ws) return TVPD_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
   if (ws_bytes < L.bytes) return TVPD_ERR_WORKSPACE;
-  // grid of the driver: two blocks per CU for graph blocks, one per CU for
-  // the persistent kernel (capped by co-residency); every block sweeps tiles
-  // grid-stride.  One persistent block per CU is faster on the 64 uneven
-  // images (61.7 against 66.4 ms): the grid barrier costs more with twice
-  // the blocks, and the extra waves do not speed up the full passes.
+  // grid of the driver: one block per CU for the persistent kernel (capped by
+  // co-residency), two (one of 8 waves) for the launch drivers; every block
+  // sweeps tiles grid-stride.  One persistent block per CU is faster on the 64
+  // uneven images (61.7 against 66.4 ms with two of 4 waves): the grid
+  // barrier costs by the block; one block of 8 waves, two per SIMD, takes
+  // 55.7 ms against 59.1 with 4 waves, the extra waves shortening the
+  // latency-bound walks at no barrier cost.
   int cus = 0;
   {
     int dev = 0;
@@ -300,7 +302,9 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
       return TVPD_ERR_HIP;
     cus = p.multiProcessorCount;
   }
-  int grid = 2 * cus;
+  // (launch drivers: two blocks per CU of up to 4 waves, one of 8 waves;
+  // either way two waves per SIMD, all resident at once)
+  int grid = (wpb >= 8 ? 1 : 2) * cus;
   if (mode == 0) {
     const int cap = batch_persistent_grid(wpb);
     if (cap <= 0) return TVPD_ERR_HIP;
@@ -387,7 +391,7 @@ int tvpd_solve_batched(int32_t n, const tvpd_shape* shapes,
   }
   if (mode < 0 || mode > 2) return TVPD_ERR_INVALID_ARG;
   if (th < 0 || th > 4096 || th_short < 0 || th_short > 4096 ||
-      !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4))
+      !(wpb == 0 || wpb == 1 || wpb == 2 || wpb == 4 || wpb == 8))
     return TVPD_ERR_INVALID_ARG;
   {
     std::lock_guard<std::mutex> gl(g_btile_mu);
@@ -417,7 +421,7 @@ int tvpd_batch_autotune(int32_t n, const tvpd_shape* shapes,
   BHIP(hipEventCreate(&e0));
   BHIP(hipEventCreate(&e1));
   static const int ths[] = {8, 16, 32, 64, 128};
-  static const int wpbs[] = {1, 2, 4};
+  static const int wpbs[] = {1, 2, 4, 8};
   float best = 1e30f;
   int bth = 32, bwpb = 4;
   int rc = TVPD_OK;

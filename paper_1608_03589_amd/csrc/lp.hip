@@ -51,7 +51,7 @@ constexpr int kLpMaxL = 16384;        // rho transform length limit (LDS)
 constexpr int kLpMaxRho = kLpMaxL / 2;
 constexpr int kLpMaxPhi = 4096;
 constexpr int kLpElems = 16384;       // LDS elements of the angle transforms (n_phi C)
-constexpr int kLpThreads = 512;
+constexpr int kLpThreads = 1024;      // 16 waves: 4 per SIMD at <= 128 VGPRs
 constexpr int kLpMaxStages = 16;
 constexpr uint32_t kLpMagic = 0x4c50424bu;
 

@@ -64,8 +64,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum (a, b) over the block in a fixed order; result valid in thread 0.
-__device__ __forceinline__ void block_sum2(double& a, double& b,
-                                           double (*red)[kMaxBlock / kWave]) {
+// red: two rows of NW >= blockDim.x / 64 slots in LDS.
+template <int NW>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double (*red)[NW]) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int nw = (blockDim.x + kWave - 1) / kWave;
   a = wave_sum(a);

@@ -231,7 +231,13 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       if constexpr (GAP) {
         // gap density and primal energy of (f^k, p^k) on row t
         // (the lane shuffles run on the whole wave: a row condition is the
-        // same for every lane, the column condition is applied afterwards)
+        // same for every lane, the column condition is applied afterwards).
+        // Each pixel's terms are formed in float32 and summed in float64:
+        // rounding errors of a few units in the last place per term, of
+        // either sign, bound the sum's error by 5e-7 P and leave it near 1e-9
+        // P in practice, far below any stopping tolerance; the float64 terms
+        // cost a third more instructions in this launch.
+        // lambda |grad f| - <grad f, p> is subtracted in float64 (exactly).
         if (s == 1 && r >= y0 && r < y1) {
           const F4& A = L.f;                          // f^k, row r+1
           const float nfr = from_right(B.v[0]);
@@ -240,20 +246,18 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
           for (int j = 0; j < 4; ++j) {
             if (owned && (!kEdge || xg + j < nx)) {
               const float right = (j < 3) ? B.v[j + 1] : nfr;
-              const double fv = B.v[j];
-              const double gx =
-                  (!kEdge || xg + j < nx - 1) ? (double)right - fv : 0.0;
-              const double gy = dn ? (double)A.v[j] - fv : 0.0;
-              const double lo = (j == 0) ? ((!kEdge || xg > 0) ? (double)lox : 0.0)
-                                         : (double)EX.v[j - 1];
-              const double uo = up ? (double)lp2y.v[j] : 0.0;
-              const double d = ((double)EX.v[j] - lo) + ((double)EY.v[j] - uo);
-              const double e = fv - (double)Gv.v[j];
-              const double res = e - d;
-              const double nrm = sqrt(gx * gx + gy * gy);
-              acc_gap += 0.5 * res * res + (double)lam * nrm -
-                         (gx * (double)EX.v[j] + gy * (double)EY.v[j]);
-              acc_P += 0.5 * e * e + (double)lam * nrm;
+              const float fv = B.v[j];
+              const float gx = (!kEdge || xg + j < nx - 1) ? right - fv : 0.0f;
+              const float gy = dn ? A.v[j] - fv : 0.0f;
+              const float lo = (j == 0) ? ((!kEdge || xg > 0) ? lox : 0.0f) : EX.v[j - 1];
+              const float uo = up ? lp2y.v[j] : 0.0f;
+              const float d = (EX.v[j] - lo) + (EY.v[j] - uo);
+              const float e = fv - Gv.v[j];
+              const float res = e - d;
+              const float tv = lam * __builtin_amdgcn_sqrtf(fmaf(gx, gx, gy * gy));
+              const float dot = fmaf(gx, EX.v[j], gy * EY.v[j]);
+              acc_gap += (double)(0.5f * res * res) + ((double)tv - (double)dot);
+              acc_P += (double)(0.5f * e * e) + (double)tv;
             }
           }
         }

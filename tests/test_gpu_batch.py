@@ -73,7 +73,7 @@ def test_batch_tile_shapes_do_not_change_iterates():
     b = tv.BatchedSolver([g.shape for g in imgs], DEV)
     gts = [torch.from_numpy(g).to(DEV) for g in imgs]
     ref = None
-    for th, wpb in [(8, 4), (3, 1), (64, 2), (1, 4)]:
+    for th, wpb in [(8, 4), (3, 1), (64, 2), (1, 4), (16, 8)]:
         print(f"case: batch tile th={th} wpb={wpb}", flush=True)
         fs, rs = b.solve(gts, lam=0.1, max_iter=120, check_every=10,
                          gap_tol=-1.0, th=th, wpb=wpb)
@@ -160,7 +160,7 @@ def test_batch_autotune():
     imgs = small_batch(600)
     b = tv.BatchedSolver([g.shape for g in imgs], DEV)
     (th, wpb), ms = b.autotune([torch.from_numpy(g).to(DEV) for g in imgs])
-    assert th in (8, 16, 32, 64, 128) and wpb in (1, 2, 4) and ms > 0
+    assert th in (8, 16, 32, 64, 128) and wpb in (1, 2, 4, 8) and ms > 0
 
 
 def test_batch64_workload():
@@ -203,11 +203,11 @@ def test_batch_table_switches_do_not_change_iterates(mode):
     gts = [torch.from_numpy(d[1].astype(np.float32)).to(DEV) for d in data]
     b = tv.BatchedSolver([tuple(g.shape) for g in gts], DEV)
     ref = None
-    for th, th_short in [(32, 8), (16, 4), (24, 3), (64, 1)]:
-        print(f"case: batch64 {mode} th={th} th_short={th_short}", flush=True)
+    for th, th_short, wpb in [(32, 8, 4), (16, 4, 4), (24, 3, 4), (64, 1, 4), (32, 8, 8)]:
+        print(f"case: batch64 {mode} th={th} th_short={th_short} wpb={wpb}", flush=True)
         fs, rs = b.solve(gts, lam=w["lam"], max_iter=w["max_iter"],
                          check_every=w["check_every"], gap_tol=w["gap_tol"],
-                         mode=mode, th=th, wpb=4, th_short=th_short)
+                         mode=mode, th=th, wpb=wpb, th_short=th_short)
         out = ([f.cpu().numpy().copy() for f in fs], [r.iters for r in rs])
         assert all(r.converged for r in rs)
         if ref is None:

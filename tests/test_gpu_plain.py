@@ -203,8 +203,11 @@ def test_energy_gap_of_device_state_matches_oracle():
 
 def test_fused_gap_equals_standalone_gap():
     """A solve that stops at a check reports the gap reduced inside the sweep;
-    re-evaluating the frozen pair with the standalone kernel gives the same
-    value up to summation order."""
+    re-evaluating the frozen pair with the standalone kernel (float64 terms)
+    gives the same value up to the rounding of the sweep's float32 per-pixel
+    terms: a few units in the last place of each of 1/2 r^2, lam |grad f| and
+    <grad f, p> (|<grad f, p>| <= lam |grad f|), so at most 4 * 2^-24 (P +
+    lam TV) <= 5e-7 P (observed about 3e-9 P)."""
     shape = (257, 300)
     g32 = scene32(*shape, 12, 0.1, 80)
     s = tv.PlainSolver(shape, DEV)
@@ -213,8 +216,8 @@ def test_fused_gap_equals_standalone_gap():
     assert res.converged and res.iters > 0
     assert s.iteration() == res.iters
     P, D, gap = s.energy_gap(0.1)
-    assert abs(P - res.primal) <= 1e-12 * P
-    assert abs(gap - res.gap) <= 1e-9 * P
+    assert abs(P - res.primal) <= 5e-7 * P
+    assert abs(gap - res.gap) <= 5e-7 * P
     assert torch.equal(f, s.state(with_dual=False))
 
 
