@@ -56,7 +56,7 @@ struct BatchArgs {
   int32_t nimg, ntiles;
   int32_t max_iter, check_every;
   int32_t wpb;
-  int32_t switch_tiles;  // use short bands once fewer tall tiles are active
+  int32_t switch_tiles;  // SIMD slots: short bands once fewer tall tiles are active
   int32_t depth;         // longest pass (iterations per sweep), 1 .. kBatchMaxPass
 };
 

@@ -10,7 +10,7 @@
 //
 // Two drivers share the tile code:
 //  - persistent: one cooperative launch runs every iteration; waves take
-//    active tiles grid-stride, a grid barrier separates iterations, and on
+//    shares of the active tiles, a grid barrier separates iterations, and on
 //    check iterations the blocks reduce the per-image gaps, stop images and
 //    rebuild the active list;
 //  - graph blocks: one launch per iteration over the active list, the last
@@ -26,7 +26,10 @@ namespace {
 
 using namespace dev;
 
-constexpr long kSpinLimit = 1L << 24;  // ~1 s of s_sleep before giving up
+constexpr long kSpinLimit = 1L << 22;  // polls (seconds of them) before giving up
+// Set in the barrier generation word by a block whose wait ran out, so that
+// every waiting block leaves at its next poll.
+constexpr unsigned kGenError = 0x80000000u;
 
 __device__ __forceinline__ int load_i32(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -37,34 +40,38 @@ __device__ __forceinline__ SyncArea* sync_of(BatchHdr* h) {
 }
 
 // Grid-wide barrier for a co-resident grid (hierarchical arrival, one
-// generation word polled with a short sleep).  Every wait is bounded: after
-// kSpinLimit polls the barrier flags an error and every block leaves.
+// generation word polled with a short sleep; the ordering of sync.h: every
+// wave's stores in L2, one release per block before arriving, one acquire
+// per block after the generation moves).  Every wait is bounded: after
+// kSpinLimit polls the barrier flags an error, marks the generation word and
+// every block leaves.
 __device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
   __shared__ int s_ok;
+  wait_vmem();
   __syncthreads();
   if (threadIdx.x == 0) {
     SyncArea* sa = sync_of(h);
-    __threadfence();
+    release_agent();
     const unsigned g = gen;
-    int ok = 1;
+    unsigned seen;
     if (arrive_last(sa, gridDim.x)) {
-      __threadfence();
-      atomicAdd(&sa->gen.v, 1u);
+      seen = atomicAdd(&sa->gen.v, 1u) + 1u;
     } else {
       long spins = 0;
-      while (__hip_atomic_load(&sa->gen.v, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(4);
+      while ((seen = __hip_atomic_load(&sa->gen.v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT)) == g) {
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit) {
           atomicOr(&h->flags, kBatchErrBarrier);
-          ok = 0;
+          atomicOr(&sa->gen.v, kGenError);
+          seen = kGenError;
           break;
         }
       }
+      acquire_agent();
     }
-    __threadfence();
     gen = g + 1;
-    s_ok = ok && !(load_i32(&h->flags) & kBatchErrBarrier);
+    s_ok = (seen & kGenError) ? 0 : 1;
   }
   __syncthreads();
   return s_ok != 0;
@@ -101,6 +108,30 @@ __device__ __forceinline__ void tile_pass(const BatchArgs& a,
   c.th = D.theta;
   c.tau_prev = D.tau;   // every step of an image has its tau (at k = 0 any value)
   sweep_tile_xs<N, kBatchMargin, CHECK, false>(c, sg, sp);
+}
+
+// The waves' share of the active list.  The list is cut into one
+// contiguous chunk per XCD (blocks are dealt to the 8 XCDs round-robin), so
+// that bands sharing halo rows meet in one L2; inside a chunk consecutive
+// tiles go to the XCD's blocks before their further waves, so that a short
+// list (the last images of a batch) spreads over every CU at one wave per
+// SIMD instead of stacking the waves of a few CUs.  A wave sweeps tiles
+// active[base + j] for j = first, first + step, ... below end.
+struct TileShare {
+  int base, first, step, end;
+};
+
+__device__ __forceinline__ TileShare tile_share(int nact, int wave, int wpb) {
+  const int nb = gridDim.x;
+  const int nx = (nb % kSyncGroups == 0) ? kSyncGroups : 1;
+  const int per = (nact + nx - 1) / nx;  // tiles per chunk
+  const int bx = nb / nx;                // blocks per chunk
+  TileShare r;
+  r.base = (blockIdx.x % nx) * per;
+  r.first = wave * bx + blockIdx.x / nx;
+  r.step = wpb * bx;
+  r.end = min(per, nact - r.base);
+  return r;
 }
 
 template <bool CHECK>
@@ -162,9 +193,9 @@ __device__ int running_tiles(const BatchArgs& a, int tbl) {
 }
 
 // Rebuild the active tile list from the images that still run (one block).
-// Once fewer tall-band tiles than waves remain, switch for good to the
-// first short-band table, and from there to a table of shorter bands
-// whenever its tiles still fit the waves: the iterates do not depend on the
+// Once fewer tall-band tiles than SIMD slots (switch_tiles) remain, switch
+// for good to the first short-band table, and from there to a table of
+// shorter bands whenever its tiles still fit the slots: the iterates do not depend on the
 // tiling, and a shorter band is a shorter serial walk for its wave, which
 // is what a pass costs while only a few images are left.
 __device__ void compact_active(const BatchArgs& a) {
@@ -194,11 +225,11 @@ __device__ void compact_active(const BatchArgs& a) {
     if (threadIdx.x == 0 && !conv) s_pos = pos + count;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    __threadfence();
+  // (the grid barrier or the kernel boundary that follows a rebuild
+  // publishes the list and its length)
+  if (threadIdx.x == 0)
     __hip_atomic_store(&a.hdr->n_active, s_pos, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-  }
   __syncthreads();
 }
 
@@ -209,24 +240,25 @@ __global__ __launch_bounds__(kBatchBlock) void batch_persistent_kernel(
   unsigned gen = __hip_atomic_load(&sync_of(h)->gen.v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   const int wave = wave_in_block();
-  const int nw = gridDim.x * a.wpb;
-  const int gw = blockIdx.x * a.wpb + wave;
   int k = 0, slot = 0;
+  // the active list and its table change only when an image stops
+  int nact = load_i32(&h->n_active);
+  int tbl = load_i32(&h->table);
   while (k < a.max_iter) {
     const bool check = a.check_every > 0 && (k % a.check_every) == 0;
     const int n = batch_pass_len(k, a.max_iter, a.check_every, a.depth);
-    const int nact = load_i32(&h->n_active);
     if (nact == 0) break;
-    if (wave < a.wpb)
-      for (int idx = gw; idx < nact; idx += nw) {
+    if (wave < a.wpb) {
+      const TileShare r = tile_share(nact, wave, a.wpb);
+      for (int j = r.first; j < r.end; j += r.step) {
         if (check)
-          do_tile<true>(a, a.active[idx], slot, n);
+          do_tile<true>(a, a.active[r.base + j], slot, n);
         else
-          do_tile<false>(a, a.active[idx], slot, n);
+          do_tile<false>(a, a.active[r.base + j], slot, n);
       }
+    }
     if (!grid_barrier(h, gen)) return;
     if (check) {
-      const int tbl = load_i32(&h->table);
       for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
         if (!a.state[i].converged) reduce_image(a, i, k, slot, tbl, red);
       if (!grid_barrier(h, gen)) return;
@@ -238,6 +270,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_persistent_kernel(
           if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
         }
         if (!grid_barrier(h, gen)) return;
+        nact = load_i32(&h->n_active);
+        tbl = load_i32(&h->table);
       }
     }
     k += n;
@@ -264,19 +298,22 @@ __global__ __launch_bounds__(kBatchBlock) void batch_sweep_kernel(BatchArgs a,
   const int nact = h->n_active;
   if (nact == 0) return;
   const int wave = wave_in_block();
-  const int nw = gridDim.x * a.wpb;
-  const int gw = blockIdx.x * a.wpb + wave;
-  if (wave < a.wpb)
-    for (int idx = gw; idx < nact; idx += nw)
-      do_tile<CHECK>(a, a.active[idx], slot, n);
+  if (wave < a.wpb) {
+    const TileShare r = tile_share(nact, wave, a.wpb);
+    for (int j = r.first; j < r.end; j += r.step)
+      do_tile<CHECK>(a, a.active[r.base + j], slot, n);
+  }
+  // the partials of every wave in L2, one release per block (sync.h); the
+  // last block acquires in arrive_last, the planes reach the next launch
+  // across the kernel boundary
+  wait_vmem();
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    release_agent();
     s_last = arrive_last(sync_of(h), gridDim.x) ? 1 : 0;
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   if (CHECK) {
     const int tbl = h->table;
     for (int i = 0; i < a.nimg; ++i)

@@ -118,7 +118,7 @@ constexpr int kShortBand = 8;
 
 void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
                  const int64_t* offsets, const tvpd_params* prm, int th,
-                 int th_short, int wpb, int nwaves, char* ws, BatchSetup& B) {
+                 int th_short, int wpb, int slots, char* ws, BatchSetup& B) {
   B.host.assign(L.off_part, 0);
   char* h = B.host.data();
   ImgDesc* imgs = reinterpret_cast<ImgDesc*>(h + L.off_imgs);
@@ -168,8 +168,8 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
     for (int i = 0; i < n; ++i) c += imgs[i].tile_count[tbl];
     return c;
   };
-  int tbl0 = tiles_of(0) < nwaves ? 1 : 0;
-  while (tbl0 >= 1 && tbl0 + 1 < kBatchTables && tiles_of(tbl0 + 1) <= nwaves) ++tbl0;
+  int tbl0 = tiles_of(0) < slots ? 1 : 0;
+  while (tbl0 >= 1 && tbl0 + 1 < kBatchTables && tiles_of(tbl0 + 1) <= slots) ++tbl0;
   int na = 0;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < imgs[i].tile_count[tbl0]; ++j)
@@ -192,7 +192,7 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   a.max_iter = prm[0].max_iter;
   a.check_every = prm[0].check_every;
   a.wpb = wpb;
-  a.switch_tiles = nwaves;
+  a.switch_tiles = slots;
   a.depth = pass_depth() < kBatchMaxPass ? pass_depth() : kBatchMaxPass;
 }
 
@@ -287,8 +287,9 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return TVPD_ERR_ALIGNMENT;
   if (ws_bytes < L.bytes) return TVPD_ERR_WORKSPACE;
   // grid of the driver: one block per CU for the persistent kernel (capped by
-  // co-residency), two (one of 8 waves) for the launch drivers; every block
-  // sweeps tiles grid-stride.  One persistent block per CU is faster on the 64
+  // co-residency), two (one of 8 waves) for the launch drivers; the waves
+  // share the active tiles out (tile_share).  One persistent block per CU is
+  // faster on the 64
   // uneven images (61.7 against 66.4 ms with two of 4 waves): the grid
   // barrier costs by the block; one block of 8 waves, two per SIMD, takes
   // 55.7 ms against 59.1 with 4 waves, the extra waves shortening the
@@ -311,7 +312,11 @@ int solve_batched_impl(int n, const tvpd_shape* shapes, const int64_t* offsets,
     grid = std::min(cus, cap);
   }
   BatchSetup B;
-  build_setup(L, n, shapes, offsets, prm, th, th_short, wpb, grid * wpb,
+  // Short-band tables are taken while their tiles fit one wave per SIMD: a
+  // walk is issue-bound once few images are left, and two waves sharing a
+  // SIMD double its time, more than the longer walk of the next taller band.
+  const int slots = std::min(grid * wpb, 4 * cus);
+  build_setup(L, n, shapes, offsets, prm, th, th_short, wpb, slots,
               static_cast<char*>(ws), B);
   BHIP(hipMemcpyAsync(ws, B.host.data(), B.host.size(), hipMemcpyHostToDevice,
                       s));

@@ -26,16 +26,18 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
       store_agent(&partials[2 * blockIdx.x + 1], acc_P);
     }
   }
-  __syncthreads();  // every wave of the block has read k and finished
+  // Every wave of the block has read k and finished.  Only thread 0 stored
+  // data the last block reads (the partials): its release covers them, and
+  // the planes reach the next launch across the kernel boundary.
+  __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    release_agent();
     SyncArea* sa = reinterpret_cast<SyncArea*>(reinterpret_cast<char*>(st) +
                                                kSyncOffset);
     s_last = arrive_last(sa, nb) ? 1 : 0;
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
   if constexpr (!GAP) {
     if (threadIdx.x == 0) {
       st->k = k + STEP;
