@@ -20,11 +20,24 @@ struct ImgDesc {
   double tol;        // relative gap tolerance (< 0: never stop)
 };
 
+// Plane block of an image in the batch arena: f in three slots, the dual
+// (x, y) in two, and g.  Pass j (iterations k -> k+n) reads f slot j mod 3
+// and dual slot j mod 2 and writes the next ones.  The third f slot lets the
+// persistent driver decide a gap check while the next pass already runs:
+// that pass writes f slot j+2 mod 3, so the f^k of an image stopped at the
+// check of pass j survives until the stop is known, one grid barrier later.
+constexpr int kBatchPlanes = 8;
+constexpr int kBatchG = 7;
+__host__ __device__ inline int batch_f(int fslot) { return fslot; }
+__host__ __device__ inline int batch_p(int pslot) { return 3 + 2 * pslot; }
+__host__ __device__ inline int batch_fslot(int pass) { return pass % 3; }
+__host__ __device__ inline int batch_pslot(int pass) { return pass & 1; }
+
 // Per-image result (device).
 struct ImgState {
   int32_t converged;
   int32_t iters;
-  int32_t slot;      // plane slot of the returned iterate once stopped
+  int32_t fslot;     // f slot of the returned iterate once stopped
   int32_t pad;
   double P, D, gap;
 };
@@ -41,7 +54,7 @@ struct BatchHdr {
   int32_t n_active;      // entries of the active tile list
   int32_t flags;         // error bits
   int32_t table;         // tile table in use: 0 tall bands, then shorter ones
-  int32_t slot;          // plane slot of f^k and p^k of the running images
+  int32_t pass;          // passes made: the plane slots of f^k and p^k
 };
 
 struct BatchArgs {
@@ -50,7 +63,7 @@ struct BatchArgs {
   ImgState* state;
   const TileDesc* tiles;
   int32_t* active;
-  double* partials;  // 2 per tile
+  double* partials;  // 4 per tile: (gap, P) of a check, by pass parity
   double* fparts;    // 2 per (image, final block)
   float* arena;
   int32_t nimg, ntiles;
@@ -91,7 +104,6 @@ constexpr int kFinalBlocks = 32;  // blocks per image of the final pass
 // block per CU holds two waves per SIMD (the grid barrier costs by the
 // block, the tile walks gain from the waves).
 constexpr int kBatchBlock = 512;
-constexpr int kBatchMaxWpb = kBatchBlock / kWave;
 
 hipError_t launch_batch_init(const BatchArgs& a, const float* g,
                              const int64_t* offs_dev, hipStream_t s);

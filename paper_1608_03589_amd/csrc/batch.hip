@@ -4,15 +4,16 @@
 //
 // All images live in one arena; a tile table lists every (image, strip,
 // band) tile, and an active list holds the tiles of the images that have not
-// stopped.  All running images are at the same iteration k, so the ring
-// slots are shared; an image that stops at k keeps f^k and p^k in the slots
-// of k and is never touched again.
+// stopped.  All running images are at the same iteration k, so the plane
+// slots are shared (batch.h); an image that stops at k keeps f^k in its slot
+// and is dropped from the active list before a pass could overwrite it.
 //
 // Two drivers share the tile code:
 //  - persistent: one cooperative launch runs every iteration; waves take
-//    shares of the active tiles, a grid barrier separates iterations, and on
-//    check iterations the blocks reduce the per-image gaps, stop images and
-//    rebuild the active list;
+//    shares of the active tiles and a grid barrier separates passes.  The
+//    gaps of a check are reduced and the stopping rule applied by one wave
+//    per image during the next pass, and the stopped images leave the active
+//    list after that pass's barrier, so a check costs no barrier of its own;
 //  - graph blocks: one launch per iteration over the active list, the last
 //    block to finish doing the per-image bookkeeping; launches are replayed
 //    from HIP graphs of check_every iterations.
@@ -77,25 +78,26 @@ __device__ bool grid_barrier(BatchHdr* h, unsigned& gen) {
   return s_ok != 0;
 }
 
-// Sweep one tile by a pass of n iterations k -> k+n (tile2d_xs.h, strips of
-// kBatchStrip owned columns), reading the planes of `slot` and writing the
-// other slot's; on check iterations lane 0 stores the tile's partials (the
-// gap of (f^k, p^k)).  Plane block of an image: the plain solver's layout.
+// Sweep one tile by pass `pass` of n iterations k -> k+n (tile2d_xs.h,
+// strips of kBatchStrip owned columns), reading the pass's plane slots and
+// writing the next ones (batch.h); on check iterations lane 0 stores the
+// tile's partials (the gap of (f^k, p^k)) in the pass parity's pair.
 template <int N, bool CHECK>
 __device__ __forceinline__ void tile_pass(const BatchArgs& a,
-                                          const TileDesc& T, int slot,
+                                          const TileDesc& T, int pass,
                                           double& sg, double& sp) {
   const ImgDesc& D = a.imgs[T.img];
   float* base = a.arena + D.off;
   const int64_t PL = D.plane;
+  const int fs = batch_fslot(pass), ps = batch_pslot(pass);
   TileCtxS c;
-  c.F = base + plain_f(slot) * PL;
-  c.FN = base + plain_f(slot ^ 1) * PL;
-  c.PX = base + plain_p(slot) * PL;
+  c.F = base + batch_f(fs) * PL;
+  c.FN = base + batch_f(fs == 2 ? 0 : fs + 1) * PL;
+  c.PX = base + batch_p(ps) * PL;
   c.PY = c.PX + PL;
-  c.QX = base + plain_p(slot ^ 1) * PL;
+  c.QX = base + batch_p(ps ^ 1) * PL;
   c.QY = c.QX + PL;
-  c.G = base + kPlainG * PL;
+  c.G = base + kBatchG * PL;
   c.ny = D.ny;
   c.nx = D.nx;
   c.pitch = D.pitch;
@@ -134,42 +136,51 @@ __device__ __forceinline__ TileShare tile_share(int nact, int wave, int wpb) {
   return r;
 }
 
+// Partials of tile t from a check in a pass of parity `par`: (gap, P).
+__device__ __forceinline__ double* tile_partials(const BatchArgs& a, int t,
+                                                 int par) {
+  return a.partials + 4 * (int64_t)t + 2 * par;
+}
+
 template <bool CHECK>
-__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int slot,
+__device__ __forceinline__ void do_tile(const BatchArgs& a, int t, int pass,
                                         int n) {
   const TileDesc T = a.tiles[t];
   double sg = 0.0, sp = 0.0;
   switch (n) {
-    case 1: tile_pass<1, CHECK>(a, T, slot, sg, sp); break;
-    case 2: tile_pass<2, CHECK>(a, T, slot, sg, sp); break;
-    default: tile_pass<5, CHECK>(a, T, slot, sg, sp); break;
+    case 1: tile_pass<1, CHECK>(a, T, pass, sg, sp); break;
+    case 2: tile_pass<2, CHECK>(a, T, pass, sg, sp); break;
+    default: tile_pass<5, CHECK>(a, T, pass, sg, sp); break;
   }
   static_assert(kBatchMaxPass == 5, "one case per pass length");
   if (CHECK) {
     sg = wave_sum(sg);
     sp = wave_sum(sp);
     if ((threadIdx.x & (kWave - 1)) == 0) {
-      store_agent(&a.partials[2 * t], sg);
-      store_agent(&a.partials[2 * t + 1], sp);
+      double* q = tile_partials(a, t, pass & 1);
+      store_agent(q, sg);
+      store_agent(q + 1, sp);
     }
   }
 }
 
-// Reduce the gap partials of image i in a fixed order (whole block) and
-// apply the stopping rule; thread 0 updates the image state.  `tbl` is the
-// tile table the check iteration was swept with, `slot` the plane slot of
-// (f^k, p^k).
-__device__ void reduce_image(const BatchArgs& a, int i, int k, int slot, int tbl,
-                             double (*red)[kBatchMaxWpb]) {
+// Reduce the gap partials of image i from the check at iteration k, made
+// in pass `pass` with tile table `tbl`, in a fixed order (one wave), and
+// apply the stopping rule; lane 0 updates the image state.
+__device__ void reduce_image(const BatchArgs& a, int i, int k, int pass,
+                             int tbl) {
   const ImgDesc& D = a.imgs[i];
   const int first = D.tile_first[tbl], count = D.tile_count[tbl];
+  const int lane = threadIdx.x & (kWave - 1);
   double sg = 0.0, sp = 0.0;
-  for (int j = threadIdx.x; j < count; j += blockDim.x) {
-    sg += load_agent(&a.partials[2 * (first + j)]);
-    sp += load_agent(&a.partials[2 * (first + j) + 1]);
+  for (int j = lane; j < count; j += kWave) {
+    const double* q = tile_partials(a, first + j, pass & 1);
+    sg += load_agent(q);
+    sp += load_agent(q + 1);
   }
-  block_sum2(sg, sp, red);
-  if (threadIdx.x == 0) {
+  sg = wave_sum(sg);
+  sp = wave_sum(sp);
+  if (lane == 0) {
     ImgState& S = a.state[i];
     S.gap = sg;
     S.P = sp;
@@ -177,11 +188,10 @@ __device__ void reduce_image(const BatchArgs& a, int i, int k, int slot, int tbl
     if (D.tol >= 0.0 && sg <= D.tol * sp) {
       S.converged = 1;
       S.iters = k;
-      S.slot = slot;
+      S.fslot = batch_fslot(pass);
       atomicOr(&a.hdr->flags, kBatchStopped);  // the active list must shrink
     }
   }
-  __syncthreads();
 }
 
 // Tiles of table `tbl` over the images that still run.
@@ -235,34 +245,39 @@ __device__ void compact_active(const BatchArgs& a) {
 
 __global__ __launch_bounds__(kBatchBlock) void batch_persistent_kernel(
     BatchArgs a) {
-  __shared__ double red[2][kBatchMaxWpb];
   BatchHdr* h = a.hdr;
   unsigned gen = __hip_atomic_load(&sync_of(h)->gen.v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   const int wave = wave_in_block();
-  int k = 0, slot = 0;
+  int k = 0, pass = 0;
   // the active list and its table change only when an image stops
   int nact = load_i32(&h->n_active);
   int tbl = load_i32(&h->table);
+  // the check whose stopping decisions are being made: iteration, pass and
+  // tile table (ck < 0: none)
+  int ck = -1, cpass = 0, ctbl = 0;
   while (k < a.max_iter) {
+    if (nact == 0) break;
     const bool check = a.check_every > 0 && (k % a.check_every) == 0;
     const int n = batch_pass_len(k, a.max_iter, a.check_every, a.depth);
-    if (nact == 0) break;
+    // the last wave of a block decides its images before taking tiles; the
+    // pass writes f slot pass+1 mod 3, so f^ck of a stopped image survives
+    if (ck >= 0 && wave == a.wpb - 1)
+      for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
+        if (!a.state[i].converged) reduce_image(a, i, ck, cpass, ctbl);
     if (wave < a.wpb) {
       const TileShare r = tile_share(nact, wave, a.wpb);
       for (int j = r.first; j < r.end; j += r.step) {
         if (check)
-          do_tile<true>(a, a.active[r.base + j], slot, n);
+          do_tile<true>(a, a.active[r.base + j], pass, n);
         else
-          do_tile<false>(a, a.active[r.base + j], slot, n);
+          do_tile<false>(a, a.active[r.base + j], pass, n);
       }
     }
     if (!grid_barrier(h, gen)) return;
-    if (check) {
-      for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
-        if (!a.state[i].converged) reduce_image(a, i, k, slot, tbl, red);
-      if (!grid_barrier(h, gen)) return;
-      // rebuild the active list only when an image stopped at this check
+    if (ck >= 0) {
+      // the decisions are out: rebuild the active list if an image stopped
+      ck = -1;
       if (load_i32(&h->flags) & kBatchStopped) {
         if (!grid_barrier(h, gen)) return;  // every block has read the flag
         if (blockIdx.x == 0) {
@@ -274,12 +289,21 @@ __global__ __launch_bounds__(kBatchBlock) void batch_persistent_kernel(
         tbl = load_i32(&h->table);
       }
     }
+    if (check) {
+      ck = k;
+      cpass = pass;
+      ctbl = tbl;
+    }
     k += n;
-    slot ^= 1;
+    ++pass;
   }
+  // a check in the last pass is decided here (the final kernel follows)
+  if (ck >= 0 && wave == a.wpb - 1)
+    for (int i = blockIdx.x; i < a.nimg; i += gridDim.x)
+      if (!a.state[i].converged) reduce_image(a, i, ck, cpass, ctbl);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     h->k = k;
-    h->slot = slot;
+    h->pass = pass;
   }
 }
 
@@ -289,19 +313,18 @@ __global__ __launch_bounds__(kBatchBlock) void batch_persistent_kernel(
 template <bool CHECK>
 __global__ __launch_bounds__(kBatchBlock) void batch_sweep_kernel(BatchArgs a,
                                                                   int n) {
-  __shared__ double red[2][kBatchMaxWpb];
   __shared__ int s_last;
   BatchHdr* h = a.hdr;
   const int k = h->k;
   if (k + n > a.max_iter) return;
-  const int slot = h->slot;
+  const int pass = h->pass;
   const int nact = h->n_active;
   if (nact == 0) return;
   const int wave = wave_in_block();
   if (wave < a.wpb) {
     const TileShare r = tile_share(nact, wave, a.wpb);
     for (int j = r.first; j < r.end; j += r.step)
-      do_tile<CHECK>(a, a.active[r.base + j], slot, n);
+      do_tile<CHECK>(a, a.active[r.base + j], pass, n);
   }
   // the partials of every wave in L2, one release per block (sync.h); the
   // last block acquires in arrive_last, the planes reach the next launch
@@ -316,8 +339,11 @@ __global__ __launch_bounds__(kBatchBlock) void batch_sweep_kernel(BatchArgs a,
   if (!s_last) return;
   if (CHECK) {
     const int tbl = h->table;
-    for (int i = 0; i < a.nimg; ++i)
-      if (!a.state[i].converged) reduce_image(a, i, k, slot, tbl, red);
+    if (wave < a.wpb)
+      for (int i = wave; i < a.nimg; i += a.wpb)
+        if (!a.state[i].converged) reduce_image(a, i, k, pass, tbl);
+    wait_vmem();
+    __syncthreads();
     if (load_i32(&h->flags) & kBatchStopped) {
       compact_active(a);
       if (threadIdx.x == 0) atomicAnd(&h->flags, ~kBatchStopped);
@@ -325,7 +351,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_sweep_kernel(BatchArgs a,
   }
   if (threadIdx.x == 0) {
     h->k = k + n;
-    h->slot = slot ^ 1;
+    h->pass = pass + 1;
   }
 }
 
@@ -342,9 +368,9 @@ __global__ void batch_init_kernel(BatchArgs a, const float* __restrict__ g,
     const int y = (int)(e / D.pitch);
     const int x = (int)(e - (int64_t)y * D.pitch);
     const float v = (x < D.nx) ? gi[(int64_t)y * D.nx + x] : 0.0f;
-    for (int s = 0; s < kPlainPlanes2D; ++s) base[s * PL + e] = 0.0f;
-    base[plain_f(0) * PL + e] = v;   // f^0 (f^{-1} = f^0 is implied)
-    base[kPlainG * PL + e] = v;      // g
+    for (int s = 0; s < kBatchPlanes; ++s) base[s * PL + e] = 0.0f;
+    base[batch_f(batch_fslot(0)) * PL + e] = v;  // f^0
+    base[kBatchG * PL + e] = v;                  // g
   }
 }
 
@@ -358,13 +384,13 @@ __global__ __launch_bounds__(kMaxBlock) void batch_final_kernel(
   const ImgDesc& D = a.imgs[i];
   const ImgState& S = a.state[i];
   const int conv = S.converged;
-  const int slot = conv ? S.slot : a.hdr->slot;
+  const int pass = a.hdr->pass;
   const float* base = a.arena + D.off;
   const int64_t PL = D.plane;
-  const float* f = base + plain_f(slot) * PL;
-  const float* px = base + plain_p(slot) * PL;
+  const float* f = base + batch_f(conv ? S.fslot : batch_fslot(pass)) * PL;
+  const float* px = base + batch_p(batch_pslot(pass)) * PL;  // (running only)
   const float* py = px + PL;
-  const float* g = base + kPlainG * PL;
+  const float* g = base + kBatchG * PL;
   const int64_t n = (int64_t)D.ny * D.nx;
   const int P = D.pitch;
   double sg = 0.0, sp = 0.0;

@@ -46,7 +46,7 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
     L.img_pitch.push_back(pitch);
     L.img_plane.push_back(plane);
     L.img_off.push_back(arena);
-    arena += kPlainPlanes2D * plane;
+    arena += kBatchPlanes * plane;
     // each tile table holds at most ny tiles per strip (bands of >= 1 row)
     L.tmax += (int64_t)((s[i].nx + kBatchStrip - 1) / kBatchStrip) *
               kBatchTables * s[i].ny;
@@ -63,7 +63,7 @@ BatchLayout make_batch_layout(int n, const tvpd_shape* s) {
   L.off_active = o;
   o = align_up(o + L.tmax * sizeof(int32_t), kAlign);
   L.off_part = o;
-  o = align_up(o + L.tmax * 2 * sizeof(double), kAlign);
+  o = align_up(o + L.tmax * 4 * sizeof(double), kAlign);
   L.off_fpart = o;
   o = align_up(o + (size_t)n * kFinalBlocks * 2 * sizeof(double), kAlign);
   L.off_arena = o;

@@ -203,8 +203,9 @@ def test_batch_workspace_size_bounds_the_tile_tables(L):
     n = C.c_size_t()
     ok = (Shape * 2)(Shape(2, 1, 300, 700), Shape(2, 1, 17, 5))
     assert L.tvpd_batch_workspace_size(2, ok, C.byref(n)) == 0
-    # the arena alone: 7 planes of 300 x 700 and of 17 x 8 (pitch) floats
-    assert n.value > 7 * 4 * (300 * 700 + 17 * 8)
+    # the arena alone: 8 planes (three f slots, two dual slots of x and y, g)
+    # of 300 x 700 and of 17 x 8 (pitch) floats
+    assert n.value > 8 * 4 * (300 * 700 + 17 * 8)
     # 4 tile tables of one entry per row and 256-column strip must fit int32
     big = (Shape * 1)(Shape(2, 1, 1 << 20, 1 << 20))
     assert L.tvpd_batch_workspace_size(1, big, C.byref(n)) == -6
