@@ -68,12 +68,12 @@ struct AdjRowB {
 
 // t from s for a pixel with dual argument q (same branch as the forward).
 __device__ __forceinline__ void adj_project2(float qx, float qy, float sx,
-                                             float sy, float lam, float lam2,
+                                             float sy, float lam,
                                              float& tx, float& ty,
                                              float& ns_out, bool& outside) {
   const float n2 = sq2(qx, qy);
-  outside = n2 > lam2;
   const float rn = inv_norm(n2);
+  outside = ball_scale_r(rn, lam) < 1.0f;
   const float nx = qx * rn, ny = qy * rn;
   float ns = nx * sx;
   ns = ns + ny * sy;
@@ -93,7 +93,6 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
   const bool lin = xc < c.pitch;
   const bool hl = (lane == 0) && (x0 > 0);
   const float lam = c.lam, tau = c.tau, sig = c.sig, th = c.th;
-  const float lam2 = lam * lam;
   const float iopt = prox_factor(tau);
   const float opth = 1.0f + th;
   const int xcl = min(xc, c.pitch - kColsPerLane);
@@ -160,12 +159,12 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
       const float gy = dn ? nb.v[j] - cb.v[j] : 0.0f;
       const float qx = dual_arg(pc.px.v[j], sig, gx);
       const float qy = dual_arg(pc.py.v[j], sig, gy);
-      project2(qx, qy, lam, lam2, pnx.v[j], pny.v[j]);
+      project2(qx, qy, lam, pnx.v[j], pny.v[j]);
       const float sx = pc.rx.v[j] - (xf ? rgta - ta.v[j] : 0.0f);
       const float sy = pc.ry.v[j] - (dn ? tan.v[j] - ta.v[j] : 0.0f);
       float ns;
       bool out;
-      adj_project2(qx, qy, sx, sy, lam, lam2, tx.v[j], ty.v[j], ns, out);
+      adj_project2(qx, qy, sx, sy, lam, tx.v[j], ty.v[j], ns, out);
       if (own && xc + j < nx) {
         if (out) lsum += ns;
         ssum += (double)tx.v[j] * (double)gx;
@@ -188,12 +187,12 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
         const float qx = dual_arg(pc.lpx, sig, gx);
         const float qy = dual_arg(pc.lpy, sig, gy);
         float hx, hy;
-        project2(qx, qy, lam, lam2, hx, hy);
+        project2(qx, qy, lam, hx, hy);
         const float sx = pc.lrx - (ta.v[0] - lta);
         const float sy = pc.lry - (dn ? ltan - lta : 0.0f);
         float htx, hty, ns;
         bool out;
-        adj_project2(qx, qy, sx, sy, lam, lam2, htx, hty, ns, out);
+        adj_project2(qx, qy, sx, sy, lam, htx, hty, ns, out);
         l_pn = hx;
         l_t = htx;
       }
@@ -208,8 +207,7 @@ __device__ __forceinline__ void adj_tile2d(const AdjCtx2D& c, double& acc_l,
         const float lt = (j == 0) ? l_t : tx.v[(j + 3) & 3];
         float d = pnx.v[j] - lpn;
         d = d + (pny.v[j] - up_pn.v[j]);
-        const float v = fmaf(tau, d, cur.f.v[j]);
-        const float fnew = fmaf(tau, pc.g.v[j], v) * iopt;
+        const float fnew = data_prox(cur.f.v[j], pc.g.v[j], d, tau, iopt);
         const float alpha = cur.a.v[j] * iopt;
         gbo.v[j] = pc.gb.v[j] + tau * alpha;
         if (xc + j < nx)

@@ -56,12 +56,12 @@ struct AdjPlaneP {
 // t from s for a voxel with dual argument q (same branch as the forward).
 __device__ __forceinline__ void adj_project3(float qx, float qy, float qz,
                                              float sx, float sy, float sz,
-                                             float lam, float lam2, float& tx,
+                                             float lam, float& tx,
                                              float& ty, float& tz,
                                              float& ns_out, bool& outside) {
   const float n2 = sq3(qx, qy, qz);
-  outside = n2 > lam2;
   const float rn = inv_norm(n2);
+  outside = ball_scale_r(rn, lam) < 1.0f;
   const float ux = qx * rn, uy = qy * rn, uz = qz * rn;
   float ns = ux * sx;
   ns = ns + uy * sy;
@@ -86,7 +86,6 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
   const bool lin = xc < c.pitch;
   const bool hl = x0 > 0;
   const float lam = c.lam, tau = c.tau, sig = c.sig, th = c.th;
-  const float lam2 = lam * lam;
   const float iopt = prox_factor(tau);
   const float opth = 1.0f + th;
   const int xcl = min(xc, c.pitch - kColsPerLane);
@@ -189,13 +188,13 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
           const float qx = dual_arg(pc.px[r].v[j], sig, gx);
           const float qy = dual_arg(pc.py[r].v[j], sig, gy);
           const float qz = dual_arg(pc.pz[r].v[j], sig, gz);
-          project3(qx, qy, qz, lam, lam2, pnx.v[j], pny.v[j], pnz.v[j]);
+          project3(qx, qy, qz, lam, pnx.v[j], pny.v[j], pnz.v[j]);
           const float sx = pc.rx[r].v[j] - (xf ? rgta - ta.v[j] : 0.0f);
           const float sy = pc.ry[r].v[j] - (dn ? tad.v[j] - ta.v[j] : 0.0f);
           const float sz = pc.rz[r].v[j] - (zf ? taz.v[j] - ta.v[j] : 0.0f);
           float ns;
           bool out;
-          adj_project3(qx, qy, qz, sx, sy, sz, lam, lam2, tx.v[j], ty.v[j],
+          adj_project3(qx, qy, qz, sx, sy, sz, lam, tx.v[j], ty.v[j],
                        tz.v[j], ns, out);
           if (xc + j < nx) {
             if (out) lsum += ns;
@@ -225,13 +224,13 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
               const float qy = dual_arg(pc.lpy[ri], sig, gy);
               const float qz = dual_arg(pc.lpz[ri], sig, gz);
               float hx, hy, hz;
-              project3(qx, qy, qz, lam, lam2, hx, hy, hz);
+              project3(qx, qy, qz, lam, hx, hy, hz);
               const float sx = pc.lrx[ri] - (ta.v[0] - lta);
               const float sy = pc.lry[ri] - (dn ? ltad - lta : 0.0f);
               const float sz = pc.lrz[ri] - (zf ? ltaz - lta : 0.0f);
               float htx, hty, htz, ns;
               bool out;
-              adj_project3(qx, qy, qz, sx, sy, sz, lam, lam2, htx, hty, htz,
+              adj_project3(qx, qy, qz, sx, sy, sz, lam, htx, hty, htz,
                            ns, out);
               if (lane == 0) {
                 l_pn = hx;
@@ -250,8 +249,7 @@ __device__ __forceinline__ void adj_tile3d(const AdjCtx3D& c, double& acc_l,
               float d = pnx.v[j] - lpn;
               d = d + (pny.v[j] - up_pn.v[j]);
               d = d + (pnz.v[j] - pzn[ri].v[j]);
-              const float v = fmaf(tau, d, cur.f[r].v[j]);
-              const float fnew = fmaf(tau, pc.g[ri].v[j], v) * iopt;
+              const float fnew = data_prox(cur.f[r].v[j], pc.g[ri].v[j], d, tau, iopt);
               const float alpha = cur.a[r].v[j] * iopt;
               gbo.v[j] = pc.gb[ri].v[j] + tau * alpha;
               if (xc + j < nx)

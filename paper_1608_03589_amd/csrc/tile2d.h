@@ -35,10 +35,10 @@ __device__ __forceinline__ F4 zero4() {
   return r;
 }
 
-// Projection of q onto the disc of radius lam (lam2 = lam * lam).
+// Projection of q onto the disc of radius lam.
 __device__ __forceinline__ void project2(float qx, float qy, float lam,
-                                         float lam2, float& px, float& py) {
-  const float c = ball_scale(sq2(qx, qy), lam, lam2);
+                                         float& px, float& py) {
+  const float c = ball_scale(sq2(qx, qy), lam);
   px = qx * c;
   py = qy * c;
 }

@@ -95,7 +95,6 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
   const bool owned = xg >= x0 && xg < x0 + kOwned && xg < c.pitch;
   const float lam = c.lam, tau = c.tau, sig = c.sig, th = c.th;
   const float iopt = prox_factor(tau);
-  const float lam2 = lam * lam;
   const float thtau = th * tau;            // fbar of the iterates this pass makes
   const float thtau0 = th * c.tau_prev;    // fbar^k
 
@@ -191,7 +190,6 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       const float lam_s = ALL ? c.slam[s - 1] : lam;
       const float tau_s = ALL ? c.stau[s - 1] : tau;
       const float sig_s = ALL ? c.ssig[s - 1] : sig;
-      const float lam2_s = ALL ? lam_s * lam_s : lam2;
       const float iopt_s = ALL ? prox_factor(tau_s) : iopt;
       const float thtau_s = ALL ? th * tau_s : thtau;
       const float nbr = from_right(cb.v[0]);
@@ -202,7 +200,7 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
         const float gx = (!kEdge || xg + j < nx - 1) ? right - cb.v[j] : 0.0f;
         const float gy = dn ? nb.v[j] - cb.v[j] : 0.0f;
         project2(dual_arg(EX.v[j], sig_s, gx), dual_arg(EY.v[j], sig_s, gy), lam_s,
-                 lam2_s, npx.v[j], npy.v[j]);
+                 npx.v[j], npy.v[j]);
       }
       const float left = from_left(npx.v[3]);
       const bool up = !kEdge || r > 0;
@@ -211,8 +209,7 @@ __device__ __forceinline__ void sweep_tile_xs(const TileCtxS& c,
       for (int j = 0; j < 4; ++j) {
         const float lp = (j == 0) ? ((!kEdge || xg > 0) ? left : 0.0f) : npx.v[j - 1];
         const float d = (npx.v[j] - lp) + (npy.v[j] - (up ? cy[s].v[j] : 0.0f));
-        const float v = fmaf(tau_s, d, B.v[j]);
-        fnew.v[j] = fmaf(tau_s, Gv.v[j], v) * iopt_s;
+        fnew.v[j] = data_prox(B.v[j], Gv.v[j], d, tau_s, iopt_s);
         fbnew.v[j] = PROX ? extrap_prox(fnew.v[j], Gv.v[j], d, thtau_s)
                           : extrap(fnew.v[j], B.v[j], th);
       }

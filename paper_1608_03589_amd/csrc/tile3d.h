@@ -44,11 +44,11 @@ struct Tile3DCtx {
   float lam, tau, sig, th;
 };
 
-// Projection of q onto the ball of radius lam (lam2 = lam * lam).
+// Projection of q onto the ball of radius lam.
 __device__ __forceinline__ void project3(float qx, float qy, float qz,
-                                         float lam, float lam2, float& px,
+                                         float lam, float& px,
                                          float& py, float& pz) {
-  const float c = ball_scale(sq3(qx, qy, qz), lam, lam2);
+  const float c = ball_scale(sq3(qx, qy, qz), lam);
   px = qx * c;
   py = qy * c;
   pz = qz * c;
@@ -92,7 +92,6 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
   const bool hl = x0 > 0;                       // a column x0-1 exists
   const float lam = c.lam, tau = c.tau, sig = c.sig, th = c.th;
   const float iopt = prox_factor(tau);
-  const float lam2 = lam * lam;
   const int xcl = min(xc, c.pitch - kColsPerLane);
   const int xlc = max(x0 - 1, 0);
   const int xrc = min(x0 + kStripCols, c.pitch - 1);
@@ -179,7 +178,7 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
           const float gy = dn ? db.v[j] - cb.v[j] : 0.0f;
           const float gz = zf ? zb.v[j] - cb.v[j] : 0.0f;
           project3(dual_arg(pc.px[r].v[j], sig, gx), dual_arg(pc.py[r].v[j], sig, gy),
-                   dual_arg(pc.pz[r].v[j], sig, gz), lam, lam2, npx.v[j], npy.v[j],
+                   dual_arg(pc.pz[r].v[j], sig, gz), lam, npx.v[j], npy.v[j],
                    npz.v[j]);
         }
         if (r > 0) {
@@ -199,7 +198,7 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
               const float gz = zf ? lzb - lb : 0.0f;
               float hx, hy, hz;
               project3(dual_arg(pc.lx[ri], sig, gx), dual_arg(pc.ly[ri], sig, gy),
-                       dual_arg(pc.lz[ri], sig, gz), lam, lam2, hx, hy, hz);
+                       dual_arg(pc.lz[ri], sig, gz), lam, hx, hy, hz);
               if (lane == 0) left_n = hx;
             } else if (lane == 0) {
               left_n = 0.0f;
@@ -210,8 +209,7 @@ __device__ __forceinline__ void sweep_tile3d(const Tile3DCtx& c,
               const float lp = (j == 0) ? left_n : npx.v[(j + 3) & 3];
               float d = (npx.v[j] - lp) + (npy.v[j] - up.v[j]);
               d = d + (npz.v[j] - pzn[ri].v[j]);
-              const float v = fmaf(tau, d, cur.f[r].v[j]);
-              fnew.v[j] = fmaf(tau, pc.g[ri].v[j], v) * iopt;
+              fnew.v[j] = data_prox(cur.f[r].v[j], pc.g[ri].v[j], d, tau, iopt);
             }
             if (lin) {
               const int64_t o = zo + (int64_t)y * P + xc;

@@ -69,7 +69,6 @@ __global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
   const float* pyi = par ? a.py1 : a.py0;
   float* pxo = par ? a.px0 : a.px1;
   float* pyo = par ? a.py0 : a.py1;
-  const float lam2 = a.lam * a.lam;
 #pragma unroll
   for (int rr = 0; rr < kTomoPrepTile; rr += 8) {
     const int r = a0 + ty + rr, c = b0 + tx;
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
         const float gy = r + 1 < ny ? fbar(r + 1, c) - v : 0.0f;
         float qx, qy;
         project2(dual_arg(pxi[o], a.sigma, gx), dual_arg(pyi[o], a.sigma, gy),
-                 a.lam, lam2, qx, qy);
+                 a.lam, qx, qy);
         pxo[o] = qx;
         pyo[o] = qy;
       }

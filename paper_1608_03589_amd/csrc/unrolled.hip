@@ -81,7 +81,7 @@ __device__ __forceinline__ float* plane(const PlaneSet& P, int b, int id) {
 template <int ND>
 __device__ __forceinline__ void project(const float* q, float lam, float* p) {
   const float n2 = ND == 3 ? sq3(q[0], q[1], q[2]) : sq2(q[0], q[1]);
-  const float c = ball_scale(n2, lam, lam * lam);
+  const float c = ball_scale(n2, lam);
 #pragma unroll
   for (int i = 0; i < ND; ++i) p[i] = q[i] * c;
 }
@@ -270,8 +270,8 @@ __global__ __launch_bounds__(kRowBlock) void u_adjA_kernel(
     project<ND>(qq, lam, pn);
     const float n2 = ND == 3 ? sq3(qq[0], qq[1], qq[2]) : sq2(qq[0], qq[1]);
     float t[ND];
-    if (n2 > lam * lam) {  // the forward's branch (ball_scale)
-      const float rn = inv_norm(n2);
+    const float rn = inv_norm(n2);
+    if (ball_scale_r(rn, lam) < 1.0f) {  // the forward's branch (ball_scale)
       float nv[ND];
       float ns = 0.0f;
 #pragma unroll
@@ -322,8 +322,7 @@ __global__ __launch_bounds__(kRowBlock) void u_adjB_kernel(
         div_point<ND>(cplane(P, q.b, ids.pn), P.plane, q.o, st, bwd);
     const float f = cplane(P, q.b, ids.fk)[q.o];
     const float g = cplane(P, q.b, ids.g)[q.o];
-    const float v = fmaf(tau, d, f);
-    const float fn = fmaf(tau, g, v) * iopt;
+    const float fn = data_prox(f, g, d, tau, iopt);
     const float alpha = cplane(P, q.b, ids.a_in)[q.o] * iopt;
     float* gbar = plane(P, q.b, ids.gbar);
     gbar[q.o] = gbar[q.o] + tau * alpha;
