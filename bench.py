@@ -686,7 +686,13 @@ def main():
                      "SQ_INSTS_VALU, overlap margins included) x 64 lanes, against one "
                      "wave64 instruction per CU and cycle (256 CUs, 2.4 GHz, no packed fp32)",
         }
-    binding = alu_bound if alu_bound and alu_bound["frac"] > hbm_bound["frac"] else hbm_bound
+    if traffic:
+        hbm_bound["measured_traffic_frac"] = traffic / launch_s / 1e9 / HBM_PEAK_GBS
+    # The binding unit is the one closer to saturation, HBM judged on the bytes
+    # the launch actually moves (halo re-reads included) when they are known;
+    # the reported fraction stays the algorithmic one of that unit.
+    hbm_use = hbm_bound.get("measured_traffic_frac", hbm_bound["frac"])
+    binding = alu_bound if alu_bound and alu_bound["frac"] > hbm_use else hbm_bound
 
     if args.copy_calibration:
         copy_calibration(dev)
@@ -749,6 +755,9 @@ def main():
             "unit": binding["unit"],
             "frac": binding["frac"],
             "bounds": {"hbm": hbm_bound, "alu": alu_bound},
+            "binding_basis": ("the unit closer to saturation: VALU issue against HBM on the "
+                              "measured traffic (the algorithmic bytes when no traffic "
+                              "profile matches the sources)"),
             "one_pass_equivalent_GBs": achieved,
             "one_pass_equivalent_basis": (
                 "32 B per pixel-iteration (one HBM pass per iteration): the bandwidth a "
