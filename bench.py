@@ -45,7 +45,8 @@ SQ_FILE = os.path.join(PROFILES, "sweep2d_xs5_denoise4096_sq.txt")
 TOMO_COUNTERS_FILE = os.path.join(PROFILES, "tomo_kernels_tomo2048x1000_counters.txt")
 CSRC = os.path.join(ROOT, "paper_1608_03589_amd", "csrc")
 KERNEL_SRCS = [os.path.join(CSRC, f)
-               for f in ("kernels2d.hip", "tile2d.h", "tile2d_xs.h", "pointwise.h")]
+               for f in ("kernels2d.hip", "tile2d.h", "tile2d_xs.h", "pointwise.h",
+                         "finish.h", "sync.h")]
 TOMO_SRCS = [os.path.join(CSRC, f)
              for f in ("tomo.hip", "tomo.h", "tile2d.h", "pointwise.h", "bst.hip", "lp.hip")]
 
@@ -137,10 +138,10 @@ def pass_schedule(iters, check_every, depth):
     return out
 
 
-def kernel_name(kernels, passes):
+def kernel_name(kernels, passes, pipelined=False):
     parts = []
     for n in kernels:
-        nm = f"sweep2d_xs_kernel<{n}>"
+        nm = "sweep2d_pipe_kernel" if pipelined else f"sweep2d_xs_kernel<{n}>"
         parts.append(f"{nm} ({n} iteration{'s' if n > 1 else ''} per launch, "
                      f"{passes.count(n)} launches per solve)")
     return "; ".join(parts) + "; the launch at each 10th iteration also reduces the gap"
@@ -197,7 +198,8 @@ def bench_denoise_256(dev):
     s = 1.0 / math.sqrt(8.0)
     rec = {"workload": "denoise_256", "image": [w["H"], w["W"]],
            "iterations": w["iters"], "gap_check_every": 10,
-           "launches_per_solve": len(pass_schedule(w["iters"], 10, tv.get_pass_depth()))}
+           "launches_per_solve": len(pass_schedule(w["iters"], 10,
+                                                   tv.pass_length(tuple(gt.shape))))}
     pix_its = w["H"] * w["W"] * w["iters"]
     for name, use_graph in (("direct", 0), ("graph", 1)):
         def run():
@@ -651,8 +653,8 @@ def main():
     # Dominant kernel: the fused sweep.  The solver runs the iterations as
     # passes of up to `depth` iterations per launch, a pass ending before the
     # next gap check (every 10 iterations); replay that schedule to count the
-    # launches (with depth 5: 400 launches of 5 iterations per solve).
-    depth = tv.get_pass_depth()
+    # launches (with passes of 10: 200 launches per solve).
+    depth = tv.pass_length((H, W))
     passes = pass_schedule(iters, 10, depth)
     launches = args.steps * len(passes)
     its_per_launch = iters / len(passes)
@@ -766,7 +768,7 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_vs_algorithmic": (traffic / pass_bytes) if traffic else None,
             "hbm_achieved_GBs": (traffic / launch_s / 1e9) if traffic else None,
-            "kernel": kernel_name(kernels, passes),
+            "kernel": kernel_name(kernels, passes, tile[2] == 2),
             "pixel_iterations_per_launch": pix * its_per_launch,
             "algorithmic_bytes_per_launch": pass_bytes,
             "avg_launch_us": launch_s * 1e6,

@@ -165,14 +165,18 @@ int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
  * Tiling of the fused 2D sweep.  A wave walks a band of `th` rows of a
  * 256-column strip; a block holds `wpb` consecutive wave tiles, numbered
  * band by band (order 0: a block's waves sit side by side) or strip by
- * strip (order 1: stacked).  The iterates do not depend on the tile (halo
- * values are recomputed with the owner's arithmetic), only the speed and the
- * summation order of the gap do.
+ * strip (order 1: stacked).  order 2 selects the pipelined passes instead:
+ * one block per band of `th` rows of a 232-column strip, whose waves run one
+ * iteration of the pass each and hand their rows on through LDS (wpb is not
+ * used; never the default, the autotuner tries it).  The iterates do not depend on the tile (halo values are
+ * recomputed with the owner's arithmetic), only the speed and the summation
+ * order of the gap do.
  * ------------------------------------------------------------------- */
 
 /* Use this tile for the 2D `shape` from now on in this process (overrides
- * the default and any autotuned choice).  th in [1, 65536], wpb in {1, 2, 4},
- * order in {0, 1}.  TVPD_ERR_UNSUPPORTED for a 3D shape. */
+ * the default and any autotuned choice).  th in [1, 65536], order in
+ * {0, 1, 2}, wpb in {1, 2, 4} for orders 0 and 1 (any value for order 2).
+ * TVPD_ERR_UNSUPPORTED for a 3D shape. */
 int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
                   int32_t order);
 
@@ -197,18 +201,26 @@ int tvpd_get_tile3d(const tvpd_shape* shape, int32_t* th, int32_t* tz,
  * against 32 per pixel-iteration for one pass per iteration that reads
  * f^{k-1}); a gap check
  * only ever falls on a pass's first iteration, so passes end before the next
- * check.  depth in 1 .. 6, default 5; the batched solver uses passes of 1,
- * 2 and (with depth >= 5) 5 iterations.  The iterates are bit-identical for
- * every depth.  Process-wide setting.
- * tvpd_set_blocking(0) is depth 1, tvpd_set_blocking(1) the default depth. */
+ * check.  depth 0 (the default) lets each kernel take its own longest pass,
+ * 5 for the strip walks and 10 for the pipelined passes; depth 1 .. 10 sets
+ * it for both, the strip walks capping it at 6.  The batched solver uses
+ * passes of 1, 2 and (with a walk depth >= 5) 5 iterations, the unrolled
+ * solver at most 5.  The iterates are bit-identical for every depth.
+ * Process-wide setting.  tvpd_set_blocking(0) is depth 1,
+ * tvpd_set_blocking(1) depth 0. */
 int tvpd_set_blocking(int32_t on);
 int tvpd_set_pass_depth(int32_t depth);
 int tvpd_get_pass_depth(int32_t* depth);
 
+/* The longest pass (iterations per launch) the plain solver takes for the
+ * 2D `shape` under the current tile and depth settings. */
+int tvpd_pass_length(const tvpd_shape* shape, int32_t* n);
+
 /* Autotuner.  Times every candidate tile of the sweep on `ws`, an
  * initialised workspace of this shape, and keeps the fastest for `shape` in
- * this process.  2D: th from 4 to 256, wpb 1/2/4, both orders, timing
- * passes of the pass depth in use.  3D: th 2/4, tz from 2 to 128,
+ * this process.  2D: th from 2 to 256, wpb 1/2/4, orders 0 and 1, and the
+ * pipelined passes (order 2) on bands of one to three tiles per CU and of
+ * 64, 128 and 256 rows, timing passes of the pass depth in use.  3D: th 2/4, tz from 2 to 128,
  * wpb 1/2/4; the chosen tz is returned in *order.  The workspace state is
  * advanced by the timing runs: call tvpd_init before solving with it.  If
  * cache_path is not NULL the choice is appended to that text file (one line

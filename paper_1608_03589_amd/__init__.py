@@ -17,7 +17,7 @@ from .unrolled import (  # noqa: F401
 )
 from .solver import (  # noqa: F401
     PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
-    get_pass_depth, get_tile, get_tile3d, make_shape, set_blocking,
+    get_pass_depth, get_tile, pass_length, get_tile3d, make_shape, set_blocking,
     set_pass_depth, set_tile, set_tile3d, solve, tune_load, workspace_size,
 )
 
@@ -28,7 +28,7 @@ __all__ = [
     "unrolled_tv",
     "alloc_workspace", "autotune",
     "tune_load",
-    "default_step", "get_pass_depth", "get_tile", "get_tile3d", "lib",
+    "default_step", "get_pass_depth", "pass_length", "get_tile", "get_tile3d", "lib",
     "make_shape", "set_pass_depth",
     "set_blocking", "set_tile", "set_tile3d", "solve",
     "workspace_size",

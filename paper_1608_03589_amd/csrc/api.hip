@@ -151,7 +151,8 @@ int enqueue_sweeps(const Layout& L, const tvpd_coeffs& c, int64_t k_first,
     return TVPD_OK;
   }
   const Tile2D t = tile2d_for(L);
-  const int depth = blocked ? pass_depth() : 1;
+  const int depth =
+      blocked ? (t.order == kOrderPipe ? pipe_depth() : walk_depth()) : 1;
   int i = 0;
   while (i < n) {
     const int64_t kk = k_first + i;
@@ -186,13 +187,22 @@ hipError_t launch_read(const Layout& L, const void* ws, float* f_out,
 }
 
 // Longest pass of the temporally blocked 2D sweep, process-wide
-// (tvpd_set_pass_depth; tvpd_set_blocking(0) means 1).
-constexpr int kDefaultDepth = 5;
-std::atomic<int> g_depth{kDefaultDepth};
+// (tvpd_set_pass_depth; 0: each kernel's default, the walk's kWalkDepth and
+// the pipelined passes' kPipeMaxPass; tvpd_set_blocking(0) means 1).
+constexpr int kWalkDepth = 5;
+std::atomic<int> g_depth{0};
 
 }  // namespace
 
 int pass_depth() { return g_depth.load(); }
+int walk_depth() {
+  const int d = g_depth.load();
+  return d == 0 ? kWalkDepth : std::min(d, kMaxPass);
+}
+int pipe_depth() {
+  const int d = g_depth.load();
+  return d == 0 ? kPipeMaxPass : std::min(d, kPipeMaxPass);
+}
 
 namespace {
 
@@ -207,7 +217,7 @@ int solve_plain(const Layout& L, const float* g, float* f_out,
 
   const int ce = prm.check_every;
   const bool can_stop = ce > 0 && prm.gap_tol >= 0.0;
-  const bool blocked = pass_depth() > 1;
+  const bool blocked = pass_depth() != 1;
   // chunk of iterations between host polls: a multiple of check_every
   int chunk = 64;
   if (ce > 0) chunk = ce * ((64 + ce - 1) / ce);
@@ -356,7 +366,7 @@ int tvpd_step(const tvpd_shape* shape, const tvpd_coeffs* c, int32_t n_iter,
   if (int rc = ws_ok(L, ws, ws_bytes)) return rc;
   hipStream_t s = (hipStream_t)stream;
   TVPD_HIP(launch_set_params(ws, INT_MAX, -1.0, s));
-  return enqueue_sweeps(L, *c, 0, n_iter, 0, pass_depth() > 1, ws, s);
+  return enqueue_sweeps(L, *c, 0, n_iter, 0, pass_depth() != 1, ws, s);
 }
 
 int tvpd_read_state(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
@@ -419,8 +429,9 @@ int tvpd_set_tile(const tvpd_shape* shape, int32_t th, int32_t wpb,
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
   if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
   if (th < 1 || th > 65536) return TVPD_ERR_INVALID_ARG;
-  if (wpb != 1 && wpb != 2 && wpb != 4) return TVPD_ERR_INVALID_ARG;
-  if (order != 0 && order != 1) return TVPD_ERR_INVALID_ARG;
+  if (order != 0 && order != 1 && order != kOrderPipe) return TVPD_ERR_INVALID_ARG;
+  if (order != kOrderPipe && wpb != 1 && wpb != 2 && wpb != 4)
+    return TVPD_ERR_INVALID_ARG;
   Tile2D t;
   t.th = th;
   t.wpb = wpb;
@@ -510,12 +521,12 @@ int tvpd_tune_load(const char* cache_path, int32_t* count) {
 
 int tvpd_set_blocking(int32_t on) {
   if (on != 0 && on != 1) return TVPD_ERR_INVALID_ARG;
-  g_depth.store(on ? kDefaultDepth : 1);
+  g_depth.store(on ? 0 : 1);
   return TVPD_OK;
 }
 
 int tvpd_set_pass_depth(int32_t depth) {
-  if (depth < 1 || depth > kMaxPass) return TVPD_ERR_INVALID_ARG;
+  if (depth < 0 || depth > kPipeMaxPass) return TVPD_ERR_INVALID_ARG;
   g_depth.store(depth);
   return TVPD_OK;
 }
@@ -523,6 +534,15 @@ int tvpd_set_pass_depth(int32_t depth) {
 int tvpd_get_pass_depth(int32_t* depth) {
   if (!depth) return TVPD_ERR_INVALID_ARG;
   *depth = g_depth.load();
+  return TVPD_OK;
+}
+
+int tvpd_pass_length(const tvpd_shape* shape, int32_t* n) {
+  if (!n) return TVPD_ERR_INVALID_ARG;
+  if (!shape_ok(shape)) return TVPD_ERR_SHAPE;
+  if (shape->ndim != 2) return TVPD_ERR_UNSUPPORTED;
+  const Tile2D t = tile2d_for(make_layout(*shape));
+  *n = t.order == kOrderPipe ? pipe_depth() : walk_depth();
   return TVPD_OK;
 }
 

@@ -66,11 +66,14 @@ std::string device_arch() {
 // bands of 2 rows: on images too small to fill the GPU a pass costs one band
 // walk of th + 2 depth - 1 steps, and at 256^2 (1000 iterations, depth 5)
 // bands of 2 rows took 3.7 ms against 4.3 and 5.3 ms with 4 and 8.
+// Pipelined passes (tile2d_pipe.h) are not a default: at 4096^2 they ran
+// 3% behind the walk (288 against 280 us per ten iterations), bound by the
+// issue of their longer per-row instruction chains; the autotuner tries them.
 Tile2D default_tile2d(const Layout& L) {
   Tile2D t;
   t.wpb = 4;
   t.order = 0;
-  const int depth = pass_depth();
+  const int depth = walk_depth();
   const int cus = device_cus();
   int64_t th;
   if (depth >= 3) {
@@ -198,7 +201,7 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
         t.wpb = w;
         t.order = order;
         float us = 0.0f;
-        rc = time_tile(L, t, pass_depth(), ws, s, e0, e1, &us);
+        rc = time_tile(L, t, walk_depth(), ws, s, e0, e1, &us);
         if (rc == TVPD_ERR_INVALID_ARG) {
           rc = TVPD_OK;
           continue;
@@ -212,6 +215,37 @@ int autotune2d(const tvpd_shape& sh, const Layout& L, void* ws, hipStream_t s,
       if (rc) break;
     }
     if (rc) break;
+  }
+  // pipelined passes: bands for one, two and three tiles per CU and a few
+  // fixed heights
+  if (rc == TVPD_OK && pass_depth() != 1) {
+    const int cus = device_cus();
+    const int ntx = (L.nx + kPipeOwned - 1) / kPipeOwned;
+    int pths[8];
+    int np = 0;
+    for (int m = 1; m <= 3; ++m) {
+      const int nty = m * cus / ntx;
+      if (nty >= 1) pths[np++] = (L.ny + nty - 1) / nty;
+    }
+    for (int th : {64, 128, 256}) pths[np++] = th;
+    for (int i = 0; i < np && rc == TVPD_OK; ++i) {
+      const int th = pths[i];
+      if (th < 1 || (th > L.ny && i >= 3)) continue;
+      Tile2D t;
+      t.th = th;
+      t.wpb = 1;
+      t.order = kOrderPipe;
+      float us = 0.0f;
+      rc = time_tile(L, t, pipe_depth(), ws, s, e0, e1, &us);
+      if (rc == TVPD_ERR_INVALID_ARG) {
+        rc = TVPD_OK;
+        continue;
+      }
+      if (rc == TVPD_OK && us < bu) {
+        bu = us;
+        bt = t;
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -345,8 +379,9 @@ int tune_load(const char* path, int* count) {
       ++n;
       continue;
     }
-    if (s.ndim != 2 || t.th < 1 || (t.wpb != 1 && t.wpb != 2 && t.wpb != 4) ||
-        (t.order != 0 && t.order != 1))
+    if (s.ndim != 2 || t.th < 1 ||
+        (t.order != 0 && t.order != 1 && t.order != kOrderPipe) ||
+        (t.order != kOrderPipe && t.wpb != 1 && t.wpb != 2 && t.wpb != 4))
       continue;
     remember_tile2d(s, t);  // later lines override earlier ones
     ++n;

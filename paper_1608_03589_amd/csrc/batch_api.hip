@@ -193,7 +193,7 @@ void build_setup(const BatchLayout& L, int n, const tvpd_shape* s,
   a.check_every = prm[0].check_every;
   a.wpb = wpb;
   a.switch_tiles = slots;
-  a.depth = pass_depth() < kBatchMaxPass ? pass_depth() : kBatchMaxPass;
+  a.depth = walk_depth() < kBatchMaxPass ? walk_depth() : kBatchMaxPass;
 }
 
 thread_local HostPoll t_pin;

@@ -69,7 +69,19 @@ __host__ __device__ constexpr int xs_margin(int n) { return n <= 3 ? 4 : 8; }
 __host__ __device__ constexpr int xs_owned(int n) {
   return kStripCols - 2 * xs_margin(n);
 }
-constexpr int kXsOwnedMin = kStripCols - 2 * xs_margin(kMaxPass);
+// Pipelined passes (tile2d_pipe.h): one block per tile whose waves run one
+// stage each, up to kPipeMaxPass iterations per launch, on strips with
+// margins of kPipeMargin >= kPipeMaxPass + 1 columns.
+constexpr int kPipeMaxPass = 10;
+constexpr int kPipeMargin = 12;
+constexpr int kPipeOwned = kStripCols - 2 * kPipeMargin;
+static_assert(kPipeMargin >= kPipeMaxPass + 1 && kPipeMargin % kColsPerLane == 0,
+              "pipelined strip margin");
+constexpr int kXsOwnedMin = kPipeOwned < kStripCols - 2 * xs_margin(kMaxPass)
+                                ? kPipeOwned
+                                : kStripCols - 2 * xs_margin(kMaxPass);
+// Threads of a pipelined block: one wave per stage and one for the gap.
+constexpr int kPipeMaxThreads = (kPipeMaxPass + 1) * kWave;
 
 // Plane block of the plain 2D solver: two slots, f in plane `slot` and p in
 // planes 2 + 2 slot (x) and 3 + 2 slot (y), and g in plane 6.  The slot of
@@ -95,7 +107,10 @@ __host__ __device__ inline int plain3_p(int k) { return 3 + 3 * (k & 1); }
 // order 0 numbers tiles band by band (consecutive tiles are horizontally
 // adjacent strips: concurrent waves read long contiguous row segments);
 // order 1 numbers them strip by strip (consecutive tiles are vertically
-// adjacent bands).
+// adjacent bands).  order 2 selects the pipelined passes instead: one block
+// per tile of kPipeOwned columns and `th` rows, numbered band by band (wpb
+// is not used).
+constexpr int kOrderPipe = 2;
 struct Tile2D {
   int th;
   int wpb;
@@ -109,6 +124,7 @@ struct Sweep2DArgs {
   int32_t ny, nx, pitch;
   int32_t th, wpb, order;
   int32_t ntx, nty, ntiles;  // wave tiles: ntx strips by nty row bands
+  int32_t n;                 // iterations of the pass (pipelined kernel)
   float lam, tau, sigma, theta;
   DevState* st;
   double* partials;   // 2 doubles per block (gap, P)
@@ -182,7 +198,11 @@ int tune_save(const char* path, const tvpd_shape& s, const Tile2D& t, float us);
 int tune_save3d(const char* path, const tvpd_shape& s, const Tile3D& t,
                 float us);
 int tune_load(const char* path, int* count);
-int pass_depth();         // longest pass in use, 1 .. kMaxPass (api.hip)
+// Longest pass of the plain 2D sweep (api.hip): 0 = each kernel's own
+// default, else the process-wide setting, capped by the kernel in use.
+int pass_depth();
+int walk_depth();         // strip walks (tile2d_xs.h): 1 .. kMaxPass
+int pipe_depth();         // pipelined passes (tile2d_pipe.h): 1 .. kPipeMaxPass
 
 // Host resources a driver keeps for polling device state while further work
 // is queued: pinned staging for two copies of a header, two events and a

@@ -8,15 +8,16 @@
 namespace tvpd {
 namespace dev {
 
-// Completion of a sweep: the last block to finish advances k and records
-// the step tau of the iterations made, or on a gap check reduces the
-// per-block partials (fixed order, float64), records the energies and
-// either freezes k (converged) or advances it.
-template <bool GAP, int STEP>
+// Completion of a sweep of `step` iterations: the last block to finish
+// advances k and records the step tau of the iterations made, or on a gap
+// check reduces the per-block partials (fixed order, float64), records the
+// energies and either freezes k (converged) or advances it.
+constexpr int kMaxBlockWaves = kPipeMaxThreads / kWave;
+template <bool GAP>
 __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
-                                             int k, double acc_gap,
+                                             int k, int step, double acc_gap,
                                              double acc_P, float tau) {
-  __shared__ double red[2][kMaxBlock / kWave];
+  __shared__ double red[2][kMaxBlockWaves];
   __shared__ int s_last;
   const unsigned nb = gridDim.x;
   if constexpr (GAP) {
@@ -40,7 +41,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
   if (!s_last) return;
   if constexpr (!GAP) {
     if (threadIdx.x == 0) {
-      st->k = k + STEP;
+      st->k = k + step;
       st->tau_prev = tau;
       st->slot ^= 1;
     }
@@ -61,7 +62,7 @@ __device__ __forceinline__ void finish_sweep(DevState* st, double* partials,
         st->converged = 1;
         st->iters = k;
       } else {
-        st->k = k + STEP;
+        st->k = k + step;
         st->tau_prev = tau;
         st->slot ^= 1;
       }

@@ -7,6 +7,7 @@
 // iteration counter kept in device memory, or on a gap check reduces the
 // per-block partials in a fixed order and applies the stopping rule.
 #include "finish.h"
+#include "tile2d_pipe.h"
 #include "tile2d_xs.h"
 
 namespace tvpd {
@@ -65,7 +66,50 @@ __global__ __launch_bounds__(kMaxBlock) void sweep2d_xs_kernel(Sweep2DArgs a) {
     c.tau_prev = tau_prev;
     sweep_tile_xs<S, xs_margin(S), GAP>(c, acc_gap, acc_P);
   }
-  finish_sweep<GAP, S>(st, a.partials, k, acc_gap, acc_P, a.tau);
+  finish_sweep<GAP>(st, a.partials, k, S, acc_gap, acc_P, a.tau);
+}
+
+// A pipelined pass of a.n iterations (tile2d_pipe.h): one block per tile of
+// kPipeOwned columns and a.th rows, a.n waves (and one for the gap).
+template <bool GAP>
+__global__ __launch_bounds__(kPipeMaxThreads) void sweep2d_pipe_kernel(
+    Sweep2DArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float pipe_lds[];
+  DevState* st = a.st;
+  const int k = st->k;
+  const int n = a.n;
+  if (st->converged || k + n > st->k_end) return;
+  const float tau_prev = st->tau_prev;
+  const int slot = st->slot;
+  // contiguous runs of tiles per XCD, as in the walk
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (b >> 3);
+  const int ty = bt / a.ntx, tx = bt - ty * a.ntx;
+  PipeCtx c;
+  const int64_t PL = a.plane;
+  c.F = a.base + plain_f(slot) * PL;
+  c.FN = a.base + plain_f(slot ^ 1) * PL;
+  c.PX = a.base + plain_p(slot) * PL;
+  c.PY = c.PX + PL;
+  c.QX = a.base + plain_p(slot ^ 1) * PL;
+  c.QY = c.QX + PL;
+  c.G = a.base + kPlainG * PL;
+  c.ny = a.ny;
+  c.nx = a.nx;
+  c.pitch = a.pitch;
+  c.x0 = tx * kPipeOwned;
+  c.y0 = ty * a.th;
+  c.y1 = min(c.y0 + a.th, a.ny);
+  c.n = n;
+  c.lam = a.lam;
+  c.tau = a.tau;
+  c.sig = a.sigma;
+  c.th = a.theta;
+  c.tau_prev = tau_prev;
+  double acc_gap = 0.0, acc_P = 0.0;
+  sweep_tile_pipe<GAP>(c, pipe_lds, acc_gap, acc_P);
+  finish_sweep<GAP>(st, a.partials, k, n, acc_gap, acc_P, a.tau);
 }
 
 __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
@@ -205,9 +249,67 @@ hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
   return hipGetLastError();
 }
 
+// LDS beyond the default dynamic limit is requested once per kernel.
+static hipError_t pipe_lds_attr(const void* fn, int bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+static hipError_t launch_sweep2d_pipe(const Layout& L, const Tile2D& t,
+                                      const tvpd_coeffs& c, bool with_gap, int n,
+                                      void* ws, hipStream_t s) {
+  if (n < 1 || n > kPipeMaxPass || t.th < 1) return hipErrorInvalidValue;
+  if (n == 1) {
+    // a one-iteration pass has nothing to pipeline: the walk computes the
+    // same iterate
+    Tile2D wt;
+    wt.th = 16;
+    wt.wpb = 4;
+    wt.order = 0;
+    return launch_sweep2d(L, wt, c, with_gap, 1, ws, s);
+  }
+  static const hipError_t attr =
+      (pipe_lds_attr(reinterpret_cast<const void*>(sweep2d_pipe_kernel<true>),
+                     pipe_lds_floats(kPipeMaxPass) * (int)sizeof(float)) ==
+               hipSuccess &&
+       pipe_lds_attr(reinterpret_cast<const void*>(sweep2d_pipe_kernel<false>),
+                     pipe_lds_floats(kPipeMaxPass) * (int)sizeof(float)) ==
+               hipSuccess)
+          ? hipSuccess
+          : hipErrorInvalidValue;
+  if (attr != hipSuccess) return attr;
+  Sweep2DArgs a;
+  a.base = planes_of(L, ws);
+  a.plane = L.plane;
+  a.ny = L.ny;
+  a.nx = L.nx;
+  a.pitch = L.pitch;
+  a.th = t.th;
+  a.wpb = 0;
+  a.order = kOrderPipe;
+  a.ntx = (L.nx + kPipeOwned - 1) / kPipeOwned;
+  a.nty = (L.ny + t.th - 1) / t.th;
+  a.ntiles = a.ntx * a.nty;
+  a.n = n;
+  a.lam = c.lam;
+  a.tau = c.tau;
+  a.sigma = c.sigma;
+  a.theta = c.theta;
+  a.st = state_of(ws);
+  a.partials = partials_of(L, ws);
+  if (a.ntiles > L.max_partials) return hipErrorInvalidValue;
+  const dim3 grid(a.ntiles), block((n + (with_gap ? 1 : 0)) * kWave);
+  const size_t lds = (size_t)pipe_lds_floats(n) * sizeof(float);
+  if (with_gap)
+    hipLaunchKernelGGL((sweep2d_pipe_kernel<true>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((sweep2d_pipe_kernel<false>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
                           const tvpd_coeffs& c, bool with_gap, int n,
                           void* ws, hipStream_t s) {
+  if (t.order == kOrderPipe) return launch_sweep2d_pipe(L, t, c, with_gap, n, ws, s);
   if (n < 1 || n > kMaxPass) return hipErrorInvalidValue;
   Sweep2DArgs a;
   a.base = planes_of(L, ws);
@@ -218,6 +320,7 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   a.th = t.th;
   a.wpb = t.wpb;
   a.order = t.order;
+  a.n = n;
   // every pass runs on overlapping strips of xs_owned(n) owned columns
   const int strip = xs_owned(n);
   a.ntx = (L.nx + strip - 1) / strip;
@@ -255,6 +358,8 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
 }
 
 int sweep2d_blocks(const Layout& L, const Tile2D& t, int n) {
+  if (t.order == kOrderPipe)
+    return ((L.nx + kPipeOwned - 1) / kPipeOwned) * ((L.ny + t.th - 1) / t.th);
   const int strip = xs_owned(n);
   const int ntx = (L.nx + strip - 1) / strip;
   const int nty = (L.ny + t.th - 1) / t.th;

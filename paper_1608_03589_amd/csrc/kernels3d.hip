@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kMaxBlock) void sweep3d_kernel(Sweep3DArgs a) {
     c.th = a.theta;
     sweep_tile3d<TH, GAP>(c, acc_gap, acc_P);
   }
-  finish_sweep<GAP, 1>(st, a.partials, k, acc_gap, acc_P, a.tau);
+  finish_sweep<GAP>(st, a.partials, k, 1, acc_gap, acc_P, a.tau);
 }
 
 __global__ void init3d_kernel(float* base, int64_t plane, int nz, int ny,

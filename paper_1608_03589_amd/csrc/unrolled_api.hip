@@ -149,7 +149,7 @@ int uws_ok(const ULayout& L, void* ws, size_t bytes) {
 int run_steps(const UPlan& p, const PlaneSet& P, int j, int k_from, int k_to,
               const float* coeffs, float theta, hipStream_t s) {
   if (P.ndim == 2) {
-    const int depth = std::max(1, std::min(pass_depth(), kMaxPass - 1));
+    const int depth = std::max(1, std::min(walk_depth(), kMaxPass - 1));
     for (int k = k_from; k < k_to;) {
       const int n = std::min(depth, k_to - k);
       PassIds ids;

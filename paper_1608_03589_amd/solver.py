@@ -156,7 +156,9 @@ class PlainSolver:
 
 def set_tile(shape, th: int, wpb: int = 4, order: int = 1):
     """Force the 2D sweep tile for ``shape`` in this process: rows per wave
-    band, waves per block, tile order (0 band by band, 1 strip by strip)."""
+    band, waves per block, tile order (0 band by band, 1 strip by strip; 2
+    selects the pipelined passes, one block per band of ``th`` rows, and
+    ignores ``wpb``)."""
     call("tvpd_set_tile", C.byref(make_shape(shape)), int(th), int(wpb),
          int(order))
 
@@ -183,8 +185,10 @@ def get_tile3d(shape):
 
 
 def set_pass_depth(depth: int):
-    """Longest pass (iterations per launch) of the plain 2D solver, 1 .. 6;
-    the iterates are the same for every depth.  Process-wide."""
+    """Longest pass (iterations per launch) of the plain 2D solver: 0 for
+    each kernel's default (5 for the strip walk, 10 for the pipelined
+    passes), else 1 .. 10, capped at 6 for the strip walk; the iterates are
+    the same for every depth.  Process-wide."""
     call("tvpd_set_pass_depth", int(depth))
 
 
@@ -192,6 +196,14 @@ def get_pass_depth() -> int:
     d = C.c_int32()
     call("tvpd_get_pass_depth", C.byref(d))
     return d.value
+
+
+def pass_length(shape) -> int:
+    """Longest pass the plain solver takes for the 2D ``shape`` now (its
+    tile's kernel and the depth setting)."""
+    n = C.c_int32()
+    call("tvpd_pass_length", C.byref(make_shape(shape)), C.byref(n))
+    return n.value
 
 
 def set_blocking(on: bool):

@@ -245,3 +245,33 @@ def test_logpolar_limits(L):
     assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 8, 4096)), C.byref(n)) == -6
     assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 8, 3)), C.byref(n)) == -6
     assert L.tvpd_lp_workspace_size(C.byref(_lib.TomoGeom(16, 16, 8, 40)), C.byref(n)) == 0
+
+
+def test_tile_and_depth_settings_are_validated(L):
+    # host-side settings: no GPU needed
+    from paper_1608_03589_amd._lib import Shape
+    s = Shape(2, 1, 300, 517)
+    th, wpb, order = C.c_int32(), C.c_int32(), C.c_int32()
+    # the pipelined passes (order 2) take any wpb; the walks 1, 2 or 4
+    assert L.tvpd_set_tile(C.byref(s), 300, 0, 2) == 0
+    assert L.tvpd_get_tile(C.byref(s), C.byref(th), C.byref(wpb), C.byref(order)) == 0
+    assert (th.value, order.value) == (300, 2)
+    assert L.tvpd_set_tile(C.byref(s), 8, 3, 0) == -1
+    assert L.tvpd_set_tile(C.byref(s), 8, 4, 3) == -1
+    assert L.tvpd_set_tile(C.byref(s), 0, 1, 2) == -1
+    assert L.tvpd_set_tile(C.byref(s), 8, 4, 1) == 0
+    d = C.c_int32()
+    assert L.tvpd_get_pass_depth(C.byref(d)) == 0
+    old = d.value
+    try:
+        for ok in (0, 1, 6, 10):
+            assert L.tvpd_set_pass_depth(ok) == 0
+            assert L.tvpd_get_pass_depth(C.byref(d)) == 0 and d.value == ok
+        for bad in (-1, 11):
+            assert L.tvpd_set_pass_depth(bad) == -1
+        assert L.tvpd_set_blocking(0) == 0
+        assert L.tvpd_get_pass_depth(C.byref(d)) == 0 and d.value == 1
+        assert L.tvpd_set_blocking(1) == 0
+        assert L.tvpd_get_pass_depth(C.byref(d)) == 0 and d.value == 0
+    finally:
+        L.tvpd_set_pass_depth(old)
