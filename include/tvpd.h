@@ -150,13 +150,16 @@ int tvpd_iteration(const tvpd_shape* shape, const void* ws, size_t ws_bytes,
 
 /* Primal energy, dual energy and duality gap of the current pair
  * (f^k, p^k) for weight lam, accumulated in float64: out[0] = P,
- * out[1] = D, out[2] = gap (host out).  Synchronises the stream. */
+ * out[1] = D, out[2] = gap (host out).  Synchronises the stream.
+ * TVPD_ERR_DEVICE if a pipelined pass since the last tvpd_init recorded a
+ * timed-out wait (the state is then not a valid iterate). */
 int tvpd_energy_gap(const tvpd_shape* shape, float lam, void* ws,
                     size_t ws_bytes, double out[3], void* stream);
 
 /* Full solve: init from g (device), iterate with the stopping rule of
  * tvpd_params, write the returned iterate to f_out (device, dense).  res is
- * host memory.  Synchronises the stream. */
+ * host memory.  Synchronises the stream.  TVPD_ERR_DEVICE: a wait inside a
+ * pipelined pass (tile order 2) timed out, so f_out is not valid. */
 int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
                const tvpd_params* prm, void* ws, size_t ws_bytes,
                tvpd_result* res, void* stream);
@@ -215,6 +218,14 @@ int tvpd_get_pass_depth(int32_t* depth);
 /* The longest pass (iterations per launch) the plain solver takes for the
  * 2D `shape` under the current tile and depth settings. */
 int tvpd_pass_length(const tvpd_shape* shape, int32_t* n);
+
+/* Polls after which a wait between the waves of a pipelined pass (tile
+ * order 2) gives up, process-wide; 0 (the default) means 2^24 polls, about
+ * half a second.  A wait that gives up lets the pass finish with invalid
+ * iterates and makes tvpd_solve and tvpd_energy_gap return TVPD_ERR_DEVICE
+ * until the next tvpd_init: a small limit exercises that path.  polls >= 0,
+ * else TVPD_ERR_INVALID_ARG. */
+int tvpd_set_wait_limit(int64_t polls);
 
 /* Autotuner.  Times every candidate tile of the sweep on `ws`, an
  * initialised workspace of this shape, and keeps the fastest for `shape` in

@@ -18,7 +18,8 @@ from .unrolled import (  # noqa: F401
 from .solver import (  # noqa: F401
     PlainSolver, SolveResult, alloc_workspace, autotune, default_step,
     get_pass_depth, get_tile, pass_length, get_tile3d, make_shape, set_blocking,
-    set_pass_depth, set_tile, set_tile3d, solve, tune_load, workspace_size,
+    set_pass_depth, set_tile, set_tile3d, set_wait_limit, solve, tune_load,
+    workspace_size,
 )
 
 __all__ = [
@@ -30,6 +31,6 @@ __all__ = [
     "tune_load",
     "default_step", "get_pass_depth", "pass_length", "get_tile", "get_tile3d", "lib",
     "make_shape", "set_pass_depth",
-    "set_blocking", "set_tile", "set_tile3d", "solve",
+    "set_blocking", "set_tile", "set_tile3d", "set_wait_limit", "solve",
     "workspace_size",
 ]

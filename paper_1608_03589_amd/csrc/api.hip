@@ -191,8 +191,17 @@ hipError_t launch_read(const Layout& L, const void* ws, float* f_out,
 // the pipelined passes' kPipeMaxPass; tvpd_set_blocking(0) means 1).
 constexpr int kWalkDepth = 5;
 std::atomic<int> g_depth{0};
+// Polls after which a bounded wait inside a pipelined pass gives up
+// (tvpd_set_wait_limit; 0: the default, about half a second).
+constexpr int64_t kDefaultWaitLimit = 1LL << 24;
+std::atomic<int64_t> g_wait_limit{0};
 
 }  // namespace
+
+int64_t pipe_wait_limit() {
+  const int64_t v = g_wait_limit.load();
+  return v == 0 ? kDefaultWaitLimit : v;
+}
 
 int pass_depth() { return g_depth.load(); }
 int walk_depth() {
@@ -285,7 +294,7 @@ int solve_plain(const Layout& L, const float* g, float* f_out,
           cleanup();
           return TVPD_ERR_HIP;
         }
-        if (hst[prev].converged) stop = true;
+        if (hst[prev].converged || hst[prev].flags) stop = true;
         inflight = 1;
       }
       slot ^= 1;
@@ -305,7 +314,7 @@ int solve_plain(const Layout& L, const float* g, float* f_out,
     res->dual = hst[0].D;
     res->gap = hst[0].gap;
   }
-  return TVPD_OK;
+  return hst[0].flags ? TVPD_ERR_DEVICE : TVPD_OK;
 }
 
 }  // namespace
@@ -408,7 +417,7 @@ int tvpd_energy_gap(const tvpd_shape* shape, float lam, void* ws,
   out[0] = h.P;
   out[1] = h.D;
   out[2] = h.gap;
-  return TVPD_OK;
+  return h.flags ? TVPD_ERR_DEVICE : TVPD_OK;
 }
 
 int tvpd_solve(const tvpd_shape* shape, const float* g, float* f_out,
@@ -528,6 +537,12 @@ int tvpd_set_blocking(int32_t on) {
 int tvpd_set_pass_depth(int32_t depth) {
   if (depth < 0 || depth > kPipeMaxPass) return TVPD_ERR_INVALID_ARG;
   g_depth.store(depth);
+  return TVPD_OK;
+}
+
+int tvpd_set_wait_limit(int64_t polls) {
+  if (polls < 0) return TVPD_ERR_INVALID_ARG;
+  g_wait_limit.store(polls);
   return TVPD_OK;
 }
 

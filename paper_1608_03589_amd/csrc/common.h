@@ -36,7 +36,7 @@ struct DevState {
   uint32_t unused0;      // (arrival counters: SyncArea at kSyncOffset)
   int32_t checks;        // number of gap checks performed
   int32_t nblocks;       // block count of the last gap sweep
-  int32_t flags;         // device-side error bits
+  int32_t flags;         // device-side error bits (kStateErr*)
   double P, D, gap;      // energies of the last evaluated pair
   double tol;            // relative gap tolerance (< 0: never stop)
   float tau_prev;        // step that produced f^k (0 after initialisation)
@@ -44,6 +44,9 @@ struct DevState {
   double pad[7];
 };
 static_assert(sizeof(DevState) <= 256, "state header");
+// DevState.flags: a wait of a pipelined pass ran out (its iterates are not
+// valid; the solve reports TVPD_ERR_DEVICE).
+constexpr int32_t kStateErrPipeWait = 1;
 
 // Workspace layout of the plain solver (2D and 3D share it).
 struct Layout {
@@ -128,6 +131,7 @@ struct Sweep2DArgs {
   float lam, tau, sigma, theta;
   DevState* st;
   double* partials;   // 2 doubles per block (gap, P)
+  int64_t wait_limit; // polls before a wait of the pipelined kernel gives up
 };
 
 // Tile configuration of the 3D sweep: each wave owns a strip of 256 columns,
@@ -203,6 +207,7 @@ int tune_load(const char* path, int* count);
 int pass_depth();
 int walk_depth();         // strip walks (tile2d_xs.h): 1 .. kMaxPass
 int pipe_depth();         // pipelined passes (tile2d_pipe.h): 1 .. kPipeMaxPass
+int64_t pipe_wait_limit();  // polls per bounded wait of the pipelined passes
 
 // Host resources a driver keeps for polling device state while further work
 // is queued: pinned staging for two copies of a header, two events and a

@@ -6,6 +6,8 @@
 // writes 12 (f^{k+n}, p^{k+n} x2).  The last block to finish advances the
 // iteration counter kept in device memory, or on a gap check reduces the
 // per-block partials in a fixed order and applies the stopping rule.
+#include <atomic>
+
 #include "finish.h"
 #include "tile2d_pipe.h"
 #include "tile2d_xs.h"
@@ -107,6 +109,8 @@ __global__ __launch_bounds__(kPipeMaxThreads) void sweep2d_pipe_kernel(
   c.sig = a.sigma;
   c.th = a.theta;
   c.tau_prev = tau_prev;
+  c.err = &st->flags;
+  c.wait_limit = a.wait_limit;
   double acc_gap = 0.0, acc_P = 0.0;
   sweep_tile_pipe<GAP>(c, pipe_lds, acc_gap, acc_P);
   finish_sweep<GAP>(st, a.partials, k, n, acc_gap, acc_P, a.tau);
@@ -249,9 +253,25 @@ hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
   return hipGetLastError();
 }
 
-// LDS beyond the default dynamic limit is requested once per kernel.
-static hipError_t pipe_lds_attr(const void* fn, int bytes) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+// LDS beyond the default dynamic limit, requested for both instances of the
+// pipelined kernel once per device (a function attribute is per device).
+static hipError_t pipe_lds_ready() {
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> done[kMaxDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const bool known = dev >= 0 && dev < kMaxDevices;
+  if (known && done[dev].load(std::memory_order_acquire)) return hipSuccess;
+  const int bytes = pipe_lds_floats(kPipeMaxPass) * (int)sizeof(float);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep2d_pipe_kernel<true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep2d_pipe_kernel<false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  if (known) done[dev].store(1, std::memory_order_release);
+  return hipSuccess;
 }
 
 static hipError_t launch_sweep2d_pipe(const Layout& L, const Tile2D& t,
@@ -267,15 +287,7 @@ static hipError_t launch_sweep2d_pipe(const Layout& L, const Tile2D& t,
     wt.order = 0;
     return launch_sweep2d(L, wt, c, with_gap, 1, ws, s);
   }
-  static const hipError_t attr =
-      (pipe_lds_attr(reinterpret_cast<const void*>(sweep2d_pipe_kernel<true>),
-                     pipe_lds_floats(kPipeMaxPass) * (int)sizeof(float)) ==
-               hipSuccess &&
-       pipe_lds_attr(reinterpret_cast<const void*>(sweep2d_pipe_kernel<false>),
-                     pipe_lds_floats(kPipeMaxPass) * (int)sizeof(float)) ==
-               hipSuccess)
-          ? hipSuccess
-          : hipErrorInvalidValue;
+  const hipError_t attr = pipe_lds_ready();
   if (attr != hipSuccess) return attr;
   Sweep2DArgs a;
   a.base = planes_of(L, ws);
@@ -286,6 +298,7 @@ static hipError_t launch_sweep2d_pipe(const Layout& L, const Tile2D& t,
   a.th = t.th;
   a.wpb = 0;
   a.order = kOrderPipe;
+  a.wait_limit = pipe_wait_limit();
   a.ntx = (L.nx + kPipeOwned - 1) / kPipeOwned;
   a.nty = (L.ny + t.th - 1) / t.th;
   a.ntiles = a.ntx * a.nty;
@@ -321,6 +334,7 @@ hipError_t launch_sweep2d(const Layout& L, const Tile2D& t,
   a.wpb = t.wpb;
   a.order = t.order;
   a.n = n;
+  a.wait_limit = 0;  // (the walk has no waits)
   // every pass runs on overlapping strips of xs_owned(n) owned columns
   const int strip = xs_owned(n);
   a.ntx = (L.nx + strip - 1) / strip;

@@ -50,7 +50,6 @@ constexpr int kPipeRow = kStripCols;  // floats per LDS row
 constexpr int kPipeAhead = 4;         // rows in flight ahead of the one taken in
 constexpr int kPipeBufs = kPipeAhead + 1;  // wave 0's row buffers
 constexpr int kPipeCounts = 16;       // progress counts (>= kPipeMaxPass + 1)
-constexpr long kPipeSpinLimit = 1L << 24;  // polls before a wait gives up
 static_assert(kPipeCounts >= kPipeMaxPass + 2, "progress counts and abort flag");
 
 constexpr int kPipeArrays = 5;        // rows per ring slot: f, p_x, p_y, g, fbar
@@ -76,6 +75,8 @@ struct PipeCtx {
   int n;            // iterations of the pass, 1 .. kPipeMaxPass
   float lam, tau, sig, th;
   float tau_prev;   // the step that produced f^k (any value at k = 0)
+  int* err;         // device error bits: kStateErrPipeWait if a wait ran out
+  int64_t wait_limit;  // polls before a wait gives up
 };
 
 __device__ __forceinline__ void lds_st4(float* p, const F4& a) {
@@ -150,15 +151,16 @@ __device__ __forceinline__ void sweep_tile_pipe(const PipeCtx& c, float* lds,
 
   // wait until wave v has finished `t` steps.  Bounded: a wait that runs
   // out raises the block's abort flag, after which no wait waits, so the
-  // pass ends (with wrong results) instead of hanging.
+  // pass ends instead of hanging, and the block records the error in the
+  // device state (its results are not valid).
   auto wait_for = [&](int v, int t) {
-    long spins = 0;
+    int64_t spins = 0;
     while (__hip_atomic_load(&prog[v], __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP) < t) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_WORKGROUP) != 0)
         break;
-      if (++spins > kPipeSpinLimit) {
+      if (++spins > c.wait_limit) {
         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
         break;
@@ -385,6 +387,8 @@ __device__ __forceinline__ void sweep_tile_pipe(const PipeCtx& c, float* lds,
       post(t + 1);
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && *abort_flag != 0) atomicOr(c.err, kStateErrPipeWait);
 }
 
 }  // namespace dev

@@ -206,6 +206,13 @@ def pass_length(shape) -> int:
     return n.value
 
 
+def set_wait_limit(polls: int):
+    """Polls after which a wait between the waves of a pipelined pass gives
+    up (0: the default, about half a second), process-wide.  A pass whose
+    wait gave up makes the solve raise (TVPD_ERR_DEVICE)."""
+    call("tvpd_set_wait_limit", int(polls))
+
+
 def set_blocking(on: bool):
     """Temporal blocking of the plain and batched 2D solvers on (passes of
     up to the default depth) or off (one iteration per launch), process-wide;

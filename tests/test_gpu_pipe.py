@@ -47,6 +47,7 @@ def run(g32, depth, tile, n_fixed, solves):
 def test_pipelined_passes_equal_the_walk(shape, th):
     g32 = scene32(*shape, 7000 + shape[0] + shape[1])
     solves = (10, 7, 3)
+    saved = tv.get_tile(shape)
     try:
         print(f"case: walk depth 1 shape {shape}", flush=True)
         ref = run(g32, 1, (4, 4, 0), 23, solves)
@@ -61,6 +62,7 @@ def test_pipelined_passes_equal_the_walk(shape, th):
                 assert np.array_equal(a[0], b[0]), (depth, ce)
     finally:
         tv.set_blocking(True)
+        tv.set_tile(shape, *saved)
 
 
 def test_full_size_pipelined_passes_equal_the_walk():
@@ -79,3 +81,36 @@ def test_full_size_pipelined_passes_equal_the_walk():
         tv.set_tile(shape, *default)
     assert np.array_equal(got["fixed"][0], ref["fixed"][0])
     assert np.array_equal(got["fixed"][1], ref["fixed"][1])
+
+
+def test_timed_out_wait_is_reported():
+    # with a one-poll limit the first wait that is not satisfied almost at
+    # once gives up (stage 2 waits for stage 1's first row, which needs loads
+    # from memory); every wave still ends its pass, and the solve raises
+    shape = (300, 517)
+    saved = tv.get_tile(shape)
+    g32 = scene32(*shape, 7200)
+    gt = torch.from_numpy(g32).to(DEV)
+    kw = dict(tau=S2, sigma=S2, max_iter=20, check_every=10, gap_tol=-1.0)
+    try:
+        tv.set_pass_depth(0)
+        tv.set_tile(shape, 4, 4, 0)
+        s = tv.PlainSolver(shape, DEV)
+        ref, _ = s.solve(gt, 0.1, **kw)
+        ref = ref.cpu().numpy()
+        tv.set_tile(shape, 64, 1, 2)
+        tv.set_wait_limit(1)
+        print("case: pipelined solve with a one-poll wait limit", flush=True)
+        with pytest.raises(tv.TVPDError):
+            s.solve(gt, 0.1, **kw)
+        torch.cuda.synchronize()
+        tv.set_wait_limit(0)
+        print("case: the same solve with the default limit", flush=True)
+        f, r = s.solve(gt, 0.1, **kw)
+        f = f.cpu().numpy()
+    finally:
+        tv.set_wait_limit(0)
+        tv.set_blocking(True)
+        tv.set_tile(shape, *saved)
+    assert r.iters == 20
+    assert np.array_equal(f, ref)
