@@ -37,7 +37,6 @@ VALU_PEAK_WAVE_INSTR_S = 256 * 2.4e9
 VALU_PEAK_TOPS = VALU_PEAK_WAVE_INSTR_S * 64 / 1e12      # 39.3 T lane-ops/s
 # Texture-addresser ceiling of the gathers: 4 lane addresses per clock per
 # CU, one wave64 buffer load per 16 cycles.
-TA_PEAK_WAVE_INSTR_S = 256 * 2.4e9 / 16
 
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "sweep2d_xs5_denoise4096_traffic.txt")
@@ -496,15 +495,28 @@ def bench_tomo(dev):
             rec["frac"] = max(rec["valu_frac"], rec["hbm_frac"])
         return rec
 
+    # A's units from its counters (A alone, the first instance): VALU issue
+    # against one wave64 instruction per CU and clock, the LDS and the
+    # texture path's busy fractions; the binding one is the busiest
     proj = cnt.get("tomo_project_kernel#1", {})
-    ta = None
-    if proj.get("vmem_rd_wave_instr"):
-        ach = proj["vmem_rd_wave_instr"] / (ms_radon * 1e-3)
-        ta = {"achieved_vmem_wave_instr_s": ach, "peak": TA_PEAK_WAVE_INSTR_S,
-              "frac": ach / TA_PEAK_WAVE_INSTR_S,
-              "ta_busy": proj.get("ta_busy"),
-              "basis": "buffer loads issued per second (rocprofv3 SQ_INSTS_VMEM_RD) against "
-                       "the texture addresser's 4 lane addresses per clock per CU"}
+    proj_units = None
+    if proj.get("valu_wave_instr"):
+        valu_s = proj["valu_wave_instr"] / (ms_radon * 1e-3)
+        proj_units = {
+            "valu_wave_instr_s": valu_s,
+            "valu_frac": valu_s / VALU_PEAK_WAVE_INSTR_S,
+            "lds_busy": proj.get("lds_busy"),
+            "lds_bank_conflict": proj.get("lds_bank_conflict"),
+            "ta_busy": proj.get("ta_busy"),
+            "td_busy": proj.get("td_busy"),
+            "vmem_rd_wave_instr": proj.get("vmem_rd_wave_instr"),
+            "basis": "rocprofv3 SQ_INSTS_VALU per launch over the live launch time against "
+                     "256 CUs x 2.4 GHz; SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT and "
+                     "TA/TD busy per CU-cycle of the counter run"}
+        units = {"alu": proj_units["valu_frac"],
+                 "lds": proj_units["lds_busy"] or 0.0,
+                 "ta": proj_units["ta_busy"] or 0.0}
+        proj_units["bound"] = max(units, key=units.get)
     return {
         "workload": "tomo_2048x1000",
         "image": [H, W], "n_angles": na, "n_det": nd, "reg": "tv", "lam": lam,
@@ -527,16 +539,18 @@ def bench_tomo(dev):
                                               "lp_angle_conv_kernel",
                                               "lp_rows_inverse_kernel",
                                               "lp_cartesian_kernel"]),
-        "projection_ta_bound": ta,
+        "projection_units": proj_units,
         "gpairs_per_s_radon": pairs / (ms_radon * 1e-3) / 1e9,
         "gpairs_per_s_backproject": pairs / (ms_bp * 1e-3) / 1e9,
         "roofline": {
-            "bound": "alu",
+            "bound": proj_units["bound"] if proj_units else "alu",
             "kernel": "tomo_project_kernel (A, with the padded-copy kernel in the timing)",
-            "achieved": tf_proj,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": tf_proj / FP32_VECTOR_PEAK_TFLOPS,
+            "achieved": proj_units["valu_wave_instr_s"] / 1e12 if proj_units else None,
+            "peak": VALU_PEAK_WAVE_INSTR_S / 1e12,
+            "unit": "T wave64 VALU instructions/s",
+            "frac": proj_units["valu_frac"] if proj_units else None,
+            "flops_achieved_tflops": tf_proj,
+            "flops_frac_of_fp32_peak": tf_proj / FP32_VECTOR_PEAK_TFLOPS,
             "flops_per_pixel_angle": TOMO_FLOPS_PROJ,
             "backprojection_achieved": tf_bp,
             "backprojection_frac": tf_bp / FP32_VECTOR_PEAK_TFLOPS,

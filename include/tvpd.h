@@ -420,6 +420,13 @@ int tvpd_tomo_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes);
 int tvpd_radon_forward(const tvpd_tomo_geom* geom, const float* f, float* sino,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* How A gathers the image, process-wide: with on = 1 (the default) a
+ * block of 8 angles stages each image row's window of 256 columns in LDS
+ * once for all 8 (blocks whose angles straddle a diagonal, or whose columns
+ * spread wider, gather from memory); with on = 0 every lane gathers its
+ * three columns from memory.  Both give A f bit for bit.  on in {0, 1}. */
+int tvpd_set_projection_staging(int32_t on);
+
 /* img = A^T sino.  sino: device [n_angles][n_det]; img: device [ny][nx].
  * Uses no workspace state except the angle table (rebuilt by the call). */
 int tvpd_radon_backward(const tvpd_tomo_geom* geom, const float* sino,

@@ -9,7 +9,8 @@ memory and streams through PyTorch.
 from ._lib import TVPDError, lib  # noqa: F401
 from .batch import BatchedSolver  # noqa: F401
 from .tomo import (  # noqa: F401
-    TomoSolver, default_steps, fbp_noalloc, tomo_workspace_size,
+    TomoSolver, default_steps, fbp_noalloc, set_projection_staging,
+    tomo_workspace_size,
 )
 from .unrolled import (  # noqa: F401
     UnrolledSolver, UnrolledTV, default_coeffs, set_fused_adjoint,
@@ -24,7 +25,7 @@ from .solver import (  # noqa: F401
 
 __all__ = [
     "BatchedSolver", "PlainSolver", "SolveResult", "TVPDError", "TomoSolver",
-    "default_steps", "fbp_noalloc", "tomo_workspace_size",
+    "default_steps", "fbp_noalloc", "set_projection_staging", "tomo_workspace_size",
     "UnrolledSolver", "UnrolledTV", "default_coeffs", "set_fused_adjoint",
     "unrolled_tv",
     "alloc_workspace", "autotune",

@@ -119,6 +119,7 @@ SIGNATURES = {
                                       C.POINTER(C.c_float), _P]),
     "tvpd_tomo_workspace_size": (C.c_int, [C.POINTER(TomoGeom), C.POINTER(_SZ)]),
     "tvpd_radon_forward": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
+    "tvpd_set_projection_staging": (C.c_int, [_I32]),
     "tvpd_radon_backward": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _P, _SZ, _P]),
     "tvpd_tomo_init": (C.c_int, [C.POINTER(TomoGeom), _P, _P, _SZ, _P]),
     "tvpd_tomo_step": (C.c_int, [C.POINTER(TomoGeom), _P, C.POINTER(TomoParams), _I32,

@@ -8,7 +8,8 @@
 // over the angles (the backprojection of Section 2, eq. bp_app, without the
 // factor pi / n_angles).  Both are gathers:
 //
-//  * projection (one lane per detector bin): for an angle with |cos| >=
+//  * projection (one lane per detector bin, a block of 8 angles by 64
+//    bins): for an angle with |cos| >=
 //    |sin| the lane walks the image rows; in row a the bin's hat covers the
 //    columns within 1/|cos| of j* = (t_i - y_a sin) / cos + (nx - 1) / 2, at
 //    most three of them.  For |sin| > |cos| the lane walks the columns of the
@@ -19,7 +20,13 @@
 //    padded copies (kTomoPad zero columns on each side): a wave walks only
 //    the rows its bins' hats meet, and in those rows every candidate column
 //    of its 64 bins lies inside the padded row, so hats partly outside the
-//    image read zeros instead of branching.
+//    image read zeros instead of branching.  The 8 angles of a block walk
+//    the same rows (all |cos| >= |sin| or all not) and their 64 bins' hats
+//    meet nearby columns, so the block stages a 256-column window of each
+//    row in LDS (one 16-byte load per lane and row for the block instead of
+//    a 12-byte gather per lane for each angle) and every lane reads its
+//    three columns from there; blocks whose angles straddle a diagonal, or
+//    whose columns spread wider than the window, gather from memory.
 //
 //  * backprojection (one lane per pixel, eight pixels per lane down a
 //    column): a block owns a 32 x 64 pixel tile; for each angle the tile's
@@ -37,7 +44,14 @@ namespace tvpd {
 constexpr int kTomoPad = 104;        // zero columns on each side of a padded row
 constexpr int kTomoMaxSide = 32768;  // ny, nx, n_det limit
 constexpr int kTomoMaxAngles = 65535;
-constexpr int kProjBlock = 256;      // bins per projection block (4 waves)
+constexpr int kProjAngles = 8;       // projection block: 8 angles (one wave
+constexpr int kProjThreads = kProjAngles * kWave;  // each) by 64 bins
+constexpr int kProjChunk = 16;       // rows staged per round (two per wave)
+constexpr int kProjWin = 256;        // staged columns per row (four per lane)
+// Column spread of a block's hats in one row that a staged block allows: a
+// chunk's window also covers the rows' shift over the chunk (up to one
+// column per row), rounding and alignment.
+constexpr double kProjMaxSpread = 208.0;
 constexpr int kBpRows = 32;          // backprojection tile: rows
 constexpr int kBpCols = 64;          //   columns (one wave wide)
 constexpr int kBpPerLane = kBpRows / (kMaxBlock / kWave);  // 8 pixels per lane
@@ -112,6 +126,7 @@ struct ProjArgs {
   double* part;       // kProjResid: one slot per block
   float sigma;        // kProjDual
   int ny, nx, na, nd, pitch_b, pitch_t;
+  int staged;         // 1: stage image rows in LDS where a block allows it
 };
 
 struct BpArgs {

@@ -1,5 +1,6 @@
 // HIP kernels of the tomographic data term (see tomo.h for the operators'
 // layout in memory and the iteration they serve).
+#include <climits>
 #include <cmath>
 
 #include "tile2d.h"
@@ -110,7 +111,8 @@ __global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
   }
 }
 
-// Projection: one lane per bin of one angle (see tomo.h).
+// Projection: one lane per bin of one angle, a block of kProjAngles angles
+// by 64 bins (see tomo.h).
 //
 // Weights.  With e = j* - rr = jl + phi (jl integer, 0 <= phi < 1) and
 // aa = |cos| (rows) or |sin| (columns), aa rr = 1, the hat weights
@@ -124,50 +126,105 @@ __global__ __launch_bounds__(256) void tomo_prep_kernel(PrepArgs a) {
 // every row; the wave walks only the rows in which at least one of its
 // bins' hats meets the image (plus one row on each side), and there every
 // candidate column lies inside the padded row (kTomoPad >= 94 zeros; 10
-// spare), so no per-row clamp is needed.  Each row costs one 12-byte load
-// per lane; staging the wave's row segment through LDS (two coalesced
-// dword loads, a store and the three reads) measured slower.
-template <int MODE>
-__global__ __launch_bounds__(kProjBlock) void tomo_project_kernel(ProjArgs a) {
-  __shared__ double red[2][kMaxBlock / kWave];
-  const int k = blockIdx.y;
-  const int i = blockIdx.x * kProjBlock + threadIdx.x;
+// spare), so no per-row clamp is needed.
+
+// Geometry of one angle for the 64 bins from i0w: the walk's rows, the
+// fixed-point column of each bin, and the column range of the 64 bins.
+struct ProjAngle {
+  bool xmaj;        // walks the rows of the image (else of its transpose)
+  double al;        // cos (rows) or sin (columns)
+  double m;         // column step per row, -sin/cos or -cos/sin
+  double rr;        // half-width of the hat in columns, 1/|al|
+  double cq0;       // coordinate of row 0, 1/2 - nq/2
+  int q_lo, q_hi;   // rows met (q_hi < q_lo: none)
+  double e_lo;      // min over the 64 bins of e at row coordinate 0
+  double e_hi;      // max
+};
+
+__device__ __forceinline__ double proj_A(const ProjArgs& a, double al, int nj, int bin) {
+  return ((double)bin + 0.5 - 0.5 * (double)a.nd) / al + 0.5 * (double)(nj - 1);
+}
+
+__device__ __forceinline__ ProjAngle proj_angle(const ProjArgs& a, int k, int i0w) {
+  ProjAngle g;
   const double c = a.trig[2 * k], s = a.trig[2 * k + 1];
-  const bool xmaj = fabs(c) >= fabs(s);
-  const double al = xmaj ? c : s, be = xmaj ? s : c;
-  const int nq = xmaj ? a.ny : a.nx, nj = xmaj ? a.nx : a.ny;
-  const float* src = xmaj ? a.fb : a.fbt;
-  const int64_t pitch = xmaj ? a.pitch_b : a.pitch_t;
-  const double rr = 1.0 / fabs(al);          // half-width of the hat in columns
+  g.xmaj = fabs(c) >= fabs(s);
+  g.al = g.xmaj ? c : s;
+  const double be = g.xmaj ? s : c;
+  const int nq = g.xmaj ? a.ny : a.nx, nj = g.xmaj ? a.nx : a.ny;
+  g.rr = 1.0 / fabs(g.al);
   // j*(q) = A_i + m c_q, c_q = q + 1/2 - nq/2 the row's coordinate
-  const double m = -be / al;
-  const double half = 0.5 * (double)(nj - 1);
-  auto A_of = [&](int bin) {
-    return ((double)bin + 0.5 - 0.5 * (double)a.nd) / al + half;
-  };
-  // rows met by the wave (uniform over the wave)
-  const int i0w = __builtin_amdgcn_readfirstlane(i);
-  const double Af = A_of(i0w), Al = A_of(i0w + kWave - 1);
+  g.m = -be / g.al;
+  g.cq0 = 0.5 - 0.5 * (double)nq;
+  const double Af = proj_A(a, g.al, nj, i0w), Al = proj_A(a, g.al, nj, i0w + kWave - 1);
   const double Alo = fmin(Af, Al), Ahi = fmax(Af, Al);
-  const double lo_j = -rr, hi_j = (double)(nj - 1) + rr;   // j* range that meets
-  const double cq0 = 0.5 - 0.5 * (double)nq;
-  int q_lo = 0, q_hi = nq - 1;
-  if (m == 0.0) {
-    if (!(Ahi > lo_j && Alo < hi_j)) q_hi = -1;
+  const double lo_j = -g.rr, hi_j = (double)(nj - 1) + g.rr;   // j* range that meets
+  g.q_lo = 0;
+  g.q_hi = nq - 1;
+  if (g.m == 0.0) {
+    if (!(Ahi > lo_j && Alo < hi_j)) g.q_hi = -1;
   } else {
     // Ahi + m c > lo_j  and  Alo + m c < hi_j
-    double c1 = (lo_j - Ahi) / m, c2 = (hi_j - Alo) / m;
+    double c1 = (lo_j - Ahi) / g.m, c2 = (hi_j - Alo) / g.m;
     const double cmin = fmin(c1, c2), cmax = fmax(c1, c2);
-    const double qa = floor(cmin - cq0) - 1.0, qb = ceil(cmax - cq0) + 1.0;
-    q_lo = (int)fmax(qa, 0.0);
-    q_hi = (int)fmin(qb, (double)(nq - 1));
+    const double qa = floor(cmin - g.cq0) - 1.0, qb = ceil(cmax - g.cq0) + 1.0;
+    g.q_lo = (int)fmax(qa, 0.0);
+    g.q_hi = (int)fmin(qb, (double)(nq - 1));
   }
-  // e(q) = j*(q) - rr in 32.32 fixed point, from row q_lo
+  g.e_lo = Alo - g.rr;
+  g.e_hi = Ahi - g.rr;
+  return g;
+}
+
+// min / max over the 8 lanes of a lane group (lanes l, l^1, ..., l^7).
+__device__ __forceinline__ int group_min(int v) {
+  v = min(v, __shfl_xor(v, 1));
+  v = min(v, __shfl_xor(v, 2));
+  return min(v, __shfl_xor(v, 4));
+}
+__device__ __forceinline__ int group_max(int v) {
+  v = max(v, __shfl_xor(v, 1));
+  v = max(v, __shfl_xor(v, 2));
+  return max(v, __shfl_xor(v, 4));
+}
+__device__ __forceinline__ double group_min(double v) {
+  v = fmin(v, __shfl_xor(v, 1));
+  v = fmin(v, __shfl_xor(v, 2));
+  return fmin(v, __shfl_xor(v, 4));
+}
+__device__ __forceinline__ float group_min(float v) {
+  v = fminf(v, __shfl_xor(v, 1));
+  v = fminf(v, __shfl_xor(v, 2));
+  return fminf(v, __shfl_xor(v, 4));
+}
+__device__ __forceinline__ double group_max(double v) {
+  v = fmax(v, __shfl_xor(v, 1));
+  v = fmax(v, __shfl_xor(v, 2));
+  return fmax(v, __shfl_xor(v, 4));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kProjThreads) void tomo_project_kernel(ProjArgs a) {
+  __shared__ __attribute__((aligned(16))) float win[2][kProjChunk][kProjWin];
+  __shared__ double red[2][kProjAngles];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int g0 = blockIdx.y * kProjAngles;
+  const int k = g0 + wave;
+  const bool live = k < a.na;
+  const int i0w = blockIdx.x * kWave;
+  const int i = i0w + lane;
+
+  // this wave's angle (waves past the last angle walk no rows)
+  const ProjAngle P = proj_angle(a, live ? k : a.na - 1, i0w);
+  const float* src = P.xmaj ? a.fb : a.fbt;
+  const int64_t pitch = P.xmaj ? a.pitch_b : a.pitch_t;
+  const int qlo = __builtin_amdgcn_readfirstlane(P.q_lo);
+  const int qhi = live ? __builtin_amdgcn_readfirstlane(P.q_hi) : -1;
+  // e(q) = j*(q) - rr in 32.32 fixed point, from row qlo
   constexpr double kFx = 4294967296.0;
-  const int qlo = __builtin_amdgcn_readfirstlane(q_lo);
-  const int qhi = __builtin_amdgcn_readfirstlane(q_hi);
-  const double e0 = A_of(i) + m * cq0 - rr;
-  const int64_t dE = llrint(m * kFx);
+  const double e0 = proj_A(a, P.al, P.xmaj ? a.nx : a.ny, i) + P.m * P.cq0 - P.rr;
+  const int64_t dE = llrint(P.m * kFx);
   const int64_t E0 = llrint(e0 * kFx) + (int64_t)qlo * dE;
   // the 32.32 value as an integer part and a fraction word, stepped with an
   // explicit carry (two 32-bit adds)
@@ -175,35 +232,169 @@ __global__ __launch_bounds__(kProjBlock) void tomo_project_kernel(ProjArgs a) {
   uint32_t lo = (uint32_t)E0;
   const int32_t dhi = (int32_t)(dE >> 32);
   const uint32_t dlo = (uint32_t)dE;
-  const float aa = (float)fabs(al);
+  const float aa = (float)fabs(P.al);
   const float aaf = aa * 2.3283064365386963e-10f;   // aa 2^-32 (phi carried x 2^32)
   const float c2w = 2.0f * aa - 1.0f, c3w = 2.0f - 3.0f * aa;
   float acc = 0.0f;
-  // one buffer descriptor per row (scalar work): reads past the row's end
-  // return 0 instead of touching the next row
-  const char* rowb = reinterpret_cast<const char*>(src + (int64_t)qlo * pitch);
-  const int row_bytes = (int)(pitch * sizeof(float));
-  constexpr uint32_t kOff0 = (kTomoPad + 1) * sizeof(float);
-#pragma unroll 8
-  for (int q = qlo; q <= qhi; ++q) {
+  // one row: the hat weights of the lane's three columns v0, v1, v2, then
+  // the step to the next row
+  auto accumulate = [&](float v0, float v1, float v2) {
     const float ph = (float)lo;                       // phi * 2^32
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<char*>(rowb), (short)0, row_bytes, kBufferWord3);
-    const auto v3 =
-        __builtin_amdgcn_raw_buffer_load_b96(rs, ((uint32_t)hi << 2) + kOff0, 0, 0);
     const float w1 = fmaf(-aaf, ph, aa);
     const float w2 = 1.0f - fabsf(fmaf(-aaf, ph, c2w));
     const float w3 = __builtin_amdgcn_fmed3f(fmaf(aaf, ph, c3w), 0.0f, 1.0f);
-    acc = fmaf(w1, __uint_as_float(v3[0]), acc);
-    acc = fmaf(w2, __uint_as_float(v3[1]), acc);
-    acc = fmaf(w3, __uint_as_float(v3[2]), acc);
+    acc = fmaf(w1, v0, acc);
+    acc = fmaf(w2, v1, acc);
+    acc = fmaf(w3, v2, acc);
     unsigned carry;
     lo = __builtin_addc(lo, dlo, 0u, &carry);
     hi = (int32_t)__builtin_addc((unsigned)hi, (unsigned)dhi, carry, &carry);
-    rowb += row_bytes;
+  };
+  const int row_bytes = (int)(pitch * sizeof(float));
+  constexpr uint32_t kOff0 = (kTomoPad + 1) * sizeof(float);
+
+  // The block's angles, angle g0 + (lane & 7) in every lane (the same in
+  // every wave, so every decision below is uniform over the block).
+  const int kj = min(g0 + (lane & (kProjAngles - 1)), a.na - 1);
+  const ProjAngle G = proj_angle(a, kj, i0w);
+  const bool inc = g0 + (lane & (kProjAngles - 1)) < a.na && G.q_hi >= G.q_lo;
+  const uint64_t maj = __ballot(G.xmaj);
+  const bool same = maj == 0 || maj == ~0ull;
+  const int Q0 = __builtin_amdgcn_readfirstlane(group_min(inc ? G.q_lo : INT_MAX));
+  const int Q1 = __builtin_amdgcn_readfirstlane(group_max(inc ? G.q_hi : INT_MIN));
+  // The columns the block's lanes read in row q lie in [min_j lo_j(q),
+  // max_j hi_j(q) + 3] with lo_j, hi_j = e_lo, e_hi + m c_q: the spread is
+  // convex in q, so its largest value over [Q0, Q1] is at an end.
+  auto spread_at = [&](int q) {
+    const double cq = (double)q + G.cq0;
+    const double l = group_min(inc ? G.e_lo + G.m * cq : INFINITY);
+    const double h = group_max(inc ? G.e_hi + G.m * cq : -INFINITY);
+    return h - l;
+  };
+  const bool any = Q1 >= Q0;
+  const int staged = __builtin_amdgcn_readfirstlane(
+      (a.staged != 0 && same && any &&
+       fmax(spread_at(Q0), spread_at(Q1)) < kProjMaxSpread) ? 1 : 0);
+
+  if (staged) {
+    // First padded column of the window of the chunk of rows q0 ..
+    // q0 + kProjChunk - 1: two columns below the block's leftmost in any of
+    // them (the leftmost of an angle is at the first or the last row), on a
+    // 16-byte boundary, in float32 (the window leaves room for its
+    // rounding).  Uniform, kept in a scalar register.
+    const float elo_f = inc ? (float)G.e_lo : INFINITY;
+    const float m_f = (float)G.m, cq0_f = (float)G.cq0;
+    auto base_of = [&](int q0) {
+      const float c0 = (float)q0 + cq0_f;
+      const float l = group_min(
+          inc ? fminf(fmaf(m_f, c0, elo_f), fmaf(m_f, c0 + (float)(kProjChunk - 1), elo_f))
+              : INFINITY);
+      // (the opaque step keeps the conversion ahead of the read-first-lane,
+      // so the base and the row addresses built on it are scalar values)
+      int pbv = ((int)floorf(l) + kTomoPad - 1) & ~3;
+      __asm__ volatile("" : "+v"(pbv));
+      return __builtin_amdgcn_readfirstlane(pbv);
+    };
+    typedef unsigned int Row __attribute__((ext_vector_type(4)));
+    constexpr int kRowsPerWave = kProjChunk / kProjAngles;
+    // this wave's rows q0 + wave + 8 j of the chunk from q0, with the
+    // chunk's base pb; rows past Q1 read nothing (an empty buffer range
+    // returns zeros)
+    auto load_rows = [&](int q0, int pb, Row* v) {
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; ++j) {
+        const int q = q0 + wave + j * kProjAngles;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(src + (int64_t)min(q, Q1) * pitch), (short)0,
+            q <= Q1 ? row_bytes : 0, kBufferWord3);
+        // (columns left of the row wrap to large offsets: out of range, zeros)
+        const uint32_t off = (uint32_t)(pb + 4 * lane) * (uint32_t)sizeof(float);
+        v[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+      }
+    };
+    auto store_rows = [&](int buf, const Row* v) {
+#pragma unroll
+      for (int j = 0; j < kRowsPerWave; ++j) {
+        float4 t;
+        t.x = __uint_as_float(v[j][0]);
+        t.y = __uint_as_float(v[j][1]);
+        t.z = __uint_as_float(v[j][2]);
+        t.w = __uint_as_float(v[j][3]);
+        *reinterpret_cast<float4*>(&win[buf][wave + j * kProjAngles][4 * lane]) = t;
+      }
+    };
+    // Chunk ch is read from window buffer ch & 1; its rows were loaded two
+    // chunks earlier into one of two register sets, which alternate (the
+    // loop is unrolled by two, so no loaded register is moved).
+    const int nch = (Q1 - Q0) / kProjChunk + 1;
+    int pb0 = base_of(Q0), pb1 = base_of(Q0 + kProjChunk);
+    Row ra[kRowsPerWave], rb[kRowsPerWave];
+    load_rows(Q0, pb0, ra);
+    load_rows(Q0 + kProjChunk, pb1, rb);
+    store_rows(0, ra);
+    __syncthreads();
+    // one chunk: rows qc .. qc + kProjChunk - 1 from buffer buf with base
+    // pbc; the rows of chunk ch + 1 (in nxt) go to the other buffer, and the
+    // rows of chunk ch + 2 are loaded into cur's registers, whose base
+    // replaces pbc
+    auto chunk = [&](int ch, int& pbc, Row* cur, Row* nxt) {
+      const int qc = Q0 + ch * kProjChunk;
+      const int buf = ch & 1;
+      const int pb2 = base_of(qc + 2 * kProjChunk);
+      load_rows(qc + 2 * kProjChunk, pb2, cur);
+      // the window's column of padded index 0 in buffer buf
+      const float* w0 = &win[buf][0][0] + (kTomoPad + 1) - pbc;
+      // Row r's column hi is read at w0 + r kProjWin + hi: one shift-add on
+      // a scalar base per row.  (The opaque step after each row keeps the
+      // compiler from deriving each row's address from the previous one's,
+      // which costs two more instructions per row.)
+      if (qc >= qlo && qc + kProjChunk - 1 <= qhi) {
+        // every row of the chunk (one block of code: the reads of later rows
+        // can go ahead of the sums of earlier ones)
+#pragma unroll
+        for (int r = 0; r < kProjChunk; ++r) {
+          const float* rowp = w0 + r * kProjWin + hi;
+          accumulate(rowp[0], rowp[1], rowp[2]);
+          __asm__ volatile("" : "+v"(hi));
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < kProjChunk; ++r) {
+          const int q = qc + r;
+          if (q >= qlo && q <= qhi) {
+            const float* rowp = w0 + r * kProjWin + hi;
+            accumulate(rowp[0], rowp[1], rowp[2]);
+            __asm__ volatile("" : "+v"(hi));
+          }
+        }
+      }
+      store_rows(buf ^ 1, nxt);
+      __syncthreads();
+      pbc = pb2;
+    };
+    int ch = 0;
+    for (; ch + 1 < nch; ch += 2) {
+      chunk(ch, pb0, ra, rb);
+      chunk(ch + 1, pb1, rb, ra);
+    }
+    if (ch < nch) chunk(ch, pb0, ra, rb);
+  } else {
+    // one buffer descriptor per row (scalar work): reads past the row's end
+    // return 0 instead of touching the next row
+    const char* rowb = reinterpret_cast<const char*>(src + (int64_t)qlo * pitch);
+#pragma unroll 8
+    for (int q = qlo; q <= qhi; ++q) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(rowb), (short)0, row_bytes, kBufferWord3);
+      const auto v3 =
+          __builtin_amdgcn_raw_buffer_load_b96(rs, ((uint32_t)hi << 2) + kOff0, 0, 0);
+      accumulate(__uint_as_float(v3[0]), __uint_as_float(v3[1]),
+                 __uint_as_float(v3[2]));
+      rowb += row_bytes;
+    }
   }
   double v = 0.0, unused = 0.0;
-  if (i < a.nd) {
+  if (live && i < a.nd) {
     const int64_t o = (int64_t)k * a.nd + i;
     if constexpr (MODE == kProjWrite) {
       a.out[o] = acc;
@@ -519,15 +710,15 @@ int launch_tomo_prep(const TomoLayout& L, const float* x0, const float* x1,
 }
 
 int tomo_project_blocks(int na, int nd) {
-  return ((nd + kProjBlock - 1) / kProjBlock) * na;
+  return ((nd + kWave - 1) / kWave) * ((na + kProjAngles - 1) / kProjAngles);
 }
 
 int launch_tomo_project(const ProjArgs& a, int mode, hipStream_t s) {
-  const dim3 grid((a.nd + kProjBlock - 1) / kProjBlock, a.na);
+  const dim3 grid((a.nd + kWave - 1) / kWave, (a.na + kProjAngles - 1) / kProjAngles);
   switch (mode) {
-    case kProjWrite: tomo_project_kernel<kProjWrite><<<grid, kProjBlock, 0, s>>>(a); break;
-    case kProjDual: tomo_project_kernel<kProjDual><<<grid, kProjBlock, 0, s>>>(a); break;
-    case kProjResid: tomo_project_kernel<kProjResid><<<grid, kProjBlock, 0, s>>>(a); break;
+    case kProjWrite: tomo_project_kernel<kProjWrite><<<grid, kProjThreads, 0, s>>>(a); break;
+    case kProjDual: tomo_project_kernel<kProjDual><<<grid, kProjThreads, 0, s>>>(a); break;
+    case kProjResid: tomo_project_kernel<kProjResid><<<grid, kProjThreads, 0, s>>>(a); break;
     default: return TVPD_ERR_INVALID_ARG;
   }
   return TOMO_LAUNCHED();

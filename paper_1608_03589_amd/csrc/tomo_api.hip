@@ -1,5 +1,6 @@
 // C ABI of the tomographic data term: argument checks, workspace layout and
 // the host side of the iteration (see include/tvpd.h for the semantics).
+#include <atomic>
 #include <cmath>
 #include <mutex>
 
@@ -82,8 +83,12 @@ int params_ok(const tvpd_tomo_params* p) {
   return TVPD_OK;
 }
 
+// Staging of image rows in LDS by the projection (tvpd_set_projection_staging).
+std::atomic<int> g_proj_staged{1};
+
 ProjArgs proj_args(const TomoLayout& L, const TomoPtrs& P) {
   ProjArgs a{};
+  a.staged = g_proj_staged.load();
   a.fb = P.fb;
   a.fbt = P.fbt;
   a.trig = P.trig;
@@ -194,6 +199,12 @@ int scratch_address(void** out) {
 using namespace tvpd;
 
 extern "C" {
+
+int tvpd_set_projection_staging(int32_t on) {
+  if (on != 0 && on != 1) return TVPD_ERR_INVALID_ARG;
+  g_proj_staged.store(on);
+  return TVPD_OK;
+}
 
 int tvpd_tomo_workspace_size(const tvpd_tomo_geom* geom, size_t* bytes) {
   if (!geom_ok(geom)) return TVPD_ERR_SHAPE;

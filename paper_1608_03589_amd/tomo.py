@@ -30,6 +30,13 @@ def tomo_workspace_size(ny: int, nx: int, n_angles: int, n_det: int) -> int:
     return n.value
 
 
+def set_projection_staging(on: bool):
+    """A stages image rows in LDS for blocks of 8 angles (True, the default)
+    or gathers every lane's columns from memory (False); the results are the
+    same bit for bit.  Process-wide."""
+    call("tvpd_set_projection_staging", 1 if on else 0)
+
+
 def default_steps(opnorm_sq: float, reg: str = "tv"):
     """(tau, sigma_r, sigma_p) meeting the convergence condition with
     equality: TV tau = 1/L, sigma_r = 1/(2L), sigma_p = L/16 (so that
