@@ -59,10 +59,15 @@ std::string device_arch() {
 
 // Default: blocks of 4 side-by-side waves.  One-iteration and two-iteration
 // passes: bands tall enough for about one block per compute unit (few
-// concurrent row streams keep HBM pages open).  Deeper passes are bound by
-// latency and issue rather than by HBM: the shortest bands whose blocks all
-// fit on the GPU at once (two per CU at two waves per SIMD, one for passes of
-// 6), so that every CU holds as many waves as it can.  The search starts at
+// concurrent row streams keep HBM pages open).  Deeper passes: the shortest
+// bands whose blocks all fit on the GPU at once, one block per CU from
+// passes of 5 on (two per CU for passes of 3 and 4).  At depth 5 one block
+// per CU (one wave per SIMD) beat two: its bands are twice as tall, so the
+// 2 depth + 1 halo rows each band recomputes cost half as much -- 4096^2:
+// 74-row bands 642 000 Mpixel-iterations/s against 617 000 with 37 rows;
+// 2048^2: 19 rows 495 000 against 420 000 with 10; 1024^2: 6 rows 209 000
+// against 186 000 with 3.  (One block more than the CUs is a second round
+// for some CUs: 70-row bands at 4096^2 gave 488 000.)  The search starts at
 // bands of 2 rows: on images too small to fill the GPU a pass costs one band
 // walk of th + 2 depth - 1 steps, and at 256^2 (1000 iterations, depth 5)
 // bands of 2 rows took 3.7 ms against 4.3 and 5.3 ms with 4 and 8.
@@ -78,7 +83,7 @@ Tile2D default_tile2d(const Layout& L) {
   int64_t th;
   if (depth >= 3) {
     const int64_t ntx = (L.nx + xs_owned(depth) - 1) / xs_owned(depth);
-    const int64_t max_blocks = (depth >= 6 ? 1LL : 2LL) * cus;
+    const int64_t max_blocks = (depth >= 5 ? 1LL : 2LL) * cus;
     th = 2;
     while (th < 256 &&
            (ntx * ((L.ny + th - 1) / th) + t.wpb - 1) / t.wpb > max_blocks)
