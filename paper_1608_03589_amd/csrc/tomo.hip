@@ -209,10 +209,18 @@ __global__ __launch_bounds__(kProjThreads) void tomo_project_kernel(ProjArgs a) 
   __shared__ double red[2][kProjAngles];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int g0 = blockIdx.y * kProjAngles;
+  // Blocks are dealt to the 8 XCDs in turn; each XCD takes a contiguous run
+  // of (bin chunk, angle group) tiles instead, so that blocks sharing its L2
+  // stage overlapping windows of the same rows.
+  const int nbx = gridDim.x, nbt = gridDim.x * gridDim.y;
+  const int bl = blockIdx.y * nbx + blockIdx.x;
+  const int q8 = nbt >> 3, r8 = nbt & 7, xcd = bl & 7;
+  const int bt = xcd * q8 + min(xcd, r8) + (bl >> 3);
+  const int bx = bt % nbx, by = bt / nbx;
+  const int g0 = by * kProjAngles;
   const int k = g0 + wave;
   const bool live = k < a.na;
-  const int i0w = blockIdx.x * kWave;
+  const int i0w = bx * kWave;
   const int i = i0w + lane;
 
   // this wave's angle (waves past the last angle walk no rows)
@@ -408,7 +416,7 @@ __global__ __launch_bounds__(kProjThreads) void tomo_project_kernel(ProjArgs a) 
   if constexpr (MODE == kProjResid) {
     block_sum2(v, unused, red);
     if (threadIdx.x == 0) {
-      const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+      const int64_t slot = bt;
       a.part[2 * slot] = v;
       a.part[2 * slot + 1] = 0.0;
     }
