@@ -88,7 +88,9 @@ typedef struct tvpd_coeffs {
  * whenever check_every > 0 and k % check_every == 0; the solve stops at the
  * first such k with gap <= gap_tol * P(f^k) and returns f^k.  gap_tol < 0
  * never stops (fixed max_iter iterations).  use_graph: 1 replays the
- * iterations as HIP graphs, 0 launches them one by one, -1 decides. */
+ * iterations as HIP graphs, 0 launches them one by one, -1 decides (graphs
+ * for images of up to 2^20 pixels run one iteration per launch, else
+ * direct launches). */
 typedef struct tvpd_params {
   tvpd_coeffs c;
   int32_t max_iter;

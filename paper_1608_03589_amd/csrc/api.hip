@@ -232,8 +232,11 @@ int solve_plain(const Layout& L, const float* g, float* f_out,
   if (ce > 0) chunk = ce * ((64 + ce - 1) / ce);
   bool use_graph = prm.use_graph == 1;
   if (prm.use_graph < 0) {
-    // graphs pay off when launches are short, i.e. on small images
-    use_graph = (int64_t)L.nz * L.ny * L.nx <= (1 << 20) &&
+    // graphs pay off when launches are short and many: small images with one
+    // iteration per launch.  With passes of several iterations the launches
+    // are few and a replay measured slower than launching them directly
+    // (1000 iterations: 256^2 3.34 against 3.25 ms, 512^2 3.77 against 3.69)
+    use_graph = !blocked && (int64_t)L.nz * L.ny * L.nx <= (1 << 20) &&
                 prm.max_iter >= 2 * chunk;
   }
   hipGraphExec_t exec = nullptr;
