@@ -275,6 +275,10 @@ def test_tile_and_depth_settings_are_validated(L):
         assert L.tvpd_get_pass_depth(C.byref(d)) == 0 and d.value == 0
         assert L.tvpd_set_wait_limit(-1) == -1
         assert L.tvpd_set_wait_limit(5) == 0
+        assert L.tvpd_set_projection_staging(2) == -1
+        assert L.tvpd_set_projection_staging(-1) == -1
+        assert L.tvpd_set_projection_staging(0) == 0
     finally:
         L.tvpd_set_pass_depth(old)
         L.tvpd_set_wait_limit(0)
+        L.tvpd_set_projection_staging(1)
