@@ -206,6 +206,7 @@ __device__ __forceinline__ double group_max(double v) {
 template <int MODE>
 __global__ __launch_bounds__(kProjThreads) void tomo_project_kernel(ProjArgs a) {
   __shared__ __attribute__((aligned(16))) float win[2][kProjChunk][kProjWin];
+  const float* const wflat = &win[0][0][0];
   __shared__ double red[2][kProjAngles];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -350,18 +351,22 @@ __global__ __launch_bounds__(kProjThreads) void tomo_project_kernel(ProjArgs a) 
       const int buf = ch & 1;
       const int pb2 = base_of(qc + 2 * kProjChunk);
       load_rows(qc + 2 * kProjChunk, pb2, cur);
-      // the window's column of padded index 0 in buffer buf
-      const float* w0 = &win[buf][0][0] + (kTomoPad + 1) - pbc;
+      // the element of the window storage holding padded column 0 of the
+      // chunk's row 0, in buffer buf
+      const int w0 = buf * kProjChunk * kProjWin + (kTomoPad + 1) - pbc;
       // Row r's column hi is read at w0 + r kProjWin + hi: one shift-add on
-      // a scalar base per row.  (The opaque step after each row keeps the
-      // compiler from deriving each row's address from the previous one's,
-      // which costs two more instructions per row.)
+      // the row's scalar base.  (The opaque steps keep the row base scalar
+      // and stop the compiler from deriving each row's address from the
+      // previous one's, which costs two more instructions per row.)
       if (qc >= qlo && qc + kProjChunk - 1 <= qhi) {
         // every row of the chunk (one block of code: the reads of later rows
         // can go ahead of the sums of earlier ones)
 #pragma unroll
         for (int r = 0; r < kProjChunk; ++r) {
-          const float* rowp = w0 + r * kProjWin + hi;
+          int rb = (w0 + r * kProjWin) * (int)sizeof(float);   // bytes
+          __asm__ volatile("" : "+s"(rb));
+          const float* rowp =
+              reinterpret_cast<const float*>(reinterpret_cast<const char*>(wflat) + rb) + hi;
           accumulate(rowp[0], rowp[1], rowp[2]);
           __asm__ volatile("" : "+v"(hi));
         }
@@ -370,7 +375,10 @@ __global__ __launch_bounds__(kProjThreads) void tomo_project_kernel(ProjArgs a) 
         for (int r = 0; r < kProjChunk; ++r) {
           const int q = qc + r;
           if (q >= qlo && q <= qhi) {
-            const float* rowp = w0 + r * kProjWin + hi;
+            int rb = (w0 + r * kProjWin) * (int)sizeof(float);   // bytes
+            __asm__ volatile("" : "+s"(rb));
+            const float* rowp =
+                reinterpret_cast<const float*>(reinterpret_cast<const char*>(wflat) + rb) + hi;
             accumulate(rowp[0], rowp[1], rowp[2]);
             __asm__ volatile("" : "+v"(hi));
           }
