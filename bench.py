@@ -561,16 +561,24 @@ def bench_tomo(dev):
 
 
 def copy_calibration(dev):
-    """Five device copies of 256 MiB: a transfer of known size against which
-    the HBM byte counters are scaled."""
+    """Five copies of 256 MiB by the library's plain copy kernel
+    (tvpd_copy_kernel: reads 256 MiB, writes 256 MiB): a transfer of known
+    size against which the HBM byte counters are scaled.  (The runtime's own
+    device copy is no reference: its counters read between 0.28 and 0.5 of
+    the bytes on different boxes, part of it apparently moved outside the
+    shader caches.)"""
+    import ctypes
     import torch
+    from paper_1608_03589_amd import _lib
     n = 64 * 1024 * 1024  # 256 MiB of float32
     a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
     b = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev).cuda_stream
     for _ in range(5):
-        b.copy_(a)
+        _lib.call("tvpd_stream_copy", ctypes.c_void_p(a.data_ptr()),
+                  ctypes.c_void_p(b.data_ptr()), ctypes.c_int64(n), ctypes.c_void_p(stream))
     torch.cuda.synchronize()
-    log("copy calibration: 5 copies of 256 MiB done")
+    log("copy calibration: 5 plain copies of 256 MiB done")
 
 
 EXTRA_WORKLOADS = {

@@ -125,6 +125,13 @@ int tvpd_version(void);
  * returns TVPD_OK. */
 int tvpd_release_thread_resources(void);
 
+/* A plain device copy dst[i] = src[i], i < n (16-byte loads and stores;
+ * src, dst device, 16-byte aligned, not overlapping; n a multiple of 4):
+ * a kernel (tvpd_copy_kernel) that moves a known number of bytes, against
+ * which profilers' HBM byte counters are scaled.  TVPD_ERR_INVALID_ARG for
+ * null or misaligned pointers or n not a positive multiple of 4. */
+int tvpd_stream_copy(const float* src, float* dst, int64_t n, void* stream);
+
 /* ---------------------------------------------------------------------
  * Plain solver (one image or volume).
  * ------------------------------------------------------------------- */

@@ -95,6 +95,7 @@ SIGNATURES = {
     "tvpd_get_pass_depth": (C.c_int, [C.POINTER(_I32)]),
     "tvpd_pass_length": (C.c_int, [C.POINTER(Shape), C.POINTER(_I32)]),
     "tvpd_set_wait_limit": (C.c_int, [C.c_int64]),
+    "tvpd_stream_copy": (C.c_int, [_P, _P, C.c_int64, _P]),
     "tvpd_set_tile3d": (C.c_int, [C.POINTER(Shape), _I32, _I32, _I32]),
     "tvpd_get_tile3d": (C.c_int, [C.POINTER(Shape), C.POINTER(_I32),
                                   C.POINTER(_I32), C.POINTER(_I32)]),

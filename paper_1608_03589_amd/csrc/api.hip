@@ -351,6 +351,14 @@ int tvpd_release_thread_resources(void) {
   return TVPD_OK;
 }
 
+int tvpd_stream_copy(const float* src, float* dst, int64_t n, void* stream) {
+  if (!src || !dst || n <= 0 || n % 4 != 0) return TVPD_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return TVPD_ERR_INVALID_ARG;
+  TVPD_HIP(launch_stream_copy(src, dst, n, static_cast<hipStream_t>(stream)));
+  return TVPD_OK;
+}
+
 int tvpd_workspace_size(const tvpd_shape* shape, size_t* bytes) {
   if (!bytes) return TVPD_ERR_INVALID_ARG;
   if (!shape_ok(shape)) return TVPD_ERR_SHAPE;

@@ -168,6 +168,7 @@ hipError_t launch_read2d(const Layout& L, const void* ws, float* f_out,
                          float* p_out, hipStream_t s);
 hipError_t launch_energy2d(const Layout& L, float lam, void* ws,
                            bool skip_if_converged, hipStream_t s);
+hipError_t launch_stream_copy(const float* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_set_params(void* ws, int32_t k_end, double tol,
                              hipStream_t s);
 int sweep2d_blocks(const Layout& L, const Tile2D& t, int n);

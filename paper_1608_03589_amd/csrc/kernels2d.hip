@@ -116,6 +116,16 @@ __global__ __launch_bounds__(kPipeMaxThreads) void sweep2d_pipe_kernel(
   finish_sweep<GAP>(st, a.partials, k, n, acc_gap, acc_P, a.tau);
 }
 
+// A plain copy of n floats (n a multiple of 4) with 16-byte accesses, the
+// reference transfer for byte counters.
+__global__ __launch_bounds__(256) void tvpd_copy_kernel(const float4* __restrict__ src,
+                                                        float4* __restrict__ dst,
+                                                        int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void init2d_kernel(float* base, int64_t plane, int ny, int nx,
                               int pitch, const float* __restrict__ g,
                               DevState* st) {
@@ -243,6 +253,15 @@ hipError_t launch_init2d(const Layout& L, const float* g, void* ws,
   hipLaunchKernelGGL(init2d_kernel, dim3(grid_for((int64_t)L.ny * L.pitch, 256)),
                      dim3(256), 0, s, planes_of(L, ws), L.plane, L.ny, L.nx,
                      L.pitch, g, state_of(ws));
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const float* src, float* dst, int64_t n,
+                              hipStream_t s) {
+  const int64_t n4 = n / 4;
+  const int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(tvpd_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n4);
   return hipGetLastError();
 }
 

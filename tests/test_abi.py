@@ -282,3 +282,13 @@ def test_tile_and_depth_settings_are_validated(L):
         L.tvpd_set_pass_depth(old)
         L.tvpd_set_wait_limit(0)
         L.tvpd_set_projection_staging(1)
+
+
+def test_stream_copy_validates(L):
+    # host-side checks only: no device memory is touched
+    P = C.c_void_p
+    assert L.tvpd_stream_copy(None, P(256), 4, None) == -1
+    assert L.tvpd_stream_copy(P(256), None, 4, None) == -1
+    assert L.tvpd_stream_copy(P(256), P(512), 6, None) == -1      # not a multiple of 4
+    assert L.tvpd_stream_copy(P(256), P(512), 0, None) == -1
+    assert L.tvpd_stream_copy(P(260), P(512), 4, None) == -1      # misaligned

@@ -366,3 +366,17 @@ def test_solution_level_against_the_minimiser(seed, lam):
     assert res.gap >= -1e-9 * res.primal
     assert d <= bound
     assert d <= 1e-4 * np.linalg.norm(f_bf)   # the bound is not vacuous here
+
+
+def test_stream_copy_copies():
+    # the plain copy kernel that calibrates byte counters copies exactly
+    import ctypes
+    from paper_1608_03589_amd import _lib
+    n = 1 << 20
+    a = torch.rand(n, device=DEV)
+    b = torch.zeros_like(a)
+    print("case: plain copy of 2^20 floats", flush=True)
+    _lib.call("tvpd_stream_copy", ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+              ctypes.c_int64(n), ctypes.c_void_p(torch.cuda.current_stream(DEV).cuda_stream))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
