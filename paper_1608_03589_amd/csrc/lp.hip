@@ -487,18 +487,21 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
   }
 }
 
-// Step 3 along the angle for one tile of C bins.
+// Step 3 along the angle for one tile of C bins.  The angle twiddles sit in
+// LDS beside the tile (every stage reads R - 1 of them per butterfly).
 __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
   __shared__ float2 x[kLpElems];
+  __shared__ float2 tw[kLpMaxPhi];
   const int n = a.n_phi, C = a.C;
   float2* t = a.s + (int64_t)blockIdx.x * n * C;
   const float2* kk = a.k2 + (int64_t)blockIdx.x * n * C;
+  for (int e = threadIdx.x; e < n; e += kLpThreads) tw[e] = a.twa[e];
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) x[e] = t[e];
   __syncthreads();
-  fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, a.twa);
+  fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, tw);
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) x[e] = cmul(x[e], kk[e]);
   __syncthreads();
-  fft<+1, false, kLpThreads>(x, n, C, a.radix, a.nstages, a.twa);
+  fft<+1, false, kLpThreads>(x, n, C, a.radix, a.nstages, tw);
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) t[e] = x[e];
 }
 
