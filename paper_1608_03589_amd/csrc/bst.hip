@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, 
     int64_t ph = ((int64_t)ms * (nd - 1)) % (2 * (int64_t)M);
     if (ph < 0) ph += 2 * (int64_t)M;
     float sn, cs;
-    sincospif((float)ph / (float)M, &sn, &cs);
+    sincospif((float)ph * (1.0f / (float)M), &sn, &cs);   // (exact: M a power of two)
     const int am = ms < 0 ? -ms : ms;
     const float kk = lam < 0.0f ? (am == 0 ? (float)M : (float)M / (float)am)
                                 : 1.0f / fmaf(lam, (float)am / (float)M, 1.0f);
@@ -278,8 +278,11 @@ __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, 
 
 // Step 3 at the grid frequency (ps, qs)/Q (signed indices) with polar
 // angle phi = atan2(qs, ps) in (-pi, pi] and radius rho: phase * bilinear(spec).
+// per_dphi = na / pi (angle steps per radian), inv_q = 1 / Q (exact: Q is a
+// power of two).
 __device__ float2 cartesian_value(const float2* spec, int na, int M, int Q, int nx, int ny,
-                                  int ps, int qs, double phi, double rho) {
+                                  int ps, int qs, double phi, double rho, double per_dphi,
+                                  float inv_q) {
   if (rho > 0.5) return make_float2(0.0f, 0.0f);
   double nu = rho;
   if (phi < 0.0) {
@@ -290,7 +293,7 @@ __device__ float2 cartesian_value(const float2* spec, int na, int M, int Q, int 
     phi -= M_PI;
     nu = -nu;
   }
-  const double aidx = phi / (M_PI / na);
+  const double aidx = phi * per_dphi;
   int k0 = (int)floor(aidx);
   if (k0 > na - 1) k0 = na - 1;                   // rounding at phi -> pi
   if (k0 < 0) k0 = 0;
@@ -316,7 +319,7 @@ __device__ float2 cartesian_value(const float2* spec, int na, int M, int Q, int 
   int64_t ph = ((int64_t)ps * (1 - nx) + (int64_t)qs * (1 - ny)) % (2 * (int64_t)Q);
   if (ph < 0) ph += 2 * (int64_t)Q;
   float sn, cs;
-  sincospif((float)ph / (float)Q, &sn, &cs);
+  sincospif((float)ph * inv_q, &sn, &cs);
   return cmul(val, make_float2(cs, sn));
 }
 
@@ -330,15 +333,20 @@ __global__ __launch_bounds__(kMaxBlock) void bst_cartesian_rows_kernel(
   __shared__ float2 x[kBstLds];
   const int q = blockIdx.x;
   const int qs = q < Q / 2 ? q : q - Q;
-  const double v = (double)qs / Q;
+  const double inv_q = 1.0 / Q;                  // exact: Q is a power of two
+  const double per_dphi = na / M_PI;
+  const double v = (double)qs * inv_q;
   for (int a = threadIdx.x; a <= Q / 2; a += blockDim.x) {
-    const double u = (double)a / Q;
+    const double u = (double)a * inv_q;
     const double rho = sqrt(u * u + v * v);
     const double phi = atan2(v, u);                        // point (a, qs)
-    if (a < Q / 2) x[lds_at(a)] = cartesian_value(spec, na, M, Q, nx, ny, a, qs, phi, rho);
+    if (a < Q / 2)
+      x[lds_at(a)] = cartesian_value(spec, na, M, Q, nx, ny, a, qs, phi, rho, per_dphi,
+                                     (float)inv_q);
     if (a > 0) {                                           // point (-a, qs)
       const double phm = (qs >= 0 ? M_PI : -M_PI) - phi;
-      x[lds_at(Q - a)] = cartesian_value(spec, na, M, Q, nx, ny, -a, qs, phm, rho);
+      x[lds_at(Q - a)] = cartesian_value(spec, na, M, Q, nx, ny, -a, qs, phm, rho, per_dphi,
+                                         (float)inv_q);
     }
   }
   __syncthreads();
