@@ -26,11 +26,13 @@
 //         row) into the real and imaginary parts of one complex sequence,
 //         zero-padded to L (a power of two >= 2 N_rho - 1: the convolution in
 //         rho is linear), one LDS transform of length L, then the two real
-//         spectra separated by their Hermitian symmetry; bins 0 .. L/2 stored
-//         in tiles of C consecutive bins, all rays of a tile contiguous;
+//         spectra separated by their Hermitian symmetry; bins 0 .. L/2 - 1
+//         stored in tiles of C consecutive bins, all rays of a tile
+//         contiguous, the real bin L/2 in the imaginary part of the real bin 0;
 //   conv  per tile: C columns of n_phi rays transformed along the angle
 //         (mixed-radix Stockham, n_phi = 2^a 3^b 5^c), times the kernel's
-//         spectrum, transformed back (Step 3, periodic in the angle);
+//         spectrum, transformed back (Step 3, periodic in the angle); the
+//         packed column of bins 0 and L/2 is split, filtered and recombined;
 //   back  per pair of rays: the full spectrum rebuilt from the two half
 //         spectra, one inverse transform of length L, the first N_rho values
 //         of each ray written out ([B g]_L);
@@ -474,12 +476,20 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
   __syncthreads();
   fft<-1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, a.twr);
   const int C = a.C;
-  for (int k = threadIdx.x; k <= L / 2; k += kLpThreads) {
+  for (int k = threadIdx.x; k < L / 2; k += kLpThreads) {
     const float2 z1 = x[lds_at(k)];
     const float2 z2 = x[lds_at((L - k) & (L - 1))];
     // A = (z1 + conj z2) / 2, B = (z1 - conj z2) / (2 i)
-    const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
-    const float2 B = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
+    float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+    float2 B = make_float2(0.5f * (z1.y + z2.y), 0.5f * (z2.x - z1.x));
+    if (k == 0) {
+      // bins 0 and L/2 of both rays are real: bin L/2 rides in the
+      // imaginary part of bin 0 (their angle convolutions are separated
+      // again in lp_angle_conv_kernel)
+      const float2 zn = x[lds_at(L / 2)];
+      A = make_float2(z1.x, zn.x);
+      B = make_float2(z1.y, zn.y);
+    }
     const int kt = k / C, c = k - kt * C;
     float2* t = a.s + ((int64_t)kt * a.n_phi + j0) * C + c;
     t[0] = A;
@@ -499,7 +509,32 @@ __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) x[e] = t[e];
   __syncthreads();
   fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, tw);
-  for (int e = threadIdx.x; e < n * C; e += kLpThreads) x[e] = cmul(x[e], kk[e]);
+  const bool packed = blockIdx.x == 0;
+  for (int e = threadIdx.x; e < n * C; e += kLpThreads)
+    if (!packed || e % C != 0) x[e] = cmul(x[e], kk[e]);
+  if (packed) {
+    // Column 0 holds z = x0 + i xN, the real sequences of bins 0 and L/2
+    // over the angle.  With Z its transform, X0[m] = (Z[m] + conj Z[-m]) / 2
+    // and XN[m] = (Z[m] - conj Z[-m]) / (2 i); each is multiplied by its own
+    // kernel spectrum (bin L/2's sits in column 0 of the last tile) and the
+    // two are recombined as X0 K0 + i XN KN, whose inverse transform is
+    // (x0 * k0) + i (xN * kN).  Pairs (m, n - m) go to one thread.
+    const float2* kn = a.k2 + (int64_t)(a.ntiles - 1) * n * C;
+    auto one = [](float2 zm, float2 zmm, float2 k0, float2 kN) {
+      const float2 x0 = make_float2(0.5f * (zm.x + zmm.x), 0.5f * (zm.y - zmm.y));
+      const float2 xn = make_float2(0.5f * (zm.y + zmm.y), 0.5f * (zmm.x - zm.x));
+      const float2 y0 = cmul(x0, k0), yn = cmul(xn, kN);
+      return make_float2(y0.x - yn.y, y0.y + yn.x);
+    };
+    for (int m = threadIdx.x; m <= n / 2; m += kLpThreads) {
+      const int mm = (n - m) % n;
+      const float2 zm = x[m * C], zmm = x[mm * C];
+      const float2 ym = one(zm, zmm, kk[m * C], kn[m * C]);
+      const float2 ymm = one(zmm, zm, kk[mm * C], kn[mm * C]);
+      x[m * C] = ym;
+      if (mm != m) x[mm * C] = ymm;
+    }
+  }
   __syncthreads();
   fft<+1, false, kLpThreads>(x, n, C, a.radix, a.nstages, tw);
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) t[e] = x[e];
@@ -512,12 +547,18 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
   __shared__ float2 x[kLpRowLds];
   const int j0 = 2 * blockIdx.x;
   const int L = a.L, C = a.C;
-  for (int k = threadIdx.x; k <= L / 2; k += kLpThreads) {
+  for (int k = threadIdx.x; k < L / 2; k += kLpThreads) {
     const int kt = k / C, c = k - kt * C;
     const float2* t = a.s + ((int64_t)kt * a.n_phi + j0) * C + c;
     const float2 A = t[0], B = t[C];
-    x[lds_at(k)] = make_float2(A.x - B.y, A.y + B.x);
-    if (k > 0 && k < L / 2) x[lds_at(L - k)] = make_float2(A.x + B.y, B.x - A.y);
+    if (k == 0) {
+      // bins 0 and L/2 come packed (real parts bin 0, imaginary bin L/2)
+      x[lds_at(0)] = make_float2(A.x, B.x);
+      x[lds_at(L / 2)] = make_float2(A.y, B.y);
+    } else {
+      x[lds_at(k)] = make_float2(A.x - B.y, A.y + B.x);
+      x[lds_at(L - k)] = make_float2(A.x + B.y, B.x - A.y);
+    }
   }
   __syncthreads();
   fft<+1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, a.twr);
@@ -684,7 +725,8 @@ int tvpd_lp_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
   const LpArgs a = lp_args(Y, ws);
   lp_rows_forward_kernel<<<Y.m.n_phi / 2, kLpThreads, 0, s>>>(a, g);
   LP_TRY(launched());
-  lp_angle_conv_kernel<<<Y.ntiles, kLpThreads, 0, s>>>(a);
+  // (the last tile holds bin L/2 alone, which rides with bin 0)
+  lp_angle_conv_kernel<<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());
   lp_rows_inverse_kernel<<<Y.m.n_phi / 2, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());
