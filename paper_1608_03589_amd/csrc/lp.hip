@@ -311,8 +311,24 @@ __device__ __forceinline__ int at(int i, int C, int c) {
   return PAD ? lds_at(i) : i * C + c;
 }
 
-template <int R, int SIGN, bool PAD, int NT>
-__device__ void stage(float2* x, int n, int C, int Ns, const float2* tw) {
+// Twiddle w^i (i < n) from a table of length n ...
+struct TwTable {
+  const float2* p;
+  __device__ __forceinline__ float2 operator()(int i) const { return p[i]; }
+};
+// ... or as the product of two short tables, w^(128 h) and w^l for
+// i = 128 h + l (both in LDS: the row transforms' full table does not fit).
+constexpr int kTwSplit = 128;
+struct TwSplit {
+  const float2* hi;
+  const float2* lo;
+  __device__ __forceinline__ float2 operator()(int i) const {
+    return cmul(hi[i / kTwSplit], lo[i % kTwSplit]);
+  }
+};
+
+template <int R, int SIGN, bool PAD, int NT, class TW>
+__device__ void stage(float2* x, int n, int C, int Ns, TW tw) {
   constexpr int U = (kLpElems / R + NT - 1) / NT;
   const int nb = (n / R) * C;                 // butterflies
   const int stride = n / (Ns * R);
@@ -335,7 +351,7 @@ __device__ void stage(float2* x, int n, int C, int Ns, const float2* tw) {
       const int k = j % Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * stride];
+        float2 w = tw(r * k * stride);
         if (SIGN > 0) w.y = -w.y;
         v[u][r] = cmul(v[u][r], w);
       }
@@ -348,9 +364,8 @@ __device__ void stage(float2* x, int n, int C, int Ns, const float2* tw) {
   __syncthreads();
 }
 
-template <int SIGN, bool PAD, int NT>
-__device__ void fft(float2* x, int n, int C, const int* radix, int nstages,
-                    const float2* tw) {
+template <int SIGN, bool PAD, int NT, class TW>
+__device__ void fft(float2* x, int n, int C, const int* radix, int nstages, TW tw) {
   int Ns = 1;
   for (int s = 0; s < nstages; ++s) {
     const int R = radix[s];
@@ -363,6 +378,15 @@ __device__ void fft(float2* x, int n, int C, const int* radix, int nstages,
     }
     Ns *= R;
   }
+}
+
+// The row transforms' split twiddle tables in LDS (w = exp(-2 pi i / L)).
+__device__ __forceinline__ void load_split_twiddles(const float2* twr, int L, float2* hi,
+                                                    float2* lo) {
+  for (int j = threadIdx.x; j < kTwSplit; j += blockDim.x)
+    lo[j] = j < L ? twr[j] : make_float2(0.0f, 0.0f);
+  const int nh = L > kTwSplit ? L / kTwSplit : 1;
+  for (int j = threadIdx.x; j < nh; j += blockDim.x) hi[j] = twr[j * kTwSplit];
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +461,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_kernel_spectrum_kernel(LpArgs a
     x[e] = make_float2((float)re, (float)im);
   }
   __syncthreads();
-  fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, a.twa);
+  fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, TwTable{a.twa});
   const float scale = (float)(a.dphi / ((double)a.L * (double)n));
   float2* out = a.k2 + (int64_t)kt * n * C;
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) out[e] = cscale(x[e], scale);
@@ -457,6 +481,7 @@ __device__ __forceinline__ float lp_interp(const float* row, int nd, int i0, flo
 // comment); bins 0 .. L/2 of both spectra into the tiles.
 __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, const float* g) {
   __shared__ float2 x[kLpRowLds];
+  __shared__ float2 twh[kLpMaxL / kTwSplit], twl[kTwSplit];
   const int j0 = 2 * blockIdx.x;
   const int L = a.L;
   const int ka = j0 < a.na ? j0 : j0 - a.na;
@@ -464,6 +489,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
   const bool pa = j0 < a.na, pb = j0 + 1 < a.na;
   const float* ga = g + (int64_t)ka * a.nd;
   const float* gb = g + (int64_t)kb * a.nd;
+  load_split_twiddles(a.twr, L, twh, twl);
   for (int i = threadIdx.x; i < L; i += kLpThreads) {
     float va = 0.0f, vb = 0.0f;
     if (i < a.n_rho) {
@@ -474,7 +500,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
     x[lds_at(i)] = make_float2(va, vb);
   }
   __syncthreads();
-  fft<-1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, a.twr);
+  fft<-1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, TwSplit{twh, twl});
   const int C = a.C;
   for (int k = threadIdx.x; k < L / 2; k += kLpThreads) {
     const float2 z1 = x[lds_at(k)];
@@ -508,7 +534,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
   for (int e = threadIdx.x; e < n; e += kLpThreads) tw[e] = a.twa[e];
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) x[e] = t[e];
   __syncthreads();
-  fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, tw);
+  fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, TwTable{tw});
   const bool packed = blockIdx.x == 0;
   for (int e = threadIdx.x; e < n * C; e += kLpThreads)
     if (!packed || e % C != 0) x[e] = cmul(x[e], kk[e]);
@@ -536,7 +562,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
     }
   }
   __syncthreads();
-  fft<+1, false, kLpThreads>(x, n, C, a.radix, a.nstages, tw);
+  fft<+1, false, kLpThreads>(x, n, C, a.radix, a.nstages, TwTable{tw});
   for (int e = threadIdx.x; e < n * C; e += kLpThreads) t[e] = x[e];
 }
 
@@ -545,8 +571,10 @@ __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
 // imaginary parts of the result are the two rays.
 __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
   __shared__ float2 x[kLpRowLds];
+  __shared__ float2 twh[kLpMaxL / kTwSplit], twl[kTwSplit];
   const int j0 = 2 * blockIdx.x;
   const int L = a.L, C = a.C;
+  load_split_twiddles(a.twr, L, twh, twl);
   for (int k = threadIdx.x; k < L / 2; k += kLpThreads) {
     const int kt = k / C, c = k - kt * C;
     const float2* t = a.s + ((int64_t)kt * a.n_phi + j0) * C + c;
@@ -561,7 +589,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
     }
   }
   __syncthreads();
-  fft<+1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, a.twr);
+  fft<+1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, TwSplit{twh, twl});
   float* ra = a.bl + (int64_t)j0 * a.n_rho;
   float* rb = ra + a.n_rho;
   for (int i = threadIdx.x; i < a.n_rho; i += kLpThreads) {
