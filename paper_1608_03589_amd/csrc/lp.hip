@@ -54,6 +54,9 @@ constexpr int kLpMaxRho = kLpMaxL / 2;
 constexpr int kLpMaxPhi = 4096;
 constexpr int kLpElems = 16384;       // LDS elements of the angle transforms (n_phi C)
 constexpr int kLpThreads = 1024;      // 16 waves: 4 per SIMD at <= 128 VGPRs
+constexpr int kLpPer = kLpElems / kLpThreads;          // tile elements per thread
+constexpr int kLpRowBatch = 8;                         // rho samples per thread and batch
+constexpr int kLpHalfPer = kLpMaxL / 2 / kLpThreads;   // half-spectrum bins per thread
 constexpr int kLpMaxStages = 16;
 constexpr uint32_t kLpMagic = 0x4c50424bu;
 
@@ -380,14 +383,23 @@ __device__ void fft(float2* x, int n, int C, const int* radix, int nstages, TW t
   }
 }
 
-// The row transforms' split twiddle tables in LDS (w = exp(-2 pi i / L)).
-__device__ __forceinline__ void load_split_twiddles(const float2* twr, int L, float2* hi,
-                                                    float2* lo) {
-  for (int j = threadIdx.x; j < kTwSplit; j += blockDim.x)
-    lo[j] = j < L ? twr[j] : make_float2(0.0f, 0.0f);
-  const int nh = L > kTwSplit ? L / kTwSplit : 1;
-  for (int j = threadIdx.x; j < nh; j += blockDim.x) hi[j] = twr[j * kTwSplit];
-}
+// The row transforms' split twiddle tables (w = exp(-2 pi i / L)): thread j
+// loads entry j of both (fetch), then writes them to LDS (put), so that the
+// loads can be in flight together with the kernel's own.
+struct SplitTwLoad {
+  float2 lo, hi;
+  __device__ __forceinline__ void fetch(const float2* twr, int L) {
+    const int j = threadIdx.x, nh = L > kTwSplit ? L / kTwSplit : 1;
+    lo = twr[min(j, L - 1)];
+    hi = twr[min(j, nh - 1) * kTwSplit];
+  }
+  __device__ __forceinline__ void put(int L, float2* th, float2* tl) const {
+    const int j = threadIdx.x, nh = L > kTwSplit ? L / kTwSplit : 1;
+    if (j < kTwSplit) tl[j] = j < L ? lo : make_float2(0.0f, 0.0f);
+    if (j < nh) th[j] = hi;
+  }
+};
+static_assert(kLpThreads >= kTwSplit && kLpThreads >= kLpMaxL / kTwSplit, "split twiddles");
 
 // ---------------------------------------------------------------------------
 // Plan.
@@ -471,9 +483,13 @@ __global__ __launch_bounds__(kLpThreads) void lp_kernel_spectrum_kernel(LpArgs a
 // The transform.
 // ---------------------------------------------------------------------------
 
+// Both samples are loaded unconditionally (clamped indices) so that the
+// loads of a batch are all in flight before the first use.
 __device__ __forceinline__ float lp_interp(const float* row, int nd, int i0, float w) {
-  const float s0 = (i0 >= 0 && i0 < nd) ? row[i0] : 0.0f;
-  const float s1 = (i0 + 1 >= 0 && i0 + 1 < nd) ? row[i0 + 1] : 0.0f;
+  const float r0 = row[min(max(i0, 0), nd - 1)];
+  const float r1 = row[min(max(i0 + 1, 0), nd - 1)];
+  const float s0 = (i0 >= 0 && i0 < nd) ? r0 : 0.0f;
+  const float s1 = (i0 + 1 >= 0 && i0 + 1 < nd) ? r1 : 0.0f;
   return fmaf(w, s1, (1.0f - w) * s0);
 }
 
@@ -489,16 +505,37 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
   const bool pa = j0 < a.na, pb = j0 + 1 < a.na;
   const float* ga = g + (int64_t)ka * a.nd;
   const float* gb = g + (int64_t)kb * a.nd;
-  load_split_twiddles(a.twr, L, twh, twl);
-  for (int i = threadIdx.x; i < L; i += kLpThreads) {
-    float va = 0.0f, vb = 0.0f;
-    if (i < a.n_rho) {
-      const LpNode q = a.nodes[i];
-      va = pa ? lp_interp(ga, a.nd, q.ip, q.wp) : lp_interp(ga, a.nd, q.im, q.wm);
-      vb = pb ? lp_interp(gb, a.nd, q.ip, q.wp) : lp_interp(gb, a.nd, q.im, q.wm);
+  SplitTwLoad stw;
+  stw.fetch(a.twr, L);
+  // Batches of kLpRowBatch samples per thread: every node of the batch, then
+  // every sinogram sample, then the LDS stores (one wait per batch).
+  const int nr = a.n_rho;
+  for (int i0 = 0; i0 < L; i0 += kLpRowBatch * kLpThreads) {
+    if (i0 >= nr) {   // the zero padding only
+#pragma unroll
+      for (int u = 0; u < kLpRowBatch; ++u) {
+        const int i = i0 + (int)threadIdx.x + u * kLpThreads;
+        if (i < L) x[lds_at(i)] = make_float2(0.0f, 0.0f);
+      }
+      continue;
     }
-    x[lds_at(i)] = make_float2(va, vb);
+    LpNode q[kLpRowBatch];
+#pragma unroll
+    for (int u = 0; u < kLpRowBatch; ++u)
+      q[u] = a.nodes[min(i0 + (int)threadIdx.x + u * kLpThreads, nr - 1)];
+    float va[kLpRowBatch], vb[kLpRowBatch];
+#pragma unroll
+    for (int u = 0; u < kLpRowBatch; ++u) {
+      va[u] = pa ? lp_interp(ga, a.nd, q[u].ip, q[u].wp) : lp_interp(ga, a.nd, q[u].im, q[u].wm);
+      vb[u] = pb ? lp_interp(gb, a.nd, q[u].ip, q[u].wp) : lp_interp(gb, a.nd, q[u].im, q[u].wm);
+    }
+#pragma unroll
+    for (int u = 0; u < kLpRowBatch; ++u) {
+      const int i = i0 + (int)threadIdx.x + u * kLpThreads;
+      if (i < L) x[lds_at(i)] = i < nr ? make_float2(va[u], vb[u]) : make_float2(0.0f, 0.0f);
+    }
   }
+  stw.put(L, twh, twl);
   __syncthreads();
   fft<-1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, TwSplit{twh, twl});
   const int C = a.C;
@@ -531,13 +568,40 @@ __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
   const int n = a.n_phi, C = a.C;
   float2* t = a.s + (int64_t)blockIdx.x * n * C;
   const float2* kk = a.k2 + (int64_t)blockIdx.x * n * C;
-  for (int e = threadIdx.x; e < n; e += kLpThreads) tw[e] = a.twa[e];
-  for (int e = threadIdx.x; e < n * C; e += kLpThreads) x[e] = t[e];
+  const int nc = n * C;
+  {
+    // every load of the tile and the twiddles in flight before the first
+    // LDS store
+    constexpr int kTw = kLpMaxPhi / kLpThreads;
+    float2 r[kLpPer], w[kTw];
+#pragma unroll
+    for (int u = 0; u < kLpPer; ++u) r[u] = t[min((int)threadIdx.x + u * kLpThreads, nc - 1)];
+#pragma unroll
+    for (int u = 0; u < kTw; ++u) w[u] = a.twa[min((int)threadIdx.x + u * kLpThreads, n - 1)];
+#pragma unroll
+    for (int u = 0; u < kTw; ++u) {
+      const int e = threadIdx.x + u * kLpThreads;
+      if (e < n) tw[e] = w[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kLpPer; ++u) {
+      const int e = threadIdx.x + u * kLpThreads;
+      if (e < nc) x[e] = r[u];
+    }
+  }
   __syncthreads();
   fft<-1, false, kLpThreads>(x, n, C, a.radix, a.nstages, TwTable{tw});
   const bool packed = blockIdx.x == 0;
-  for (int e = threadIdx.x; e < n * C; e += kLpThreads)
-    if (!packed || e % C != 0) x[e] = cmul(x[e], kk[e]);
+  {
+    float2 r[kLpPer];
+#pragma unroll
+    for (int u = 0; u < kLpPer; ++u) r[u] = kk[min((int)threadIdx.x + u * kLpThreads, nc - 1)];
+#pragma unroll
+    for (int u = 0; u < kLpPer; ++u) {
+      const int e = threadIdx.x + u * kLpThreads;
+      if (e < nc && (!packed || e % C != 0)) x[e] = cmul(x[e], r[u]);
+    }
+  }
   if (packed) {
     // Column 0 holds z = x0 + i xN, the real sequences of bins 0 and L/2
     // over the angle.  With Z its transform, X0[m] = (Z[m] + conj Z[-m]) / 2
@@ -574,11 +638,23 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
   __shared__ float2 twh[kLpMaxL / kTwSplit], twl[kTwSplit];
   const int j0 = 2 * blockIdx.x;
   const int L = a.L, C = a.C;
-  load_split_twiddles(a.twr, L, twh, twl);
-  for (int k = threadIdx.x; k < L / 2; k += kLpThreads) {
+  SplitTwLoad stw;
+  stw.fetch(a.twr, L);
+  float2 A_[kLpHalfPer], B_[kLpHalfPer];
+#pragma unroll
+  for (int u = 0; u < kLpHalfPer; ++u) {
+    // every load in flight before the first LDS store
+    const int k = min((int)threadIdx.x + u * kLpThreads, L / 2 - 1);
     const int kt = k / C, c = k - kt * C;
     const float2* t = a.s + ((int64_t)kt * a.n_phi + j0) * C + c;
-    const float2 A = t[0], B = t[C];
+    A_[u] = t[0];
+    B_[u] = t[C];
+  }
+#pragma unroll
+  for (int u = 0; u < kLpHalfPer; ++u) {
+    const int k = threadIdx.x + u * kLpThreads;
+    if (k >= L / 2) break;
+    const float2 A = A_[u], B = B_[u];
     if (k == 0) {
       // bins 0 and L/2 come packed (real parts bin 0, imaginary bin L/2)
       x[lds_at(0)] = make_float2(A.x, B.x);
@@ -588,6 +664,7 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
       x[lds_at(L - k)] = make_float2(A.x + B.y, B.x - A.y);
     }
   }
+  stw.put(L, twh, twl);
   __syncthreads();
   fft<+1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, TwSplit{twh, twl});
   float* ra = a.bl + (int64_t)j0 * a.n_rho;
