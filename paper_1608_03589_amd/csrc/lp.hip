@@ -562,10 +562,13 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
 
 // Step 3 along the angle for one tile of C bins.  The angle twiddles sit in
 // LDS beside the tile (every stage reads R - 1 of them per butterfly).
+// C (the tile's bins, a.C) is a template parameter: the butterflies' column
+// and row indices are then shifts, cheap enough to recompute in every stage.
+template <int C>
 __global__ __launch_bounds__(kLpThreads) void lp_angle_conv_kernel(LpArgs a) {
   __shared__ float2 x[kLpElems];
   __shared__ float2 tw[kLpMaxPhi];
-  const int n = a.n_phi, C = a.C;
+  const int n = a.n_phi;
   float2* t = a.s + (int64_t)blockIdx.x * n * C;
   const float2* kk = a.k2 + (int64_t)blockIdx.x * n * C;
   const int nc = n * C;
@@ -831,7 +834,10 @@ int tvpd_lp_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
   lp_rows_forward_kernel<<<Y.m.n_phi / 2, kLpThreads, 0, s>>>(a, g);
   LP_TRY(launched());
   // (the last tile holds bin L/2 alone, which rides with bin 0)
-  lp_angle_conv_kernel<<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
+  if (Y.C == 8)
+    lp_angle_conv_kernel<8><<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
+  else
+    lp_angle_conv_kernel<4><<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());
   lp_rows_inverse_kernel<<<Y.m.n_phi / 2, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());
