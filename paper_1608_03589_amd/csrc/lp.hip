@@ -41,6 +41,7 @@
 // The transforms are Stockham FFTs in LDS with radix-16, 5, 4, 3 and 2
 // butterflies (Govindaraju et al. 2008), twiddles from float64 tables, every
 // phase reduced exactly as an integer before its sine and cosine.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -145,6 +146,9 @@ LpLayout lp_layout(int ny, int nx, int na, int nd) {
   Y.nd = nd;
   Y.m = lp_mesh(ny, nx, na, nd);
   Y.C = Y.m.n_phi <= kLpElems / 8 ? 8 : 4;
+  // at most L/2 bins a tile, so that the last tile holds bin L/2 alone
+  // (column 0), the bin packed into bin 0's imaginary part
+  Y.C = std::min(Y.C, Y.m.L / 2);
   Y.ntiles = (Y.m.L / 2 + 1 + Y.C - 1) / Y.C;
   if (!factor(Y.m.n_phi, Y.radix, &Y.nstages)) Y.nstages = -1;
   if (!factor(Y.m.L, Y.rradix, &Y.rstages)) Y.rstages = -1;
@@ -180,6 +184,11 @@ struct LpArgs {
   int nstages, rstages;
   int radix[kLpMaxStages];
   int rradix[kLpMaxStages];
+  // rfused: the rho transform's last radix-16 stage runs fused, first in the
+  // forward (with Step 1) and last in the inverse (with the stores of
+  // [B g]_L), and rrest lists the other stages; otherwise rrest = rradix.
+  int rfused, rrest_n;
+  int rrest[kLpMaxStages];
 };
 
 // ---------------------------------------------------------------------------
@@ -367,9 +376,10 @@ __device__ void stage(float2* x, int n, int C, int Ns, TW tw) {
   __syncthreads();
 }
 
+// Stages radix[0 .. nstages) after earlier ones whose radices multiply to Ns0.
 template <int SIGN, bool PAD, int NT, class TW>
-__device__ void fft(float2* x, int n, int C, const int* radix, int nstages, TW tw) {
-  int Ns = 1;
+__device__ void fft(float2* x, int n, int C, const int* radix, int nstages, TW tw, int Ns0 = 1) {
+  int Ns = Ns0;
   for (int s = 0; s < nstages; ++s) {
     const int R = radix[s];
     switch (R) {
@@ -507,37 +517,51 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_forward_kernel(LpArgs a, c
   const float* gb = g + (int64_t)kb * a.nd;
   SplitTwLoad stw;
   stw.fetch(a.twr, L);
-  // Batches of kLpRowBatch samples per thread: every node of the batch, then
-  // every sinogram sample, then the LDS stores (one wait per batch).
   const int nr = a.n_rho;
-  for (int i0 = 0; i0 < L; i0 += kLpRowBatch * kLpThreads) {
-    if (i0 >= nr) {   // the zero padding only
+  auto sample = [&](const LpNode& q, int i) {
+    const float va = pa ? lp_interp(ga, a.nd, q.ip, q.wp) : lp_interp(ga, a.nd, q.im, q.wm);
+    const float vb = pb ? lp_interp(gb, a.nd, q.ip, q.wp) : lp_interp(gb, a.nd, q.im, q.wm);
+    return i < nr ? make_float2(va, vb) : make_float2(0.0f, 0.0f);
+  };
+  if (a.rfused) {
+    // First stage radix 16 (Ns = 1, no twiddles) on Step 1's values in
+    // registers: butterfly j takes samples j + r L/16, of which r >= 8 lie
+    // in the zero padding (N_rho <= L/2).
+    const int m = L / 16, jb = threadIdx.x;
+    LpNode q[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) q[r] = a.nodes[min(jb + r * m, nr - 1)];
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = sample(q[r], jb + r * m);
+#pragma unroll
+    for (int r = 8; r < 16; ++r) v[r] = make_float2(0.0f, 0.0f);
+    if (jb < m) {
+      dft16<-1>(v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[lds_at(16 * jb + r)] = v[r];
+    }
+  } else {
+    // Batches of kLpRowBatch samples per thread: every node of the batch,
+    // then every sinogram sample, then the LDS stores (one wait per batch).
+    for (int i0 = 0; i0 < L; i0 += kLpRowBatch * kLpThreads) {
+      LpNode q[kLpRowBatch];
+#pragma unroll
+      for (int u = 0; u < kLpRowBatch; ++u)
+        q[u] = a.nodes[min(i0 + (int)threadIdx.x + u * kLpThreads, nr - 1)];
+      float2 v[kLpRowBatch];
+#pragma unroll
+      for (int u = 0; u < kLpRowBatch; ++u) v[u] = sample(q[u], i0 + (int)threadIdx.x + u * kLpThreads);
 #pragma unroll
       for (int u = 0; u < kLpRowBatch; ++u) {
         const int i = i0 + (int)threadIdx.x + u * kLpThreads;
-        if (i < L) x[lds_at(i)] = make_float2(0.0f, 0.0f);
+        if (i < L) x[lds_at(i)] = v[u];
       }
-      continue;
-    }
-    LpNode q[kLpRowBatch];
-#pragma unroll
-    for (int u = 0; u < kLpRowBatch; ++u)
-      q[u] = a.nodes[min(i0 + (int)threadIdx.x + u * kLpThreads, nr - 1)];
-    float va[kLpRowBatch], vb[kLpRowBatch];
-#pragma unroll
-    for (int u = 0; u < kLpRowBatch; ++u) {
-      va[u] = pa ? lp_interp(ga, a.nd, q[u].ip, q[u].wp) : lp_interp(ga, a.nd, q[u].im, q[u].wm);
-      vb[u] = pb ? lp_interp(gb, a.nd, q[u].ip, q[u].wp) : lp_interp(gb, a.nd, q[u].im, q[u].wm);
-    }
-#pragma unroll
-    for (int u = 0; u < kLpRowBatch; ++u) {
-      const int i = i0 + (int)threadIdx.x + u * kLpThreads;
-      if (i < L) x[lds_at(i)] = i < nr ? make_float2(va[u], vb[u]) : make_float2(0.0f, 0.0f);
     }
   }
   stw.put(L, twh, twl);
   __syncthreads();
-  fft<-1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, TwSplit{twh, twl});
+  fft<-1, true, kLpThreads>(x, L, 1, a.rrest, a.rrest_n, TwSplit{twh, twl}, a.rfused ? 16 : 1);
   const int C = a.C;
   for (int k = threadIdx.x; k < L / 2; k += kLpThreads) {
     const float2 z1 = x[lds_at(k)];
@@ -669,13 +693,40 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
   }
   stw.put(L, twh, twl);
   __syncthreads();
-  fft<+1, true, kLpThreads>(x, L, 1, a.rradix, a.rstages, TwSplit{twh, twl});
   float* ra = a.bl + (int64_t)j0 * a.n_rho;
   float* rb = ra + a.n_rho;
-  for (int i = threadIdx.x; i < a.n_rho; i += kLpThreads) {
-    const float2 v = x[lds_at(i)];
-    ra[i] = v.x;
-    rb[i] = v.y;
+  const TwSplit tw{twh, twl};
+  fft<+1, true, kLpThreads>(x, L, 1, a.rrest, a.rrest_n, tw);
+  if (a.rfused) {
+    // The last stage (radix 16, Ns = L/16) in registers: butterfly j reads
+    // and yields elements j + r L/16, stored straight to [B g]_L.
+    const int m = L / 16, jb = threadIdx.x;
+    if (jb < m) {
+      float2 v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = x[lds_at(jb + r * m)];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) {
+        float2 w = tw(r * jb);
+        w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+      dft16<+1>(v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = jb + r * m;
+        if (i < a.n_rho) {
+          ra[i] = v[r].x;
+          rb[i] = v[r].y;
+        }
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < a.n_rho; i += kLpThreads) {
+      const float2 v = x[lds_at(i)];
+      ra[i] = v.x;
+      rb[i] = v.y;
+    }
   }
 }
 
@@ -762,7 +813,15 @@ LpArgs lp_args(const LpLayout& Y, void* ws) {
   for (int i = 0; i < kLpMaxStages; ++i) {
     a.radix[i] = i < Y.nstages ? Y.radix[i] : 0;
     a.rradix[i] = i < Y.rstages ? Y.rradix[i] : 0;
+    a.rrest[i] = 0;
   }
+  int last16 = -1;
+  for (int i = 0; i < Y.rstages; ++i)
+    if (Y.rradix[i] == 16) last16 = i;
+  a.rfused = last16 >= 0 && Y.m.L / 16 <= kLpThreads;
+  a.rrest_n = 0;
+  for (int i = 0; i < Y.rstages; ++i)
+    if (!a.rfused || i != last16) a.rrest[a.rrest_n++] = Y.rradix[i];
   return a;
 }
 
@@ -836,8 +895,10 @@ int tvpd_lp_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
   // (the last tile holds bin L/2 alone, which rides with bin 0)
   if (Y.C == 8)
     lp_angle_conv_kernel<8><<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
-  else
+  else if (Y.C == 4)
     lp_angle_conv_kernel<4><<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
+  else
+    lp_angle_conv_kernel<2><<<Y.ntiles - 1, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());
   lp_rows_inverse_kernel<<<Y.m.n_phi / 2, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());

@@ -50,7 +50,8 @@ def run(H, W, na, nd, s):
     (33, 21, 45, 40),        # odd sides (a pixel at the origin), corners beyond the disc
     (128, 128, 400, 185),    # 800 rays
     (200, 120, 75, 300),     # 150 rays (2 3 5^2), rho transform of 2048
-    (6, 6, 1, 8),            # two rays, the smallest transforms
+    (6, 6, 1, 8),            # two rays, rho transform of 16 (one fused radix-16 stage)
+    (4, 4, 2, 4),            # rho transform of 8: no radix-16 stage to fuse
 ])
 def test_logpolar_matches_the_oracle(H, W, na, nd):
     print(f"case: logpolar {H}x{W} angles {na} bins {nd}", flush=True)
