@@ -361,11 +361,13 @@ __device__ void stage(float2* x, int n, int C, int Ns, TW tw) {
     if (b < nb) {
       const int j = b / C, c = b - j * C;
       const int k = j % Ns;
+      if (Ns > 1) {   // the first stage's twiddles are all 1
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        float2 w = tw(r * k * stride);
-        if (SIGN > 0) w.y = -w.y;
-        v[u][r] = cmul(v[u][r], w);
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw(r * k * stride);
+          if (SIGN > 0) w.y = -w.y;
+          v[u][r] = cmul(v[u][r], w);
+        }
       }
       dft<R, SIGN>(v[u]);
       const int d = (j - k) * R + k;
