@@ -181,6 +181,7 @@ struct LpArgs {
   int ny, nx, na, nd;
   int n_rho, n_phi, L, C, ntiles;
   double R, rho_first, drho, dphi;
+  double lnR, inv_drho, inv_dphi;   // ln R, 1 / drho, 1 / dphi
   int nstages, rstages;
   int radix[kLpMaxStages];
   int rradix[kLpMaxStages];
@@ -732,25 +733,26 @@ __global__ __launch_bounds__(kLpThreads) void lp_rows_inverse_kernel(LpArgs a) {
   }
 }
 
-// Step 4 for one pixel per thread.  A workspace not planned for this
-// geometry gives NaN everywhere.
+// Step 4 for one pixel per thread (grid: column blocks by rows).  A
+// workspace not planned for this geometry gives NaN everywhere.
 __global__ __launch_bounds__(kMaxBlock) void lp_cartesian_kernel(LpArgs a, float* img) {
-  const int64_t p = blockIdx.x * (int64_t)kMaxBlock + threadIdx.x;
-  if (p >= (int64_t)a.ny * a.nx) return;
+  const int col = blockIdx.x * kMaxBlock + threadIdx.x, row = blockIdx.y;
+  if (col >= a.nx) return;
+  const int64_t p = (int64_t)row * a.nx + col;
   const LpHdr* h = a.hdr;
   if (h->magic != kLpMagic || h->ny != a.ny || h->nx != a.nx || h->na != a.na ||
       h->nd != a.nd) {
     img[p] = __builtin_nanf("");
     return;
   }
-  const int row = (int)(p / a.nx), col = (int)(p - (int64_t)row * a.nx);
   const double x = col + 0.5 - 0.5 * a.nx, y = row + 0.5 - 0.5 * a.ny;
-  const double r = sqrt(x * x + y * y);
-  double u = (log(r / a.R) - a.rho_first) / a.drho;   // -inf at the origin
+  // ln(r / R) as ln(r^2) / 2 - ln R, and multiplications by 1/drho and
+  // 1/dphi: no float64 square root or division per pixel
+  double u = (0.5 * log(x * x + y * y) - a.lnR - a.rho_first) * a.inv_drho;   // -inf at the origin
   u = fmin(fmax(u, 0.0), (double)(a.n_rho - 1));
   double th = atan2(y, x);
   if (th < 0.0) th += 2.0 * M_PI;
-  const double v = th / a.dphi;
+  const double v = th * a.inv_dphi;
   int i0 = (int)floor(u);
   if (i0 > a.n_rho - 2) i0 = a.n_rho - 2;
   const float wu = (float)(u - i0);
@@ -810,6 +812,9 @@ LpArgs lp_args(const LpLayout& Y, void* ws) {
   a.rho_first = Y.m.rho0 + Y.m.drho;
   a.drho = Y.m.drho;
   a.dphi = Y.m.dphi;
+  a.lnR = std::log(Y.m.R);
+  a.inv_drho = 1.0 / Y.m.drho;
+  a.inv_dphi = 1.0 / Y.m.dphi;
   a.nstages = Y.nstages;
   a.rstages = Y.rstages;
   for (int i = 0; i < kLpMaxStages; ++i) {
@@ -904,9 +909,8 @@ int tvpd_lp_backproject(const tvpd_tomo_geom* geom, const float* g, float* img,
   LP_TRY(launched());
   lp_rows_inverse_kernel<<<Y.m.n_phi / 2, kLpThreads, 0, s>>>(a);
   LP_TRY(launched());
-  const int64_t npx = (int64_t)Y.ny * Y.nx;
-  lp_cartesian_kernel<<<(unsigned)((npx + kMaxBlock - 1) / kMaxBlock), kMaxBlock, 0, s>>>(a,
-                                                                                       img);
+  lp_cartesian_kernel<<<dim3((unsigned)((Y.nx + kMaxBlock - 1) / kMaxBlock), (unsigned)Y.ny),
+                        kMaxBlock, 0, s>>>(a, img);
   LP_TRY(launched());
   if (lp_out &&
       hipMemcpyAsync(lp_out, a.bl, 4 * (size_t)Y.m.n_phi * Y.m.n_rho, hipMemcpyDeviceToDevice,
