@@ -32,6 +32,9 @@
 namespace tvpd {
 
 constexpr int kBstMaxLen = 4096;   // LDS FFT length limit
+// phases reduced in 32-bit integers: two products of a signed frequency
+// index (at most kBstMaxLen / 2) and a side (at most kTomoMaxSide)
+static_assert(2LL * (kBstMaxLen / 2) * kTomoMaxSide < (1LL << 31), "bst phase range");
 // LDS index of element i of a transform: one spare slot per 16 elements, so
 // that the strided writes of the Stockham stages spread over the banks.
 constexpr int kBstLds = kBstMaxLen + kBstMaxLen / 16;
@@ -263,9 +266,9 @@ __global__ __launch_bounds__(kMaxBlock) void bst_spectra_kernel(const float* g, 
   for (int m = threadIdx.x; m < M; m += blockDim.x) {
     const int ms = m < M / 2 ? m : m - M;          // signed frequency index
     // t_0 = (1 - nd) / 2: phase -2 pi ms t_0 / M = pi ms (nd - 1) / M,
-    // reduced modulo 2M exactly
-    int64_t ph = ((int64_t)ms * (nd - 1)) % (2 * (int64_t)M);
-    if (ph < 0) ph += 2 * (int64_t)M;
+    // reduced modulo 2M exactly (a mask: 2M is a power of two, and
+    // |ms (nd - 1)| <= 2048 x 32767 fits in 32 bits)
+    const int ph = (ms * (nd - 1)) & (2 * M - 1);
     float sn, cs;
     sincospif((float)ph * (1.0f / (float)M), &sn, &cs);   // (exact: M a power of two)
     const int am = ms < 0 ? -ms : ms;
@@ -315,9 +318,10 @@ __device__ float2 cartesian_value(const float2* spec, int na, int M, int Q, int 
   };
   const float2 r0 = radial(k0, nu), r1 = radial(k1, nu1);
   const float2 val = make_float2(r0.x + wa * (r1.x - r0.x), r0.y + wa * (r1.y - r0.y));
-  // pixel centres at n + (1 - n_side)/2: phase 2 pi (ps (1 - nx) + qs (1 - ny)) / (2Q)
-  int64_t ph = ((int64_t)ps * (1 - nx) + (int64_t)qs * (1 - ny)) % (2 * (int64_t)Q);
-  if (ph < 0) ph += 2 * (int64_t)Q;
+  // pixel centres at n + (1 - n_side)/2: phase 2 pi (ps (1 - nx) + qs (1 - ny)) / (2Q),
+  // reduced modulo 2Q exactly (a mask: 2Q is a power of two, and the sum is
+  // at most 2 x 2048 x 32767 in magnitude, within 32 bits)
+  const int ph = (ps * (1 - nx) + qs * (1 - ny)) & (2 * Q - 1);
   float sn, cs;
   sincospif((float)ph * inv_q, &sn, &cs);
   return cmul(val, make_float2(cs, sn));
