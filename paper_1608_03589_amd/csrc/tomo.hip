@@ -532,11 +532,15 @@ __global__ __launch_bounds__(kMaxBlock) void tomo_fbp_taps_kernel(float* hs, int
   const int lane = threadIdx.x & (kWave - 1);
   const int n = blockIdx.x * (kMaxBlock / kWave) + wave_in_block();
   if (n >= nd) return;                       // whole waves
+  // L is a power of two: 1/L and 2/L are exact, m n mod L is a mask
+  // (m n < L nd / 2 <= 2^30, L < 4 nd)
+  static_assert(2LL * kTomoMaxSide * kTomoMaxSide <= (1LL << 31), "fbp taps phase range");
+  const double inv_l = 1.0 / (double)L, two_inv_l = 2.0 / (double)L;
   double acc = 0.0;
   for (int m = 1 + lane; m < L / 2; m += kWave) {
-    const double nu = (double)m / (double)L;
-    const int mn = (int)(((int64_t)m * n) % L);
-    acc += 2.0 * (nu / (1.0 + lam * nu)) * cospi(2.0 * (double)mn / (double)L);
+    const double nu = (double)m * inv_l;
+    const int mn = (m * n) & (L - 1);
+    acc += 2.0 * (nu / (1.0 + lam * nu)) * cospi((double)mn * two_inv_l);
   }
   acc = dev::wave_sum(acc);
   if (lane == 0) {
