@@ -418,6 +418,57 @@ __global__ void bst_extract_kernel(const float2* B, float* img, int Q, int ny, i
     if (st_ != TVPD_OK) return st_;     \
   } while (0)
 
+// Regularised FBP filtering through the FFT (Section 6: the filter
+// |sigma| / (1 + lam |sigma|) of the regularised FBP): rays 2k and 2k + 1 as
+// the real and imaginary parts of one sequence, zero padded to L >= 2 nd (so
+// that the circular convolution is the linear one over the nd outputs),
+// transformed, multiplied by H_m = |nu_m| / (1 + lam |nu_m|) with nu_m the
+// signed frequency m/L (real and even, so the two rays stay apart),
+// transformed back; the outputs are scaled by scale / L.
+__global__ __launch_bounds__(kMaxBlock) void fbp_fft_filter_kernel(const float* g, float* q,
+                                                                   const float2* tw, int na,
+                                                                   int nd, int L, float lam,
+                                                                   float scale) {
+  __shared__ float2 x[kBstLds];
+  const int ka = 2 * blockIdx.x, kb = ka + 1;
+  const bool hb = kb < na;
+  const float* ga = g + (int64_t)ka * nd;
+  const float* gb = g + (int64_t)(hb ? kb : ka) * nd;
+  constexpr int kPer = kBstMaxLen / kMaxBlock;
+  float va[kPer], vb[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kMaxBlock;
+    va[u] = i < nd ? ga[i] : 0.0f;
+    vb[u] = (hb && i < nd) ? gb[i] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = threadIdx.x + u * kMaxBlock;
+    if (i < L) x[lds_at(i)] = make_float2(va[u], vb[u]);
+  }
+  __syncthreads();
+  fft_lds<-1>(x, L, tw, L);
+  const float inv_l = 1.0f / (float)L;          // exact: L is a power of two
+  for (int m = threadIdx.x; m < L; m += blockDim.x) {
+    const int am = m <= L / 2 ? m : L - m;      // |signed index|; m = L/2 gives 1/2
+    const float nu = (float)am * inv_l;
+    const float h = nu / fmaf(lam, nu, 1.0f);
+    const float2 v = x[lds_at(m)];
+    x[lds_at(m)] = make_float2(v.x * h, v.y * h);
+  }
+  __syncthreads();
+  fft_lds<+1>(x, L, tw, L);
+  const float sc = scale * inv_l;
+  float* qa = q + (int64_t)ka * nd;
+  float* qb = q + (int64_t)kb * nd;
+  for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+    const float2 v = x[lds_at(i)];
+    qa[i] = v.x * sc;
+    if (hb) qb[i] = v.y * sc;
+  }
+}
+
 int launched() { return hipGetLastError() == hipSuccess ? TVPD_OK : TVPD_ERR_HIP; }
 
 bool geom_ok(const tvpd_tomo_geom* g) {
@@ -488,6 +539,19 @@ int run_bst(const tvpd_tomo_geom* geom, const float* g, float* img, float lam, v
 }
 
 }  // namespace
+
+static_assert(kFbpFftMaxLen <= kBstMaxLen, "FBP FFT length");
+
+int launch_fbp_fft_filter(const float* g, float* q, float2* tw, int na, int nd, float lam,
+                          float scale, hipStream_t s) {
+  const int L = tomo_fbp_length(nd);
+  if (L > kFbpFftMaxLen) return TVPD_ERR_UNSUPPORTED;
+  bst_twiddle_kernel<<<(L + 255) / 256, 256, 0, s>>>(tw, L);
+  if (int rc = launched()) return rc;
+  fbp_fft_filter_kernel<<<(na + 1) / 2, kMaxBlock, 0, s>>>(g, q, tw, na, nd, L, lam, scale);
+  return launched();
+}
+
 }  // namespace tvpd
 
 using namespace tvpd;

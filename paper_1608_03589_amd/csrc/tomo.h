@@ -162,6 +162,12 @@ int launch_tomo_backproject(const BpArgs& a, int mode, const int32_t* kptr,
 // Regularised FBP: taps hs[0, nd) of the filter |nu| / (1 + lam |nu|), and
 // q = scale * (hs * g) row by row.
 int launch_tomo_fbp_taps(float* hs, int nd, float lam, hipStream_t s);
+// Regularised FBP filtering through the FFT (LDS transforms of the BST) for
+// padded lengths tomo_fbp_length(nd) <= kFbpFftMaxLen: tw receives the
+// length-L twiddle table (8 L bytes), q the filtered sinogram times scale.
+constexpr int kFbpFftMaxLen = 4096;
+int launch_fbp_fft_filter(const float* g, float* q, float2* tw, int na, int nd, float lam,
+                          float scale, hipStream_t s);
 int launch_tomo_fbp_filter(const float* g, float* q, const float* hs, int na, int nd,
                            float scale, hipStream_t s);
 int launch_tomo_fill(float* p, int64_t n, float v, hipStream_t s);

@@ -1,5 +1,6 @@
 // C ABI of the tomographic data term: argument checks, workspace layout and
 // the host side of the iteration (see include/tvpd.h for the semantics).
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <mutex>
@@ -27,7 +28,9 @@ TomoLayout tomo_layout(int ny, int nx, int na, int nd) {
   L.off_trig = kHeaderBytes;
   L.off_part = (size_t)round_up((int64_t)L.off_trig + 16 * (int64_t)na, (int64_t)kAlign);
   L.off_fbp = (size_t)round_up((int64_t)L.off_part + 16 * L.max_partials, (int64_t)kAlign);
-  L.off_planes = (size_t)round_up((int64_t)L.off_fbp + 4 * (int64_t)nd, (int64_t)kAlign);
+  // FBP filter region: the taps (4 nd bytes) or the FFT twiddles (8 L bytes)
+  const int64_t fbp_bytes = std::max<int64_t>(4 * (int64_t)nd, 8 * (int64_t)tomo_fbp_length(nd));
+  L.off_planes = (size_t)round_up((int64_t)L.off_fbp + fbp_bytes, (int64_t)kAlign);
   L.bytes = L.off_planes +
             sizeof(float) * (size_t)(kTNumImg * L.img + kTNumSino * L.sino + L.fb + L.fbt);
   return L;
@@ -167,6 +170,7 @@ constexpr size_t kNoAllocTapOff = 65536 * 16;
 constexpr size_t kNoAllocSinoOff = kNoAllocTapOff + 4 * size_t(kTomoMaxSide);
 constexpr size_t kNoAllocSinoFloats = (kNoAllocBytes - kNoAllocSinoOff) / 4;
 static_assert(16 * size_t(kTomoMaxAngles) <= kNoAllocTapOff, "angle table");
+static_assert(8 * size_t(kFbpFftMaxLen) <= 4 * size_t(kTomoMaxSide), "FBP twiddles");
 static_assert(kNoAllocSinoOff % 256 == 0, "sinogram alignment");
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
@@ -191,6 +195,20 @@ int scratch_address(void** out) {
   }
   *out = g_scratch_ptr[dev];
   return TVPD_OK;
+}
+
+// The regularised FBP's filtering into P.sino[kTS], with the factor dtheta
+// of the backprojection: through the FFT for padded lengths up to
+// kFbpFftMaxLen (P.fbp holds the twiddles), else a direct convolution with
+// float64 taps (P.fbp holds the taps).
+int fbp_filter(const TomoLayout& L, const float* g, const TomoPtrs& P, float lam,
+               hipStream_t s) {
+  const float dtheta = (float)(M_PI / (double)L.na);
+  if (tomo_fbp_length(L.nd) <= kFbpFftMaxLen)
+    return launch_fbp_fft_filter(g, P.sino[kTS], reinterpret_cast<float2*>(P.fbp), L.na, L.nd,
+                                 lam, dtheta, s);
+  TOMO_TRY(launch_tomo_fbp_taps(P.fbp, L.nd, lam, s));
+  return launch_tomo_fbp_filter(g, P.sino[kTS], P.fbp, L.na, L.nd, dtheta, s);
 }
 
 }  // namespace
@@ -390,10 +408,7 @@ int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out
   const TomoPtrs P = tomo_ptrs(L, ws);
   hipStream_t s = static_cast<hipStream_t>(stream);
   TOMO_TRY(launch_tomo_trig(P.trig, L.na, s));
-  TOMO_TRY(launch_tomo_fbp_taps(P.fbp, L.nd, lam, s));
-  // the factor dtheta of the backprojection goes with the filter
-  TOMO_TRY(launch_tomo_fbp_filter(g, P.sino[kTS], P.fbp, L.na, L.nd,
-                                  (float)(M_PI / (double)L.na), s));
+  TOMO_TRY(fbp_filter(L, g, P, lam, s));
   return backward(L, P, P.sino[kTS], f_out, s);
 }
 
@@ -415,9 +430,7 @@ int tvpd_fbp_noalloc(const tvpd_tomo_geom* geom, const float* g, float lam,
   // every scratch word the kernels read is written first in this call: no
   // clearing is needed
   TOMO_TRY(launch_tomo_trig(P.trig, L.na, s));
-  TOMO_TRY(launch_tomo_fbp_taps(P.fbp, L.nd, lam, s));
-  TOMO_TRY(launch_tomo_fbp_filter(g, P.sino[kTS], P.fbp, L.na, L.nd,
-                                  (float)(M_PI / (double)L.na), s));
+  TOMO_TRY(fbp_filter(L, g, P, lam, s));
   return backward(L, P, P.sino[kTS], f_out, s);
 }
 

@@ -240,8 +240,9 @@ def test_first_iteration_at_full_size():
 
 @pytest.mark.parametrize("H,W,na,nd,lam", [
     (64, 64, 48, 92, 0.0), (64, 64, 48, 92, 4.0), (37, 53, 30, 70, 1.5),
-    (40, 40, 12, 2500, 0.0),     # two output tiles, three input chunks
-    (1, 1, 3, 1, 0.0)])
+    (40, 40, 12, 2500, 0.0),     # padded length 8192: direct convolution with taps
+    (33, 21, 45, 40, 1e30),      # FFT filtering, the filter ~1/lam beyond frequency 0
+    (1, 1, 3, 1, 0.0)])          # padded length 2, an odd number of rays
 def test_fbp_matches_the_oracle(H, W, na, nd, lam):
     print(f"case: fbp {H}x{W} angles {na} bins {nd} lam {lam}", flush=True)
     rng = np.random.default_rng(H + nd)
