@@ -478,17 +478,19 @@ int tvpd_tomo_opnorm(const tvpd_tomo_geom* geom, int32_t iters, void* ws,
  * the standard inversion formula), as a linear convolution over the
  * detector: the circular convolution on the zero-padded grid of length L,
  * the smallest power of two >= 2 n_det.  g: device [n_angles][n_det];
- * f_out: device [ny][nx].  The response's taps are formed on the device in
- * O(L n_det) work per call; the filtering costs n_det^2 per projection.
- * Uses the workspace's scratch sinogram only. */
+ * f_out: device [ny][nx].  For L <= 4096 the filtering runs through FFTs of
+ * length L (two projections per transform, O(L log L) each); beyond, as a
+ * direct convolution with taps formed on the device in O(L n_det) work
+ * (n_det^2 per projection).  Uses the workspace's scratch sinogram and its
+ * filter region only. */
 int tvpd_fbp(const tvpd_tomo_geom* geom, const float* g, float lam, float* f_out,
              void* ws, size_t ws_bytes, void* stream);
 
 /* tvpd_fbp without a workspace, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same result as tvpd_fbp, bit for bit (the same
- * kernels); g and f_out as there.  The angle table, the filter taps and the
- * filtered sinogram live in a static device array of 32 MiB that the library
+ * kernels); g and f_out as there.  The angle table, the filter's twiddles or
+ * taps and the filtered sinogram live in a static device array of 32 MiB that the library
  * holds on each device it runs on until the process ends; the call allocates
  * nothing.  Limit: n_angles * n_det <= 8093696 (TVPD_ERR_SCRATCH beyond), the
  * other limits as for tvpd_fbp.  Every call on one device shares that array:
